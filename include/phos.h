@@ -1,0 +1,306 @@
+/*
+ * phos.h — C ABI of the MI355X (gfx950) hot path of concurrent GPU
+ * checkpoint/restore with validated speculation (PhoenixOS, arXiv 2405.12079).
+ *
+ * Paper map:
+ *   Section 4.1  speculation from launch arguments, runtime validation
+ *                -> phos_spec_register, phos_validate, phos_validate_batch
+ *   Section 4.2  soft copy-on-write            -> phos_ckpt_begin / _cow / _end
+ *   Section 4.3  soft recopy (dirty tracking)   -> PHOS_V_TRACK, phos_ckpt_recopy
+ *   Section 5    chunked device-to-host drain   -> phos_ckpt_end (host_image)
+ *   Section 6    concurrent on-demand restore   -> phos_restore_begin / _on_demand / _end
+ *   (no paper analog) batched persistent copy and a serving loop
+ *                -> phos_batch_*, phos_copy_plain, phos_serve_run
+ *
+ * Conventions.  Every call returns a phos_status; nothing throws across the
+ * ABI; on failure phos_last_error() holds a thread-local message.  "Device
+ * memory" means memory the GPU can dereference (hipMalloc'd, or pinned host
+ * memory from hipHostMalloc).  Calls that take a stream are asynchronous on
+ * it unless stated; their outputs are valid after that stream synchronizes.
+ * A context and its handles are single-threaded: calls on one context must
+ * come from one host thread at a time.
+ *
+ * Addresses.  The application's device memory is one pool [pool_base,
+ * pool_base + pool_bytes), split into pages of page_bytes (a power of two,
+ * 4 KiB .. 2 MiB); pool_base is page aligned.  Buffers are page-aligned,
+ * whole pages, non-overlapping and inside the pool, so every pool page
+ * belongs to at most one buffer.  The checkpoint image holds every buffer's
+ * bytes back to back in ascending base order (gaps excluded).
+ *
+ * Access records.  A kernel's access stream is an array of uint64_t records:
+ * bits 3..63 are the byte address (8-aligned), bit 0 is 1 for a write; bits
+ * 1..2 are ignored.  A record covers [a, a + 8).
+ */
+#ifndef PHOS_H
+#define PHOS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PHOS_OK = 0,
+  PHOS_E_INVAL = 1,    /* bad argument: null pointer, misaligned or overlapping buffers, ... */
+  PHOS_E_NOMEM = 2,    /* device or pinned host allocation failed                          */
+  PHOS_E_HIP = 3,      /* a HIP runtime call failed; phos_last_error() names it            */
+  PHOS_E_STATE = 4,    /* call out of protocol order (e.g. cow before begin)               */
+  PHOS_E_OVERFLOW = 5, /* more results than the caller's capacity (true count returned)    */
+  PHOS_E_MISSPEC = 6,  /* the protocol invariant cannot be kept: fall back to stop-the-world */
+  PHOS_E_TIMEOUT = 7   /* a bounded device-side wait expired (results are not valid)        */
+} phos_status;
+
+enum { PHOS_R = 1u, PHOS_W = 2u }; /* interval / access mode bits */
+
+/* Launch-argument kinds (Section 4.1: API classes and signature filtering). */
+enum {
+  PHOS_ARG_SCALAR = 0,    /* not a pointer: names nothing                                 */
+  PHOS_ARG_PTR_CONST = 1, /* const pointer: names the containing buffer for reading (R)   */
+  PHOS_ARG_PTR_MUT = 2,   /* mutable pointer: names the containing buffer, R|W            */
+  PHOS_ARG_STRUCT = 3,    /* opaque struct of `bytes` bytes at host_struct: every 8-byte
+                             chunk is treated as a mutable pointer                       */
+  PHOS_ARG_RANGE = 4      /* API with a specified range: [value, value + bytes), mode bits */
+};
+
+/* Validation flags. */
+enum {
+  PHOS_V_READS = 1u,  /* report reads outside the read set                            */
+  PHOS_V_WRITES = 2u, /* report writes outside the write set                          */
+  PHOS_V_TRACK = 4u   /* set the context's dirty bitmap for validated writes and its
+                         victim bitmap for failing writes inside a buffer (Section 4.3) */
+};
+
+enum { PHOS_COW = 1, PHOS_RECOPY = 2 }; /* checkpoint protocols */
+
+/* Checkpoint / restore flags. */
+enum {
+  PHOS_CKPT_DEFER_BACKGROUND = 1u, /* start the background copy only at phos_ckpt_end
+                                      (deterministic copy sets, for testing)            */
+  PHOS_RST_DEFER_BACKGROUND = 1u,  /* start the background restore only at phos_restore_end */
+  PHOS_RST_PREFETCH_SPEC = 2u      /* also bring in every page of the launch's speculated
+                                      buffers, not only the pages its records touch     */
+};
+
+typedef struct phos_ctx phos_ctx;
+typedef struct phos_ckpt phos_ckpt;
+typedef struct phos_rst phos_rst;
+typedef struct phos_batch phos_batch;
+typedef uint32_t phos_spec; /* handle of a registered interval set */
+
+typedef struct { uint64_t base, bytes; } phos_buffer;
+typedef struct {
+  uint32_t kind, mode;     /* PHOS_ARG_*; mode bits for PHOS_ARG_RANGE                */
+  uint64_t value, bytes;   /* argument value; RANGE/STRUCT byte count                */
+  const void *host_struct; /* PHOS_ARG_STRUCT: host copy of the struct's bytes       */
+} phos_arg;
+typedef struct { uint64_t lo, hi; uint32_t mode, _pad; } phos_interval; /* [lo, hi) */
+
+/* One violation (32 bytes).  reason 1: the address is in no speculated
+ * interval; reason 2: it is inside one but that interval lacks the mode.
+ * victim: index of the buffer containing addr, or -1. */
+typedef struct {
+  uint64_t index, addr;
+  uint32_t launch_id;
+  uint8_t is_write, reason;
+  uint16_t _p;
+  int32_t victim;
+  uint32_t _q;
+} phos_violation;
+
+typedef struct {
+  uint64_t bg_pages;     /* pages copied by the background copy                */
+  uint64_t cow_pages;    /* pages copied before a launch (copy-on-write)       */
+  uint64_t recopy_pages; /* pages recopied after the re-quiesce                */
+  uint64_t image_bytes;  /* bytes of the image                                 */
+} phos_ckpt_stats;
+
+typedef struct {
+  uint64_t bg_pages;     /* pages brought in by the background restore */
+  uint64_t demand_pages; /* pages brought in before a launch           */
+} phos_rst_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context for the pool [pool_base, pool_base + pool_bytes) on HIP
+ * device `device`.  pool_base must be page aligned; pool_bytes a multiple of
+ * page_bytes; page_bytes a power of two in [4 KiB, 2 MiB].  The caller owns
+ * the pool memory.  E_INVAL on bad sizes, E_NOMEM / E_HIP on allocation. */
+phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes, uint32_t page_bytes,
+                        phos_ctx **out);
+/* Synchronizes the device, frees everything the context owns. */
+phos_status phos_destroy(phos_ctx *ctx);
+
+/* Section 4.1: the process's allocation table, as intercepted allocations.
+ * bufs: host array of n buffers, ascending base, page aligned, whole pages,
+ * non-overlapping, inside the pool (E_INVAL otherwise).  Replaces the table;
+ * synchronous; E_STATE while a checkpoint or restore is open. */
+phos_status phos_buffers_register(phos_ctx *ctx, const phos_buffer *bufs, uint32_t n);
+
+/* Bytes of the checkpoint image (sum of buffer sizes). */
+phos_status phos_image_bytes(phos_ctx *ctx, uint64_t *bytes);
+
+/* ------------------------------------------------------------- speculation */
+
+/* Section 4.1 (argument-based speculation with signature filtering, API
+ * specified ranges) and Section 6 (const pointers as the read set): turn one
+ * launch's arguments into a sorted interval set and keep it under a handle.
+ * A pointer names the buffer b with base_b <= value < base_b + bytes_b, whole;
+ * pointers naming no buffer and scalars are dropped; identical intervals are
+ * merged by OR-ing modes.  At most 64 intervals (E_INVAL beyond); RANGE with
+ * no mode bits or a wrapping range is E_INVAL.  Host-only, synchronous. */
+phos_status phos_spec_register(phos_ctx *ctx, uint32_t launch_id, const phos_arg *args,
+                               uint32_t nargs, phos_spec *out);
+/* Copy a registered interval set to host memory: *n = count, at most cap written. */
+phos_status phos_spec_intervals(phos_ctx *ctx, phos_spec spec, phos_interval *out, uint32_t cap,
+                                uint32_t *n);
+phos_status phos_spec_release(phos_ctx *ctx, phos_spec spec);
+
+/* -------------------------------------------------------------- validation */
+
+/* Section 4.1 runtime validation of one launch's access stream.  Each record
+ * whose access [a, a+8) is not inside a speculated interval holding the mode
+ * it needs is a violation (reads checked iff PHOS_V_READS, writes iff
+ * PHOS_V_WRITES).  Violations are written to `out` (device memory, cap
+ * entries) in ascending record index, and the count to *n_violations (device
+ * memory, one uint64_t).  With PHOS_V_TRACK the dirty / victim bitmaps are
+ * updated.  d_records: device memory, 8-byte aligned (16-byte alignment is
+ * faster).  Asynchronous on `stream`; if *n_violations > cap the contents of
+ * out are unspecified.  Validation calls on one context are serialized by
+ * the library. */
+phos_status phos_validate(phos_ctx *ctx, phos_spec spec, const uint64_t *d_records, uint64_t n,
+                          uint32_t flags, phos_violation *out, uint64_t cap,
+                          uint64_t *n_violations, hipStream_t stream);
+
+/* Many launches in one pass: launch i uses specs[i], records d_records[i]
+ * (n[i] of them); host arrays of nlaunch entries.  Output ordered by
+ * (position i in the call, record index). */
+phos_status phos_validate_batch(phos_ctx *ctx, const phos_spec *specs,
+                                const uint64_t *const *d_records, const uint64_t *n,
+                                uint32_t nlaunch, uint32_t flags, phos_violation *out,
+                                uint64_t cap, uint64_t *n_violations, hipStream_t stream);
+
+/* Clear the dirty and victim bitmaps (asynchronous on stream). */
+phos_status phos_track_reset(phos_ctx *ctx, hipStream_t stream);
+/* Synchronous copy of a bitmap to host: which 0 = dirty, 1 = victim.  Bit p%32
+ * of word p/32 is pool page p; nwords >= ceil(pool pages / 32). */
+phos_status phos_track_read(phos_ctx *ctx, uint32_t which, uint32_t *host_words, uint64_t nwords);
+
+/* ------------------------------------------------------------- checkpoint */
+
+/* Section 4.2 / 4.3: open a concurrent checkpoint.  The caller has quiesced
+ * the application (its streams are idle).  image: device memory of
+ * phos_image_bytes() bytes that receives the image (pinned host memory means
+ * copying straight to the host).  host_image: optional pinned host memory
+ * filled from image by phos_ckpt_end (NULL: none).  The background copy of
+ * every page starts on copy_stream unless PHOS_CKPT_DEFER_BACKGROUND.
+ * Opening resets the dirty / victim bitmaps when no other checkpoint is
+ * open.  At most one checkpoint per protocol may be open (E_STATE). */
+phos_status phos_ckpt_begin(phos_ctx *ctx, uint32_t protocol, uint32_t flags, void *image,
+                            void *host_image, hipStream_t copy_stream, phos_ckpt **out);
+
+/* Section 4.2: before the launch described by `spec` runs on app_stream,
+ * copy every page it may write that the checkpoint has not copied yet: the
+ * pages of its write intervals and the victim pages marked by validation.
+ * A page already being copied is waited for.  Asynchronous on app_stream;
+ * the launch must be enqueued after this call.  PROTOCOL COW only. */
+phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream);
+
+/* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every
+ * dirty or victim page into the image after the background copy; app_stream
+ * then waits for the recopy.  PROTOCOL RECOPY only. */
+phos_status phos_ckpt_recopy(phos_ckpt *ck, hipStream_t app_stream);
+
+/* Finish: wait for every copy (and app_stream), drain image to host_image if
+ * given, free the handle.  E_TIMEOUT if a device wait expired. */
+phos_status phos_ckpt_end(phos_ckpt *ck, hipStream_t app_stream, phos_ckpt_stats *stats);
+
+/* Synchronous: copied-page bitmap of an open checkpoint (bit p = pool page p). */
+phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nwords);
+
+/* ----------------------------------------------------------------- restore */
+
+/* Section 6: open a concurrent restore from `image` (device or pinned host
+ * memory, phos_image_bytes() bytes, layout as written by a checkpoint).  The
+ * background copy of every page into the pool starts on copy_stream unless
+ * PHOS_RST_DEFER_BACKGROUND.  One restore per context at a time. */
+phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
+                               hipStream_t copy_stream, phos_rst **out);
+
+/* Section 6: before a launch runs on app_stream, bring in every page inside a
+ * buffer that its records touch (and, with PHOS_RST_PREFETCH_SPEC, every page
+ * of its speculated intervals) that is not present yet.  d_faulted: optional
+ * device uint64_t, incremented by the number of pages this call copied. */
+phos_status phos_restore_on_demand(phos_rst *rs, phos_spec spec, const uint64_t *d_records,
+                                   uint64_t n, hipStream_t app_stream, uint64_t *d_faulted);
+
+/* Synchronous: present-page bitmap (bit p = pool page p). */
+phos_status phos_restore_present(phos_rst *rs, uint32_t *host_words, uint64_t nwords);
+
+/* Wait for the background restore and app_stream; free the handle. */
+phos_status phos_restore_end(phos_rst *rs, hipStream_t app_stream, phos_rst_stats *stats);
+
+/* ----------------------------------------------------- batched copy / serving */
+
+/* One copy segment of a request: bytes from src to dst (device memory;
+ * addresses and size multiples of 16), belonging to request req. */
+typedef struct { uint64_t src, dst, bytes; uint32_t req, _p; } phos_copy_seg;
+
+typedef struct {
+  uint64_t chunk_bytes; /* work unit claimed by one workgroup (64 KiB .. 4 MiB) */
+  uint32_t wg_per_cu;   /* resident workgroups per compute unit (1 .. 16)       */
+  uint32_t threads;     /* threads per workgroup: 256, 512 or 1024             */
+} phos_batch_cfg;
+
+typedef struct phos_seglist phos_seglist;
+
+/* A batched copier (no paper analog; the paper copies buffer by buffer in
+ * 4 MB chunks, Section 5): a device-resident work queue of up to max_segs
+ * segments of up to max_reqs requests, and one HIP graph holding a reset
+ * kernel and a persistent copy kernel whose workgroups claim chunk_bytes
+ * pieces of the concatenated segment stream until it is drained.  The graph
+ * is captured once and replayed for every batch.  cfg NULL: defaults. */
+phos_status phos_batch_create(int device, uint64_t max_segs, uint32_t max_reqs,
+                              const phos_batch_cfg *cfg, phos_batch **out);
+phos_status phos_batch_destroy(phos_batch *b);
+/* Load segments (host array, nseg <= max_segs, req < max_reqs) into the
+ * device queue, asynchronously on stream through pinned staging.  E_INVAL
+ * on misaligned segments. */
+phos_status phos_batch_load(phos_batch *b, const phos_copy_seg *segs, uint64_t nseg,
+                            hipStream_t stream);
+/* Replay the graph on stream: one persistent launch copies every loaded
+ * segment; per-request copied bytes are reset, then accumulate in the device
+ * array of phos_batch_done_bytes (max_reqs entries). */
+phos_status phos_batch_run(phos_batch *b, hipStream_t stream);
+/* phos_batch_load followed by phos_batch_run. */
+phos_status phos_batch_copy(phos_batch *b, const phos_copy_seg *segs, uint64_t nseg,
+                            hipStream_t stream);
+phos_status phos_batch_done_bytes(phos_batch *b, uint64_t **d_done);
+phos_status phos_batch_get_cfg(phos_batch *b, phos_batch_cfg *cfg);
+/* Change the configuration (synchronizes the device and re-captures). */
+phos_status phos_batch_set_cfg(phos_batch *b, const phos_batch_cfg *cfg);
+
+/* Plain path: a device-resident segment list (synchronous upload) and one
+ * ordinary launch per call, one workgroup per chunk, no graph. */
+phos_status phos_seglist_create(int device, const phos_copy_seg *segs, uint64_t nseg,
+                                phos_seglist **out);
+phos_status phos_seglist_destroy(phos_seglist *l);
+phos_status phos_copy_plain(const phos_seglist *l, uint64_t chunk_bytes, uint32_t threads,
+                            hipStream_t stream);
+
+/* Autotuner: time every candidate of chunk {64 KiB .. 4 MiB} x wg_per_cu
+ * {1, 2, 4, 8} x threads {256, 512, 1024} on the given segments (host
+ * array; their addresses must be valid device memory; the copies are really
+ * performed) and return the fastest.  Results are cached in memory and in
+ * the text file cache_path (may be NULL) under a key of the segment-size
+ * distribution (log2 of total bytes, segment count and mean size). */
+phos_status phos_batch_tune(int device, const phos_copy_seg *segs, uint64_t nseg,
+                            const char *cache_path, phos_batch_cfg *best, double *best_ms);
+
+const char *phos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHOS_H */

@@ -1,0 +1,127 @@
+// internal.h — device-side data layout shared by the runtime and the gfx950
+// kernels of libphos.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "phos.h"
+
+namespace phos {
+
+constexpr uint32_t kMaxIv = 64;          // intervals per speculated set
+constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no buffer / no image page"
+constexpr uint32_t kFree = 0, kClaimed = 1, kDone = 2;  // per-page copy state
+
+// Validation tiling: 256 threads = 4 wave64s; each wave owns a contiguous
+// quarter of the tile; each lane reads two records (one 16-byte load) per
+// 128-record step, four steps in flight.
+constexpr uint32_t kVThreads = 256;
+constexpr uint32_t kVWaves = 4;
+constexpr uint32_t kVStep = 128;                 // records per wave step
+constexpr uint32_t kVUnroll = 4;                 // steps in flight
+constexpr uint32_t kVQuantum = kVWaves * kVStep * kVUnroll;  // tile_recs multiple (2048)
+constexpr uint32_t kWcap = 256;                  // per-wave violation list in LDS
+constexpr uint32_t kTrackWords = 8192;           // LDS dirty-bitmap words (32 KiB)
+constexpr uint32_t kSeg = 1024;                  // tiles per scan segment
+
+// Copy kernels.
+constexpr uint32_t kCThreads = 256;
+constexpr uint32_t kUnitPages = 16;  // pages per copy-on-write work unit
+
+// Interval in the form the kernel tests: an access at a is inside iff
+// (a - lo) <= span (unsigned), span = hi - lo - 8.  Empty-for-8-byte
+// intervals get lo = ~0, span = 0.
+struct DevIv {
+  uint64_t lo, span;
+  uint32_t mode, pad;
+};
+struct DevSpec {
+  uint32_t niv, pad;
+  DevIv iv[kMaxIv];
+};
+
+// One launch's slice of a validation call.
+struct VLaunch {
+  const uint64_t *rec;
+  uint64_t n;
+  uint32_t iv_off, niv;  // intervals ivs[iv_off .. iv_off + niv) (batch only)
+  uint32_t launch_id, tile0;
+};
+
+struct VArgs {
+  const VLaunch *launches;  // device table (batch) or nullptr (single launch below)
+  VLaunch single;
+  const DevIv *ivs;         // flat interval table (batch)
+  uint32_t nlaunch, ntiles;
+  uint32_t flags, tile_recs;
+  uint64_t pool_base, pool_bytes;
+  uint32_t page_shift, n_pages;
+  const uint32_t *page_buf;  // per pool page: buffer index or kNone
+  uint32_t *dirty, *victim;  // bitmaps, bit p%32 of word p/32
+  phos_violation *scratch;
+  uint64_t scratch_cap;
+  unsigned long long *cursor;     // scratch append cursor (reset by the scan)
+  uint32_t *tile_count;           // violations per tile
+  unsigned long long *tile_off;   // scratch offset per tile
+  unsigned long long *seg_sum;    // violations per kSeg tiles (reset by the scan)
+};
+
+// Page-granular copy between the pool and an image under per-page states.
+struct CopyArgs {
+  uint8_t *pool;               // byte at pool_base
+  uint8_t *image;              // byte 0 of the image
+  uint32_t *state;             // per pool page: kFree / kClaimed / kDone
+  const uint32_t *img_page;    // per pool page: image page or kNone
+  unsigned long long *stat;    // pages copied by this kernel family
+  uint32_t *err;               // bit 0: a bounded wait expired
+  uint32_t page_shift, n_pages;
+  uint32_t to_image;           // 1: pool -> image (checkpoint); 0: image -> pool (restore)
+  uint32_t spin_limit;
+};
+
+// Pages [p0, p0 + np) per range, in work units of kUnitPages.
+struct PageRanges {
+  uint32_t n, pad;
+  uint32_t units_prefix[kMaxIv + 1];
+  uint32_t p0[kMaxIv];
+  uint32_t np[kMaxIv];
+};
+
+// Batched-copy work queue: segments, exclusive byte prefix, a chunk cursor.
+struct BatchQ {
+  const phos_copy_seg *segs;
+  const unsigned long long *byte_prefix;  // nseg + 1 entries
+  const unsigned long long *hdr;          // [0] nseg, [1] total bytes, [2] requests
+  unsigned long long *cursor;             // next chunk (reset before each drain)
+  unsigned long long *done;               // per request: bytes copied
+  uint64_t chunk_bytes;
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_validate(const VArgs &a, const DevSpec *single, bool track, hipStream_t s);
+hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
+                        uint64_t *n_out, unsigned long long *cursor, hipStream_t s);
+hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long *tile_off,
+                           uint32_t ntiles, const unsigned long long *seg_prefix,
+                           const phos_violation *scratch, uint64_t scratch_cap,
+                           phos_violation *out, uint64_t cap, hipStream_t s);
+hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const uint32_t *victim_bits,
+                      uint32_t victim_words, bool wait, hipStream_t s);
+hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor, uint32_t nchunks,
+                             uint32_t chunk_pages, uint32_t grid, hipStream_t s);
+hipError_t launch_pagelist(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+                           uint32_t *list, unsigned int *count, hipStream_t s);
+hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
+                               uint32_t grid, hipStream_t s);
+hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,
+                         unsigned long long *faulted, hipStream_t s);
+hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32_t *bits,
+                                 hipStream_t s);
+hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s);
+hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s);
+hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);
+
+}  // namespace phos

@@ -1,0 +1,767 @@
+// kernels.hip — gfx950 kernels of the validated-speculation checkpoint/restore
+// hot path (PhoenixOS, arXiv 2405.12079), written for CDNA4: wave64 ballots,
+// LDS-staged interval tables and dirty bitmaps, 16-byte vector loads/stores.
+//
+//   validate_kernel   Section 4.1 runtime validation + Section 4.3 dirty tracking
+//   vscan / vscatter  ordered compaction of the violation reports
+//   cow_kernel        Section 4.2 pre-launch copy of pages about to be written
+//   background_kernel Section 4.2/4.3/6 concurrent bulk copy under per-page claims
+//   pagelist/gather   Section 4.3 recopy of dirty and victim pages
+//   demand_kernel     Section 6 on-demand restore of the pages a launch touches
+//   batch_copy        persistent copy of many requests' segments (no paper analog)
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace phos {
+namespace {
+
+__device__ __forceinline__ uint32_t ld_acquire(uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_relaxed(uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_release(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas_u32(uint32_t *p, uint32_t &expected, uint32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+  return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
+}
+
+// Set `bits` in a global bitmap word unless they are all set already (a stale
+// read only costs a redundant atomic: bits are never cleared during a pass).
+__device__ __forceinline__ void or_word(uint32_t *w, uint32_t bits) {
+  if ((ld_relaxed(w) & bits) != bits) atomicOr(w, bits);
+}
+
+// Block-cooperative 16-byte copy, four loads in flight per thread.
+__device__ __forceinline__ void block_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                             uint64_t n16) {
+  const uint64_t T = blockDim.x;
+  uint64_t i = threadIdx.x;
+  for (; i + 3 * T < n16; i += 4 * T) {
+    const uint4 a = src[i], b = src[i + T], c = src[i + 2 * T], d = src[i + 3 * T];
+    dst[i] = a;
+    dst[i + T] = b;
+    dst[i + 2 * T] = c;
+    dst[i + 3 * T] = d;
+  }
+  for (; i < n16; i += T) dst[i] = src[i];
+}
+
+// ============================================================ validation
+struct IvRegs {
+  uint64_t lo[8], span[8];
+  uint32_t mode[8];
+  uint32_t n;
+};
+
+// 0 = valid; 1 = in no interval; 2 = inside but the mode bit is missing.
+// jw: an interval that validates a write (for dirty tracking).
+template <bool TRACK>
+__device__ __forceinline__ uint32_t classify_fast(const IvRegs &R, uint64_t a, uint32_t w, int &jw) {
+  bool inside = false, ok = false;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j < (int)R.n) {
+      const bool in = (a - R.lo[j]) <= R.span[j];
+      const bool m = (R.mode[j] >> w) & 1u;
+      inside |= in;
+      if (in && m) {
+        ok = true;
+        if (TRACK) jw = j;
+      }
+    }
+  }
+  return ok ? 0u : (inside ? 2u : 1u);
+}
+
+template <bool TRACK>
+__device__ __forceinline__ uint32_t classify_slow(const DevSpec &S, uint32_t niv, uint64_t a,
+                                                  uint32_t w, int &jw) {
+  bool inside = false, ok = false;
+  for (uint32_t j = 0; j < niv; ++j) {
+    const bool in = (a - S.iv[j].lo) <= S.iv[j].span;
+    const bool m = (S.iv[j].mode >> w) & 1u;
+    inside |= in;
+    if (in && m) {
+      ok = true;
+      if (TRACK) jw = (int)j;
+    }
+  }
+  return ok ? 0u : (inside ? 2u : 1u);
+}
+
+struct VShared {
+  DevSpec spec;
+  uint32_t list[kVWaves][kWcap];
+  uint32_t wcnt[kVWaves];
+  uint32_t seg_base[kMaxIv], seg_fw[kMaxIv];
+  uint32_t seg_nw;  // LDS dirty words in use, or kNone (global path)
+  VLaunch L;
+  unsigned long long off;
+};
+
+template <bool TRACK>
+__device__ __forceinline__ bool check_record(const VArgs &A, const VShared &S, const IvRegs &R,
+                                             bool fast, uint32_t niv, uint32_t *s_track,
+                                             uint64_t r, bool valid) {
+  const uint64_t a = r & ~7ull;
+  const uint32_t w = (uint32_t)(r & 1u);
+  int jw = -1;
+  const uint32_t reason = fast ? classify_fast<TRACK>(R, a, w, jw)
+                               : classify_slow<TRACK>(S.spec, niv, a, w, jw);
+  if (TRACK && valid && w) {
+    const uint64_t off = a - A.pool_base;
+    if (off < A.pool_bytes) {
+      const uint32_t page = (uint32_t)(off >> A.page_shift);
+      const uint32_t bit = 1u << (page & 31);
+      if (reason == 0) {
+        if (S.seg_nw != kNone) {
+          const uint32_t base = S.seg_base[jw];
+          if (base != kNone) atomicOr(&s_track[base + (page >> 5) - S.seg_fw[jw]], bit);
+        } else {
+          or_word(&A.dirty[page >> 5], bit);
+        }
+      } else if (A.page_buf[page] != kNone) {
+        or_word(&A.victim[page >> 5], bit);
+      }
+    }
+  }
+  return valid && reason != 0 && ((A.flags >> w) & 1u);
+}
+
+__device__ __forceinline__ void emit_violation(const VArgs &A, const VShared &S, const IvRegs &R,
+                                               bool fast, uint32_t niv, uint64_t idx, uint64_t r,
+                                               unsigned long long pos) {
+  if (pos >= A.scratch_cap) return;
+  const uint64_t a = r & ~7ull;
+  const uint32_t w = (uint32_t)(r & 1u);
+  int jw = -1;
+  const uint32_t reason =
+      fast ? classify_fast<false>(R, a, w, jw) : classify_slow<false>(S.spec, niv, a, w, jw);
+  const uint64_t off = a - A.pool_base;
+  const uint32_t b = off < A.pool_bytes ? A.page_buf[off >> A.page_shift] : kNone;
+  phos_violation v;
+  v.index = idx;
+  v.addr = a;
+  v.launch_id = S.L.launch_id;
+  v.is_write = (uint8_t)w;
+  v.reason = (uint8_t)reason;
+  v._p = 0;
+  v.victim = (int32_t)b;
+  v._q = 0;
+  A.scratch[pos] = v;
+}
+
+template <bool BATCH, bool TRACK>
+__global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec single) {
+  __shared__ VShared S;
+  __shared__ uint32_t s_track[TRACK ? kTrackWords : 1];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const uint32_t tile = blockIdx.x;
+
+  if (tid == 0) {
+    if (BATCH) {
+      uint32_t lo = 0, hi = A.nlaunch;  // last launch with tile0 <= tile
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A.launches[mid].tile0 <= tile) lo = mid; else hi = mid;
+      }
+      S.L = A.launches[lo];
+    } else {
+      S.L = A.single;
+    }
+  }
+  __syncthreads();
+  const uint32_t niv = rfl(BATCH ? S.L.niv : single.niv);
+  for (uint32_t j = tid; j < niv; j += kVThreads)
+    S.spec.iv[j] = BATCH ? A.ivs[S.L.iv_off + j] : single.iv[j];
+  __syncthreads();
+
+  if (TRACK) {
+    if (tid == 0) {
+      // LDS segment per write interval, aligned to global bitmap words.
+      uint32_t nw = 0;
+      const uint64_t pool_end = A.pool_base + A.pool_bytes;
+      for (uint32_t j = 0; j < niv; ++j) {
+        const DevIv iv = S.spec.iv[j];
+        S.seg_base[j] = kNone;
+        if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
+        const uint64_t hi = iv.lo + iv.span + 8;
+        const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
+        const uint64_t hi_c = hi < pool_end ? hi : pool_end;
+        if (hi_c <= lo_c) continue;
+        const uint32_t fw = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
+        const uint32_t lw = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
+        S.seg_fw[j] = fw;
+        S.seg_base[j] = nw;
+        nw += lw - fw + 1;
+        if (nw > kTrackWords) break;
+      }
+      S.seg_nw = nw <= kTrackWords ? nw : kNone;
+    }
+    __syncthreads();
+    if (S.seg_nw != kNone)
+      for (uint32_t j = tid; j < S.seg_nw; j += kVThreads) s_track[j] = 0;
+    __syncthreads();
+  }
+
+  IvRegs R;
+  const bool fast = niv <= 8;
+  R.n = fast ? niv : 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j < (int)R.n) {
+      R.lo[j] = rfl64(S.spec.iv[j].lo);
+      R.span[j] = rfl64(S.spec.iv[j].span);
+      R.mode[j] = rfl(S.spec.iv[j].mode);
+    } else {
+      R.lo[j] = ~0ull;
+      R.span[j] = 0;
+      R.mode[j] = 0;
+    }
+  }
+
+  const uint64_t n = S.L.n;
+  const uint64_t *__restrict__ rec = S.L.rec;
+  const uint32_t Q = A.tile_recs / kVWaves;
+  const uint64_t wbase = (uint64_t)(tile - S.L.tile0) * A.tile_recs + (uint64_t)wave * Q;
+  const bool al16 = (((uintptr_t)rec) & 15u) == 0;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t wcnt = 0;
+
+  for (uint32_t c = 0; c < Q; c += kVStep * kVUnroll) {
+    if (wbase + c >= n) break;
+    uint64_t r0[kVUnroll], r1[kVUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kVUnroll; ++u) {
+      const uint64_t i0 = wbase + c + u * kVStep + 2 * lane;
+      r0[u] = 0;
+      r1[u] = 0;
+      if (i0 + 1 < n) {
+        if (al16) {
+          const uint4 q = *reinterpret_cast<const uint4 *>(rec + i0);
+          r0[u] = ((uint64_t)q.y << 32) | q.x;
+          r1[u] = ((uint64_t)q.w << 32) | q.z;
+        } else {
+          r0[u] = rec[i0];
+          r1[u] = rec[i0 + 1];
+        }
+      } else if (i0 < n) {
+        r0[u] = rec[i0];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kVUnroll; ++u) {
+      const uint32_t local = c + u * kVStep + 2 * lane;
+      const uint64_t i0 = wbase + local;
+      const bool b0 = check_record<TRACK>(A, S, R, fast, niv, s_track, r0[u], i0 < n);
+      const bool b1 = check_record<TRACK>(A, S, R, fast, niv, s_track, r1[u], i0 + 1 < n);
+      const uint64_t m0 = __ballot(b0), m1 = __ballot(b1);
+      if (m0 | m1) {
+        const uint32_t rk = wcnt + __popcll(m0 & lt) + __popcll(m1 & lt);
+        if (b0 && rk < kWcap) S.list[wave][rk] = local;
+        const uint32_t rk1 = rk + (b0 ? 1u : 0u);
+        if (b1 && rk1 < kWcap) S.list[wave][rk1] = local + 1;
+        wcnt += __popcll(m0) + __popcll(m1);
+      }
+    }
+  }
+
+  if (lane == 0) S.wcnt[wave] = wcnt;
+  __syncthreads();
+
+  if (TRACK && S.seg_nw != kNone) {
+    for (uint32_t w = tid; w < S.seg_nw; w += kVThreads) {
+      const uint32_t v = s_track[w];
+      if (!v) continue;
+      uint32_t jj = 0, bb = 0;
+      for (uint32_t j = 0; j < niv; ++j) {
+        const uint32_t b = S.seg_base[j];
+        if (b != kNone && b <= w && b >= bb) { jj = j; bb = b; }
+      }
+      or_word(&A.dirty[S.seg_fw[jj] + (w - bb)], v);
+    }
+  }
+
+  if (tid == 0) {
+    uint32_t total = 0;
+    for (uint32_t w = 0; w < kVWaves; ++w) total += S.wcnt[w];
+    A.tile_count[tile] = total;
+    unsigned long long off = 0;
+    if (total) {
+      off = atomicAdd(A.cursor, (unsigned long long)total);
+      A.tile_off[tile] = off;
+      atomicAdd(&A.seg_sum[tile / kSeg], (unsigned long long)total);
+    }
+    S.off = off;
+  }
+  __syncthreads();
+  if (wcnt == 0) return;
+
+  unsigned long long start = S.off;
+  for (uint32_t w = 0; w < wave; ++w) start += S.wcnt[w];
+  if (wcnt <= kWcap) {
+    for (uint32_t j = lane; j < wcnt; j += 64) {
+      const uint64_t i = wbase + S.list[wave][j];
+      emit_violation(A, S, R, fast, niv, i, rec[i], start + j);
+    }
+  } else {
+    // More violations than the LDS list holds: rescan this wave's range in
+    // order and write each one at its rank (rare: degenerate launches).
+    uint32_t cnt = 0;
+    for (uint32_t c = 0; c < Q; c += kVStep) {
+      if (wbase + c >= n) break;
+      const uint64_t i0 = wbase + c + 2 * lane;
+      const uint64_t r0 = i0 < n ? rec[i0] : 0, r1 = i0 + 1 < n ? rec[i0 + 1] : 0;
+      const bool b0 = check_record<false>(A, S, R, fast, niv, nullptr, r0, i0 < n);
+      const bool b1 = check_record<false>(A, S, R, fast, niv, nullptr, r1, i0 + 1 < n);
+      const uint64_t m0 = __ballot(b0), m1 = __ballot(b1);
+      const uint32_t rk = cnt + __popcll(m0 & lt) + __popcll(m1 & lt);
+      if (b0) emit_violation(A, S, R, fast, niv, i0, r0, start + rk);
+      if (b1) emit_violation(A, S, R, fast, niv, i0 + 1, r1, start + rk + (b0 ? 1u : 0u));
+      cnt += __popcll(m0) + __popcll(m1);
+    }
+  }
+}
+
+// Exclusive scan of per-segment violation counts (one block of 1024).
+__global__ void __launch_bounds__(1024)
+    vscan_kernel(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
+                 uint64_t *n_out, unsigned long long *cursor) {
+  __shared__ unsigned long long s[1024];
+  const uint32_t t = threadIdx.x;
+  unsigned long long carry = 0;
+  for (uint32_t base = 0; base < nseg; base += 1024) {
+    const unsigned long long v = base + t < nseg ? seg_sum[base + t] : 0ull;
+    s[t] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      const unsigned long long x = t >= d ? s[t - d] : 0ull;
+      __syncthreads();
+      s[t] += x;
+      __syncthreads();
+    }
+    if (base + t < nseg) {
+      seg_prefix[base + t] = carry + s[t] - v;
+      seg_sum[base + t] = 0;
+    }
+    carry += s[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    *n_out = carry;
+    *cursor = 0;
+  }
+}
+
+// Move each tile's violations from scratch to their ordered place.
+__global__ void __launch_bounds__(1024)
+    vscatter_kernel(const uint32_t *tile_count, const unsigned long long *tile_off, uint32_t ntiles,
+                    const unsigned long long *seg_prefix, const phos_violation *scratch,
+                    uint64_t scratch_cap, phos_violation *out, uint64_t cap) {
+  __shared__ uint32_t s[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t tile = blockIdx.x * 1024 + t;
+  const uint32_t c = tile < ntiles ? tile_count[tile] : 0;
+  s[t] = c;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const uint32_t x = t >= d ? s[t - d] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  if (!c) return;
+  const unsigned long long dst = seg_prefix[blockIdx.x] + s[t] - c;
+  const unsigned long long src = tile_off[tile];
+  for (uint32_t i = 0; i < c; ++i)
+    if (dst + i < cap && src + i < scratch_cap) out[dst + i] = scratch[src + i];
+}
+
+// ============================================================ page copies
+__device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
+  const uint64_t pb = 1ull << C.page_shift;
+  uint8_t *pool_p = C.pool + ((uint64_t)p << C.page_shift);
+  uint8_t *img_p = C.image + ((uint64_t)C.img_page[p] << C.page_shift);
+  const uint4 *src = reinterpret_cast<const uint4 *>(C.to_image ? pool_p : img_p);
+  uint4 *dst = reinterpret_cast<uint4 *>(C.to_image ? img_p : pool_p);
+  block_copy16(src, dst, pb >> 4);
+}
+
+// Block-collective: every thread offers at most one candidate page.  Pages
+// still free are claimed (one winner per page across the whole GPU), copied
+// by this block, then published as done; with WAIT, a thread whose page is
+// claimed by someone else waits until it is done.  Every claimer publishes
+// before it waits, so no wait can form a cycle.
+template <bool WAIT>
+__device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long *extra) {
+  __shared__ uint32_t s_won[kCThreads];
+  __shared__ uint32_t s_nwon;
+  if (threadIdx.x == 0) s_nwon = 0;
+  __syncthreads();
+  bool wait = false;
+  if (cand != kNone && C.img_page[cand] != kNone) {
+    uint32_t st = ld_relaxed(&C.state[cand]);
+    if (st == kFree) {
+      uint32_t exp = kFree;
+      if (cas_u32(&C.state[cand], exp, kClaimed)) {
+        s_won[atomicAdd(&s_nwon, 1u)] = cand;
+        st = kDone;  // ours: published below
+      } else {
+        st = exp;
+      }
+    }
+    wait = (st == kClaimed);
+  }
+  __syncthreads();
+  const uint32_t nwon = s_nwon;
+  for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i]);
+  if (nwon) __threadfence();
+  __syncthreads();
+  if (threadIdx.x < nwon) st_release(&C.state[s_won[threadIdx.x]], kDone);
+  if (threadIdx.x == 0 && nwon) {
+    atomicAdd(C.stat, (unsigned long long)nwon);
+    if (extra) atomicAdd(extra, (unsigned long long)nwon);
+  }
+  if (WAIT && wait) {
+    uint32_t it = 0;
+    while (ld_acquire(&C.state[cand]) != kDone) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++it > C.spin_limit) {
+        atomicOr(C.err, 1u);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Section 4.2: units over the pages of the write intervals, then units of
+// 256 victim-bitmap words (pages hit by failing writes inside buffers).
+__global__ void __launch_bounds__(kCThreads)
+    cow_kernel(CopyArgs C, PageRanges R, const uint32_t *victim_bits, uint32_t victim_words,
+               uint32_t wait) {
+  const uint32_t unit = blockIdx.x;
+  const uint32_t t = threadIdx.x;
+  const uint32_t range_units = R.units_prefix[R.n];
+  if (unit < range_units) {
+    uint32_t j = 0;
+    while (j + 1 < R.n && R.units_prefix[j + 1] <= unit) ++j;
+    const uint32_t first = (unit - R.units_prefix[j]) * kUnitPages;
+    const uint32_t cand = (t < kUnitPages && first + t < R.np[j]) ? R.p0[j] + first + t : kNone;
+    if (wait) claim_copy<true>(cand, C, nullptr);
+    else claim_copy<false>(cand, C, nullptr);
+    return;
+  }
+  const uint32_t w = (unit - range_units) * kCThreads + t;
+  uint32_t bits = (victim_bits && w < victim_words) ? victim_bits[w] : 0u;
+  while (__syncthreads_or(bits != 0u)) {
+    uint32_t cand = kNone;
+    if (bits) {
+      const uint32_t p = w * 32 + (__ffs(bits) - 1);
+      bits &= bits - 1;
+      if (p < C.n_pages) cand = p;
+    }
+    if (wait) claim_copy<true>(cand, C, nullptr);
+    else claim_copy<false>(cand, C, nullptr);
+  }
+}
+
+// Background copy: persistent blocks take 4 MiB chunks of pages in order.
+__global__ void __launch_bounds__(kCThreads)
+    background_kernel(CopyArgs C, unsigned long long *chunk_cursor, uint32_t nchunks,
+                      uint32_t chunk_pages) {
+  __shared__ uint32_t s_chunk;
+  for (;;) {
+    if (threadIdx.x == 0) s_chunk = (uint32_t)atomicAdd(chunk_cursor, 1ull);
+    __syncthreads();
+    const uint32_t c = s_chunk;
+    __syncthreads();
+    if (c >= nchunks) break;
+    for (uint32_t g = 0; g < chunk_pages; g += kCThreads) {
+      const uint64_t p = (uint64_t)c * chunk_pages + g + threadIdx.x;
+      const uint32_t cand = (g + threadIdx.x < chunk_pages && p < C.n_pages) ? (uint32_t)p : kNone;
+      claim_copy<false>(cand, C, nullptr);
+    }
+  }
+}
+
+// Section 4.3: (dirty | victim) bitmap -> page list, wave64 prefix-sum compaction.
+__global__ void __launch_bounds__(256)
+    pagelist_kernel(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+                    uint32_t *list, unsigned int *count) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t bits = 0;
+  if (w < nwords) {
+    bits = a[w] | (b ? b[w] : 0u);
+    const uint64_t last = (uint64_t)w * 32 + 32;
+    if (last > n_pages) bits &= (n_pages - w * 32 >= 32) ? ~0u : ((1u << (n_pages - w * 32)) - 1u);
+  }
+  const uint32_t c = __popc(bits);
+  uint32_t incl = c;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t x = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += x;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane == 0 && total) base = atomicAdd(count, total);
+  base = __shfl(base, 0, 64);
+  uint32_t pos = base + incl - c;
+  while (bits) {
+    const uint32_t bit = __ffs(bits) - 1;
+    list[pos++] = w * 32 + bit;
+    bits &= bits - 1;
+  }
+}
+
+// Copy the listed pages (no claims: the application is quiesced).
+__global__ void __launch_bounds__(kCThreads)
+    gather_pages_kernel(CopyArgs C, const uint32_t *list, const unsigned int *count) {
+  const uint32_t cnt = *count;
+  uint32_t nw = 0;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const uint32_t p = list[i];
+    if (p < C.n_pages && C.img_page[p] != kNone) {
+      copy_page(C, p);
+      ++nw;
+    }
+  }
+  if (threadIdx.x == 0 && nw) atomicAdd(C.stat, (unsigned long long)nw);
+}
+
+// Section 6: bring in every not-yet-present page (inside a buffer) that the
+// launch's records touch, before the launch runs.
+constexpr uint32_t kDemandPerThread = 4;
+__global__ void __launch_bounds__(kCThreads)
+    demand_kernel(CopyArgs C, const uint64_t *rec, uint64_t n, uint64_t pool_base,
+                  unsigned long long *faulted) {
+  const uint64_t base = (uint64_t)blockIdx.x * kCThreads * kDemandPerThread;
+  const uint64_t pool_bytes = (uint64_t)C.n_pages << C.page_shift;
+  for (uint32_t u = 0; u < kDemandPerThread; ++u) {
+    const uint64_t i = base + (uint64_t)u * kCThreads + threadIdx.x;
+    uint32_t cand = kNone;
+    if (i < n) {
+      const uint64_t off = (rec[i] & ~7ull) - pool_base;
+      if (off < pool_bytes) {
+        const uint32_t p = (uint32_t)(off >> C.page_shift);
+        if (C.img_page[p] != kNone && ld_relaxed(&C.state[p]) != kDone) cand = p;
+      }
+    }
+    claim_copy<true>(cand, C, faulted);
+  }
+}
+
+__global__ void states_to_bits_kernel(const uint32_t *state, uint32_t n_pages, uint32_t *bits) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((uint64_t)w * 32 >= n_pages) return;
+  uint32_t v = 0;
+  for (uint32_t b = 0; b < 32; ++b) {
+    const uint64_t p = (uint64_t)w * 32 + b;
+    if (p < n_pages && state[p] == kDone) v |= 1u << b;
+  }
+  bits[w] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long long v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ============================================================ batched copy
+// Copy bytes [b0, b1) of the concatenated segment stream.
+__device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, uint64_t b1) {
+  __shared__ uint32_t s_seg;
+  if (threadIdx.x == 0) {
+    uint64_t lo = 0, hi = nseg;  // last segment with prefix <= b0
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (Q.byte_prefix[mid] <= b0) lo = mid; else hi = mid;
+    }
+    s_seg = (uint32_t)lo;
+  }
+  __syncthreads();
+  uint64_t s = s_seg;
+  __syncthreads();
+  uint64_t pos = b0;
+  while (pos < b1 && s < nseg) {
+    const uint64_t seg_lo = Q.byte_prefix[s], seg_hi = Q.byte_prefix[s + 1];
+    const uint64_t lo = pos > seg_lo ? pos : seg_lo;
+    const uint64_t hi = b1 < seg_hi ? b1 : seg_hi;
+    if (hi > lo) {
+      const phos_copy_seg g = Q.segs[s];
+      block_copy16(reinterpret_cast<const uint4 *>(g.src + (lo - seg_lo)),
+                   reinterpret_cast<uint4 *>(g.dst + (lo - seg_lo)), (hi - lo) >> 4);
+      if (threadIdx.x == 0) atomicAdd(&Q.done[g.req], (unsigned long long)(hi - lo));
+      pos = hi;
+    }
+    ++s;
+  }
+}
+
+// Reset the chunk cursor and the per-request completed-byte counters.
+__global__ void batch_reset_kernel(const unsigned long long *hdr, unsigned long long *cursor,
+                                   unsigned long long *done) {
+  const uint64_t nreq = hdr[2];
+  for (uint64_t i = threadIdx.x; i < nreq; i += blockDim.x) done[i] = 0;
+  if (threadIdx.x == 0) *cursor = 0;
+}
+
+// Persistent: resident blocks claim chunk_bytes pieces of the stream in order.
+__global__ void batch_copy_kernel(BatchQ Q) {
+  __shared__ unsigned long long s_chunk;
+  const uint64_t nseg = Q.hdr[0], total = Q.hdr[1];
+  const uint64_t nchunks = (total + Q.chunk_bytes - 1) / Q.chunk_bytes;
+  for (;;) {
+    if (threadIdx.x == 0) s_chunk = atomicAdd(Q.cursor, 1ull);
+    __syncthreads();
+    const uint64_t c = s_chunk;
+    __syncthreads();
+    if (c >= nchunks) break;
+    const uint64_t b0 = c * Q.chunk_bytes;
+    copy_stream_range(Q, nseg, b0, b0 + Q.chunk_bytes < total ? b0 + Q.chunk_bytes : total);
+  }
+}
+
+// Plain: one block per chunk, no persistence.
+__global__ void plain_copy_kernel(BatchQ Q) {
+  const uint64_t nseg = Q.hdr[0], total = Q.hdr[1];
+  const uint64_t b0 = (uint64_t)blockIdx.x * Q.chunk_bytes;
+  if (b0 >= total) return;
+  copy_stream_range(Q, nseg, b0, b0 + Q.chunk_bytes < total ? b0 + Q.chunk_bytes : total);
+}
+
+unsigned grid_cap(uint64_t n, unsigned block, unsigned cap) {
+  uint64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ============================================================ launchers
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_cap(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_cap(n, 256, 4096)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const VArgs &a, const DevSpec *single, bool track, hipStream_t s) {
+  if (!a.ntiles) return hipSuccess;
+  const DevSpec &sp = *single;
+  const dim3 g(a.ntiles), b(kVThreads);
+  if (a.launches) {
+    if (track) hipLaunchKernelGGL((validate_kernel<true, true>), g, b, 0, s, a, sp);
+    else hipLaunchKernelGGL((validate_kernel<true, false>), g, b, 0, s, a, sp);
+  } else {
+    if (track) hipLaunchKernelGGL((validate_kernel<false, true>), g, b, 0, s, a, sp);
+    else hipLaunchKernelGGL((validate_kernel<false, false>), g, b, 0, s, a, sp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
+                        uint64_t *n_out, unsigned long long *cursor, hipStream_t s) {
+  hipLaunchKernelGGL(vscan_kernel, dim3(1), dim3(1024), 0, s, seg_sum, nseg, seg_prefix, n_out,
+                     cursor);
+  return hipGetLastError();
+}
+
+hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long *tile_off,
+                           uint32_t ntiles, const unsigned long long *seg_prefix,
+                           const phos_violation *scratch, uint64_t scratch_cap,
+                           phos_violation *out, uint64_t cap, hipStream_t s) {
+  if (!ntiles) return hipSuccess;
+  hipLaunchKernelGGL(vscatter_kernel, dim3((ntiles + kSeg - 1) / kSeg), dim3(1024), 0, s,
+                     tile_count, tile_off, ntiles, seg_prefix, scratch, scratch_cap, out, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const uint32_t *victim_bits,
+                      uint32_t victim_words, bool wait, hipStream_t s) {
+  uint32_t units = r.units_prefix[r.n];
+  if (victim_bits) units += (victim_words + kCThreads - 1) / kCThreads;
+  if (!units) return hipSuccess;
+  hipLaunchKernelGGL(cow_kernel, dim3(units), dim3(kCThreads), 0, s, c, r, victim_bits,
+                     victim_words, wait ? 1u : 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor, uint32_t nchunks,
+                             uint32_t chunk_pages, uint32_t grid, hipStream_t s) {
+  if (!nchunks) return hipSuccess;
+  hipLaunchKernelGGL(background_kernel, dim3(grid), dim3(kCThreads), 0, s, c, chunk_cursor, nchunks,
+                     chunk_pages);
+  return hipGetLastError();
+}
+
+hipError_t launch_pagelist(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+                           uint32_t *list, unsigned int *count, hipStream_t s) {
+  if (!nwords) return hipSuccess;
+  hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, nwords,
+                     n_pages, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
+                               uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(gather_pages_kernel, dim3(grid), dim3(kCThreads), 0, s, c, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,
+                         unsigned long long *faulted, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const uint64_t per = (uint64_t)kCThreads * kDemandPerThread;
+  hipLaunchKernelGGL(demand_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(kCThreads), 0, s, c,
+                     rec, n, pool_base, faulted);
+  return hipGetLastError();
+}
+
+hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32_t *bits,
+                                 hipStream_t s) {
+  const uint32_t nw = (n_pages + 31) / 32;
+  if (!nw) return hipSuccess;
+  hipLaunchKernelGGL(states_to_bits_kernel, dim3((nw + 255) / 256), dim3(256), 0, s, state, n_pages,
+                     bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, q.hdr, q.cursor, q.done);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s) {
+  hipLaunchKernelGGL(batch_copy_kernel, dim3(grid), dim3(threads), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s) {
+  if (!nchunks) return hipSuccess;
+  hipLaunchKernelGGL(plain_copy_kernel, dim3((unsigned)nchunks), dim3(threads), 0, s, q);
+  return hipGetLastError();
+}
+
+}  // namespace phos

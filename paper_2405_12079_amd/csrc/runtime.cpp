@@ -1,0 +1,905 @@
+// runtime.cpp — host side of libphos: context, speculation (interval sets),
+// validation orchestration, and the soft copy-on-write, soft recopy and
+// concurrent-restore protocols (PhoenixOS, arXiv 2405.12079, Sections 4-6),
+// driving the gfx950 kernels in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "phos.h"
+#include "util.h"
+
+using namespace phos;
+
+// ------------------------------------------------------------------ errors
+namespace phos {
+static thread_local std::string g_err;
+
+phos_status fail(phos_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+uint32_t env_u32(const char *name, uint32_t dflt) {
+  const char *v = getenv(name);
+  if (!v || !*v) return dflt;
+  return (uint32_t)strtoul(v, nullptr, 0);
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+  if (prev_ != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev_ >= 0) (void)hipSetDevice(prev_);
+}
+}  // namespace phos
+
+extern "C" const char *phos_last_error(void) { return g_err.c_str(); }
+
+// --------------------------------------------------------------- structures
+struct HostSpec {
+  bool used = false;
+  uint32_t launch_id = 0;
+  std::vector<phos_interval> iv;  // sorted by (lo, hi)
+};
+
+struct Slot {  // per-protocol reusable device state of a checkpoint / restore
+  uint32_t *state = nullptr;               // per pool page
+  unsigned long long *counters = nullptr;  // [0] chunk cursor, [1..3] stats
+  uint32_t *list = nullptr;                // recopy page list
+  unsigned int *list_count = nullptr;
+};
+
+struct phos_ctx {
+  int device = 0;
+  uint64_t pool_base = 0, pool_bytes = 0;
+  uint32_t page_bytes = 0, page_shift = 0, n_pages = 0, nwords = 0;
+  std::vector<phos_buffer> bufs;
+  uint64_t image_bytes = 0;
+  uint32_t n_cu = 256;
+
+  uint32_t *d_page_buf = nullptr, *d_img_page = nullptr;
+  uint32_t *d_dirty = nullptr, *d_victim = nullptr;
+  uint32_t *d_err = nullptr;
+
+  // validation workspace
+  phos_violation *d_scratch = nullptr;
+  uint64_t scratch_cap = 0;
+  unsigned long long *d_cursor = nullptr;
+  uint32_t *d_tile_count = nullptr;
+  unsigned long long *d_tile_off = nullptr;
+  uint64_t tile_cap = 0;
+  unsigned long long *d_seg_sum = nullptr, *d_seg_prefix = nullptr;
+  uint64_t seg_cap = 0;
+  hipEvent_t v_evt = nullptr;
+  bool v_evt_used = false;
+
+  // batch descriptors: device [VLaunch x n][DevIv x m], pinned staging
+  void *d_vbatch = nullptr;
+  size_t vbatch_cap = 0;
+  void *h_vstage = nullptr;
+  size_t vstage_cap = 0;
+  std::vector<uint8_t> last_vbatch;  // content of the last upload
+  hipEvent_t vstage_evt = nullptr;
+  bool vstage_used = false;
+
+  std::vector<HostSpec> specs;
+  std::vector<uint32_t> free_specs;
+
+  Slot slots[3];  // [1] CoW, [2] recopy, [0] restore
+  phos_ckpt *open_ckpt[3] = {nullptr, nullptr, nullptr};
+  phos_rst *open_rst = nullptr;
+
+  hipStream_t aux = nullptr;     // private stream for synchronous reads
+  unsigned long long *h_pinned = nullptr;  // small pinned readback area
+
+  uint32_t bg_grid = 512, spin_limit = 1u << 24;
+};
+
+struct phos_ckpt {
+  phos_ctx *ctx;
+  uint32_t protocol, flags;
+  uint8_t *image;
+  void *host_image;
+  hipStream_t copy;
+  Slot *slot;
+  bool recopied = false;
+  bool bg_started = false;
+};
+
+struct phos_rst {
+  phos_ctx *ctx;
+  uint32_t flags;
+  const uint8_t *image;
+  hipStream_t copy;
+  Slot *slot;
+  bool bg_started = false;
+};
+
+#define HIP_TRY(x)                                                                  \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) return fail(PHOS_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+static phos_status dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (!count) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(PHOS_E_NOMEM, "hipMalloc(%zu): %s", count * sizeof(T),
+                                   hipGetErrorString(e));
+  return PHOS_OK;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    phos_status s_ = (x);             \
+    if (s_ != PHOS_OK) return s_;     \
+  } while (0)
+
+static bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+
+// ------------------------------------------------------------------ context
+static phos_status ctx_free(phos_ctx *c) {
+  (void)hipDeviceSynchronize();
+  void *ptrs[] = {c->d_page_buf, c->d_img_page, c->d_dirty, c->d_victim, c->d_err, c->d_scratch,
+                  c->d_cursor, c->d_tile_count, c->d_tile_off, c->d_seg_sum, c->d_seg_prefix,
+                  c->d_vbatch};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (Slot &s : c->slots) {
+    if (s.state) (void)hipFree(s.state);
+    if (s.counters) (void)hipFree(s.counters);
+    if (s.list) (void)hipFree(s.list);
+    if (s.list_count) (void)hipFree(s.list_count);
+  }
+  if (c->h_vstage) (void)hipHostFree(c->h_vstage);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->v_evt) (void)hipEventDestroy(c->v_evt);
+  if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  delete c;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes,
+                                   uint32_t page_bytes, phos_ctx **out) {
+  if (!out) return fail(PHOS_E_INVAL, "phos_create: out is NULL");
+  *out = nullptr;
+  if (!is_pow2(page_bytes) || page_bytes < 4096 || page_bytes > (2u << 20))
+    return fail(PHOS_E_INVAL, "page_bytes %u must be a power of two in [4 KiB, 2 MiB]", page_bytes);
+  if (!pool_base || pool_base % page_bytes || !pool_bytes || pool_bytes % page_bytes)
+    return fail(PHOS_E_INVAL, "pool base/size must be non-zero multiples of the page size");
+  if (pool_bytes / page_bytes >= 0xFFFFFFF0ull)
+    return fail(PHOS_E_INVAL, "pool has too many pages");
+  if (pool_base + pool_bytes < pool_base) return fail(PHOS_E_INVAL, "pool wraps the address space");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(PHOS_E_INVAL, "no HIP device %d", device);
+  DeviceGuard g(device);
+  phos_ctx *c = new phos_ctx;
+  c->device = device;
+  c->pool_base = pool_base;
+  c->pool_bytes = pool_bytes;
+  c->page_bytes = page_bytes;
+  c->page_shift = (uint32_t)__builtin_ctzll(page_bytes);
+  c->n_pages = (uint32_t)(pool_bytes / page_bytes);
+  c->nwords = (c->n_pages + 31) / 32;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = (uint32_t)prop.multiProcessorCount;
+  c->bg_grid = env_u32("PHOS_BG_GRID", 2 * c->n_cu);
+  c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
+  phos_status st = PHOS_OK;
+#define CK(x)                  \
+  do {                         \
+    st = (x);                  \
+    if (st != PHOS_OK) {       \
+      ctx_free(c);             \
+      return st;               \
+    }                          \
+  } while (0)
+  CK(dalloc(&c->d_page_buf, c->n_pages));
+  CK(dalloc(&c->d_img_page, c->n_pages));
+  CK(dalloc(&c->d_dirty, c->nwords));
+  CK(dalloc(&c->d_victim, c->nwords));
+  CK(dalloc(&c->d_err, 1));
+  c->scratch_cap = 1u << 20;
+  CK(dalloc(&c->d_scratch, c->scratch_cap));
+  CK(dalloc(&c->d_cursor, 1));
+  c->tile_cap = 1u << 16;
+  CK(dalloc(&c->d_tile_count, c->tile_cap));
+  CK(dalloc(&c->d_tile_off, c->tile_cap));
+  c->seg_cap = c->tile_cap / kSeg + 1;
+  CK(dalloc(&c->d_seg_sum, c->seg_cap));
+  CK(dalloc(&c->d_seg_prefix, c->seg_cap));
+  auto hipck = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+      fail(PHOS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+      return false;
+    }
+    return true;
+  };
+  if (!hipck(hipMemset(c->d_page_buf, 0xFF, c->n_pages * 4ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_img_page, 0xFF, c->n_pages * 4ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_dirty, 0, c->nwords * 4ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_victim, 0, c->nwords * 4ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_err, 0, 4), "hipMemset") ||
+      !hipck(hipMemset(c->d_cursor, 0, 8), "hipMemset") ||
+      !hipck(hipMemset(c->d_seg_sum, 0, c->seg_cap * 8), "hipMemset") ||
+      !hipck(hipEventCreateWithFlags(&c->v_evt, hipEventDisableTiming), "hipEventCreate") ||
+      !hipck(hipEventCreateWithFlags(&c->vstage_evt, hipEventDisableTiming), "hipEventCreate") ||
+      !hipck(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "hipStreamCreate") ||
+      !hipck(hipHostMalloc((void **)&c->h_pinned, 4096, hipHostMallocDefault), "hipHostMalloc") ||
+      !hipck(hipDeviceSynchronize(), "hipDeviceSynchronize")) {
+    ctx_free(c);
+    return PHOS_E_HIP;
+  }
+#undef CK
+  *out = c;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_destroy(phos_ctx *c) {
+  if (!c) return fail(PHOS_E_INVAL, "phos_destroy: NULL context");
+  DeviceGuard g(c->device);
+  for (phos_ckpt *k : c->open_ckpt) delete k;
+  delete c->open_rst;
+  return ctx_free(c);
+}
+
+extern "C" phos_status phos_buffers_register(phos_ctx *c, const phos_buffer *bufs, uint32_t n) {
+  if (!c || (!bufs && n)) return fail(PHOS_E_INVAL, "phos_buffers_register: NULL argument");
+  if (c->open_ckpt[1] || c->open_ckpt[2] || c->open_rst)
+    return fail(PHOS_E_STATE, "buffers cannot change while a checkpoint or restore is open");
+  const uint64_t end = c->pool_base + c->pool_bytes;
+  for (uint32_t i = 0; i < n; ++i) {
+    const phos_buffer &b = bufs[i];
+    if (!b.bytes || b.base % c->page_bytes || b.bytes % c->page_bytes)
+      return fail(PHOS_E_INVAL, "buffer %u is not page aligned whole pages", i);
+    if (b.base < c->pool_base || b.base + b.bytes > end || b.base + b.bytes < b.base)
+      return fail(PHOS_E_INVAL, "buffer %u lies outside the pool", i);
+    if (i && b.base < bufs[i - 1].base + bufs[i - 1].bytes)
+      return fail(PHOS_E_INVAL, "buffer %u overlaps or is out of order", i);
+  }
+  std::vector<uint32_t> page_buf(c->n_pages, kNone), img_page(c->n_pages, kNone);
+  uint64_t img = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t p0 = (uint32_t)((bufs[i].base - c->pool_base) >> c->page_shift);
+    const uint32_t np = (uint32_t)(bufs[i].bytes >> c->page_shift);
+    for (uint32_t q = 0; q < np; ++q) {
+      page_buf[p0 + q] = i;
+      img_page[p0 + q] = (uint32_t)((img >> c->page_shift) + q);
+    }
+    img += bufs[i].bytes;
+  }
+  DeviceGuard g(c->device);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(c->d_page_buf, page_buf.data(), c->n_pages * 4ull, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_img_page, img_page.data(), c->n_pages * 4ull, hipMemcpyHostToDevice));
+  c->bufs.assign(bufs, bufs + n);
+  c->image_bytes = img;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_image_bytes(phos_ctx *c, uint64_t *bytes) {
+  if (!c || !bytes) return fail(PHOS_E_INVAL, "phos_image_bytes: NULL argument");
+  *bytes = c->image_bytes;
+  return PHOS_OK;
+}
+
+// -------------------------------------------------------------- speculation
+// Index of the buffer containing v (binary search over the sorted table), or -1.
+static int64_t find_buffer(const std::vector<phos_buffer> &bufs, uint64_t v) {
+  auto it = std::upper_bound(bufs.begin(), bufs.end(), v,
+                             [](uint64_t x, const phos_buffer &b) { return x < b.base; });
+  if (it == bufs.begin()) return -1;
+  --it;
+  return (v - it->base < it->bytes) ? (int64_t)(it - bufs.begin()) : -1;
+}
+
+extern "C" phos_status phos_spec_register(phos_ctx *c, uint32_t launch_id, const phos_arg *args,
+                                          uint32_t nargs, phos_spec *out) {
+  if (!c || !out || (!args && nargs)) return fail(PHOS_E_INVAL, "phos_spec_register: NULL argument");
+  std::vector<phos_interval> iv;
+  auto add_ptr = [&](uint64_t v, uint32_t mode) {
+    const int64_t b = find_buffer(c->bufs, v);
+    if (b >= 0) iv.push_back({c->bufs[b].base, c->bufs[b].base + c->bufs[b].bytes, mode, 0});
+  };
+  for (uint32_t i = 0; i < nargs; ++i) {
+    const phos_arg &a = args[i];
+    switch (a.kind) {
+      case PHOS_ARG_SCALAR:
+        break;
+      case PHOS_ARG_PTR_CONST:
+        add_ptr(a.value, PHOS_R);
+        break;
+      case PHOS_ARG_PTR_MUT:
+        add_ptr(a.value, PHOS_R | PHOS_W);
+        break;
+      case PHOS_ARG_STRUCT: {
+        if (a.bytes && !a.host_struct) return fail(PHOS_E_INVAL, "arg %u: struct without bytes", i);
+        const uint8_t *s = (const uint8_t *)a.host_struct;
+        for (uint64_t off = 0; off + 8 <= a.bytes; off += 8) {
+          uint64_t v;
+          memcpy(&v, s + off, 8);
+          add_ptr(v, PHOS_R | PHOS_W);
+        }
+        break;
+      }
+      case PHOS_ARG_RANGE:
+        if (!(a.mode & (PHOS_R | PHOS_W)) || (a.mode & ~(PHOS_R | PHOS_W)))
+          return fail(PHOS_E_INVAL, "arg %u: range needs mode bits R and/or W", i);
+        if (a.value + a.bytes < a.value) return fail(PHOS_E_INVAL, "arg %u: range wraps", i);
+        if (a.bytes) iv.push_back({a.value, a.value + a.bytes, a.mode, 0});
+        break;
+      default:
+        return fail(PHOS_E_INVAL, "arg %u: unknown kind %u", i, a.kind);
+    }
+  }
+  std::sort(iv.begin(), iv.end(), [](const phos_interval &x, const phos_interval &y) {
+    return x.lo != y.lo ? x.lo < y.lo : x.hi < y.hi;
+  });
+  std::vector<phos_interval> merged;
+  for (const phos_interval &x : iv) {
+    if (!merged.empty() && merged.back().lo == x.lo && merged.back().hi == x.hi)
+      merged.back().mode |= x.mode;
+    else
+      merged.push_back(x);
+  }
+  if (merged.size() > kMaxIv)
+    return fail(PHOS_E_INVAL, "launch names %zu intervals (max %u)", merged.size(), kMaxIv);
+  uint32_t h;
+  if (!c->free_specs.empty()) {
+    h = c->free_specs.back();
+    c->free_specs.pop_back();
+  } else {
+    h = (uint32_t)c->specs.size();
+    c->specs.emplace_back();
+  }
+  c->specs[h].used = true;
+  c->specs[h].launch_id = launch_id;
+  c->specs[h].iv = std::move(merged);
+  *out = h;
+  return PHOS_OK;
+}
+
+static HostSpec *get_spec(phos_ctx *c, phos_spec s) {
+  if (!c || s >= c->specs.size() || !c->specs[s].used) return nullptr;
+  return &c->specs[s];
+}
+
+extern "C" phos_status phos_spec_intervals(phos_ctx *c, phos_spec s, phos_interval *out,
+                                           uint32_t cap, uint32_t *n) {
+  HostSpec *h = get_spec(c, s);
+  if (!h || !n || (!out && cap)) return fail(PHOS_E_INVAL, "phos_spec_intervals: bad argument");
+  *n = (uint32_t)h->iv.size();
+  for (uint32_t i = 0; i < *n && i < cap; ++i) out[i] = h->iv[i];
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_spec_release(phos_ctx *c, phos_spec s) {
+  HostSpec *h = get_spec(c, s);
+  if (!h) return fail(PHOS_E_INVAL, "phos_spec_release: unknown spec %u", s);
+  h->used = false;
+  h->iv.clear();
+  c->free_specs.push_back(s);
+  return PHOS_OK;
+}
+
+static DevIv to_dev(const phos_interval &x) {
+  DevIv d;
+  if (x.hi >= x.lo + 8 && x.hi >= 8) {
+    d.lo = x.lo;
+    d.span = x.hi - x.lo - 8;
+  } else {
+    d.lo = ~0ull;
+    d.span = 0;
+  }
+  d.mode = x.mode;
+  d.pad = 0;
+  return d;
+}
+
+static void fill_devspec(const HostSpec &h, DevSpec *d) {
+  d->niv = (uint32_t)h.iv.size();
+  d->pad = 0;
+  for (uint32_t i = 0; i < d->niv; ++i) d->iv[i] = to_dev(h.iv[i]);
+}
+
+// -------------------------------------------------------------- validation
+static phos_status ensure_workspace(phos_ctx *c, uint64_t ntiles, uint64_t cap) {
+  if (ntiles <= c->tile_cap && cap <= c->scratch_cap) return PHOS_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  if (ntiles > c->tile_cap) {
+    uint64_t nc = std::max<uint64_t>(ntiles, c->tile_cap * 2);
+    (void)hipFree(c->d_tile_count);
+    (void)hipFree(c->d_tile_off);
+    (void)hipFree(c->d_seg_sum);
+    (void)hipFree(c->d_seg_prefix);
+    c->d_tile_count = nullptr;
+    c->d_tile_off = c->d_seg_sum = c->d_seg_prefix = nullptr;
+    c->tile_cap = c->seg_cap = 0;
+    TRY(dalloc(&c->d_tile_count, nc));
+    TRY(dalloc(&c->d_tile_off, nc));
+    const uint64_t ns = nc / kSeg + 1;
+    TRY(dalloc(&c->d_seg_sum, ns));
+    TRY(dalloc(&c->d_seg_prefix, ns));
+    HIP_TRY(hipMemset(c->d_seg_sum, 0, ns * 8));
+    c->tile_cap = nc;
+    c->seg_cap = ns;
+  }
+  if (cap > c->scratch_cap) {
+    uint64_t nc = std::max<uint64_t>(cap, c->scratch_cap * 2);
+    (void)hipFree(c->d_scratch);
+    c->d_scratch = nullptr;
+    c->scratch_cap = 0;
+    TRY(dalloc(&c->d_scratch, nc));
+    c->scratch_cap = nc;
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  return PHOS_OK;
+}
+
+static uint32_t pick_tile(uint64_t total) {
+  // Small calls: small tiles, so one launch still spreads over the GPU.
+  return total <= (8ull << 20) ? kVQuantum : 4 * kVQuantum;
+}
+
+static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
+  VArgs a;
+  memset(&a, 0, sizeof a);
+  a.flags = flags;
+  a.tile_recs = tile_recs;
+  a.pool_base = c->pool_base;
+  a.pool_bytes = c->pool_bytes;
+  a.page_shift = c->page_shift;
+  a.n_pages = c->n_pages;
+  a.page_buf = c->d_page_buf;
+  a.dirty = c->d_dirty;
+  a.victim = c->d_victim;
+  a.scratch = c->d_scratch;
+  a.scratch_cap = c->scratch_cap;
+  a.cursor = c->d_cursor;
+  a.tile_count = c->d_tile_count;
+  a.tile_off = c->d_tile_off;
+  a.seg_sum = c->d_seg_sum;
+  return a;
+}
+
+static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *single,
+                                  phos_violation *out, uint64_t cap, uint64_t *n_out,
+                                  hipStream_t s) {
+  if (c->v_evt_used) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
+  HIP_TRY(launch_validate(a, single, (a.flags & PHOS_V_TRACK) != 0, s));
+  const uint32_t nseg = (a.ntiles + kSeg - 1) / kSeg;
+  HIP_TRY(launch_vscan(c->d_seg_sum, nseg, c->d_seg_prefix, n_out, c->d_cursor, s));
+  HIP_TRY(launch_vscatter(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_seg_prefix, c->d_scratch,
+                          c->scratch_cap, out, cap, s));
+  HIP_TRY(hipEventRecord(c->v_evt, s));
+  c->v_evt_used = true;
+  return PHOS_OK;
+}
+
+static const uint32_t kFlagMask = PHOS_V_READS | PHOS_V_WRITES | PHOS_V_TRACK;
+
+extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t *d_records,
+                                     uint64_t n, uint32_t flags, phos_violation *out,
+                                     uint64_t cap, uint64_t *n_violations, hipStream_t stream) {
+  HostSpec *h = get_spec(c, spec);
+  if (!h) return fail(PHOS_E_INVAL, "phos_validate: unknown spec %u", spec);
+  if ((n && !d_records) || (cap && !out) || !n_violations || (flags & ~kFlagMask))
+    return fail(PHOS_E_INVAL, "phos_validate: bad argument");
+  if (((uintptr_t)d_records) & 7) return fail(PHOS_E_INVAL, "records must be 8-byte aligned");
+  const uint32_t tile = pick_tile(n);
+  const uint64_t ntiles = (n + tile - 1) / tile;
+  if (ntiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
+  DeviceGuard g(c->device);
+  TRY(ensure_workspace(c, ntiles, cap));
+  DevSpec ds;
+  fill_devspec(*h, &ds);
+  VArgs a = base_vargs(c, flags, tile);
+  a.launches = nullptr;
+  a.single.rec = d_records;
+  a.single.n = n;
+  a.single.launch_id = h->launch_id;
+  a.single.tile0 = 0;
+  a.nlaunch = 1;
+  a.ntiles = (uint32_t)ntiles;
+  return run_validation(c, a, &ds, out, cap, n_violations, stream);
+}
+
+extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
+                                           const uint64_t *const *d_records, const uint64_t *n,
+                                           uint32_t nlaunch, uint32_t flags, phos_violation *out,
+                                           uint64_t cap, uint64_t *n_violations,
+                                           hipStream_t stream) {
+  if (!c || (nlaunch && (!specs || !d_records || !n)) || (cap && !out) || !n_violations ||
+      (flags & ~kFlagMask))
+    return fail(PHOS_E_INVAL, "phos_validate_batch: bad argument");
+  uint64_t total = 0, total_iv = 0;
+  for (uint32_t i = 0; i < nlaunch; ++i) {
+    HostSpec *h = get_spec(c, specs[i]);
+    if (!h) return fail(PHOS_E_INVAL, "launch %u: unknown spec %u", i, specs[i]);
+    if ((n[i] && !d_records[i]) || (((uintptr_t)d_records[i]) & 7))
+      return fail(PHOS_E_INVAL, "launch %u: records NULL or misaligned", i);
+    total += n[i];
+    total_iv += h->iv.size();
+  }
+  const uint32_t tile = pick_tile(total / (nlaunch ? nlaunch : 1) * 4);
+  // host image of the descriptor table and the flat interval table
+  std::vector<uint8_t> blob(nlaunch * sizeof(VLaunch) + total_iv * sizeof(DevIv));
+  VLaunch *L = reinterpret_cast<VLaunch *>(blob.data());
+  DevIv *IV = reinterpret_cast<DevIv *>(blob.data() + nlaunch * sizeof(VLaunch));
+  uint64_t tiles = 0, ivo = 0;
+  for (uint32_t i = 0; i < nlaunch; ++i) {
+    const HostSpec &h = c->specs[specs[i]];
+    L[i].rec = d_records[i];
+    L[i].n = n[i];
+    L[i].iv_off = (uint32_t)ivo;
+    L[i].niv = (uint32_t)h.iv.size();
+    L[i].launch_id = h.launch_id;
+    L[i].tile0 = (uint32_t)tiles;
+    for (const phos_interval &x : h.iv) IV[ivo++] = to_dev(x);
+    tiles += (n[i] + tile - 1) / tile;
+  }
+  if (tiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
+  DeviceGuard g(c->device);
+  TRY(ensure_workspace(c, tiles, cap));
+  if (blob.size() > c->vbatch_cap) {
+    HIP_TRY(hipDeviceSynchronize());
+    if (c->d_vbatch) (void)hipFree(c->d_vbatch);
+    if (c->h_vstage) (void)hipHostFree(c->h_vstage);
+    c->d_vbatch = c->h_vstage = nullptr;
+    c->vbatch_cap = c->vstage_cap = 0;
+    const size_t cap2 = std::max<size_t>(blob.size(), 1 << 16) * 2;
+    uint8_t *dv = nullptr;
+    TRY(dalloc(&dv, cap2));
+    c->d_vbatch = dv;
+    if (hipHostMalloc(&c->h_vstage, cap2, hipHostMallocDefault) != hipSuccess)
+      return fail(PHOS_E_NOMEM, "hipHostMalloc(%zu)", cap2);
+    c->vbatch_cap = c->vstage_cap = cap2;
+    c->last_vbatch.clear();
+  }
+  if (c->v_evt_used) HIP_TRY(hipStreamWaitEvent(stream, c->v_evt, 0));
+  if (blob != c->last_vbatch) {
+    if (c->vstage_used) HIP_TRY(hipEventSynchronize(c->vstage_evt));
+    memcpy(c->h_vstage, blob.data(), blob.size());
+    HIP_TRY(hipMemcpyAsync(c->d_vbatch, c->h_vstage, blob.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(c->vstage_evt, stream));
+    c->vstage_used = true;
+    c->last_vbatch = std::move(blob);
+  }
+  VArgs a = base_vargs(c, flags, tile);
+  a.launches = reinterpret_cast<const VLaunch *>(c->d_vbatch);
+  a.ivs = reinterpret_cast<const DevIv *>((const uint8_t *)c->d_vbatch + nlaunch * sizeof(VLaunch));
+  a.nlaunch = nlaunch;
+  a.ntiles = (uint32_t)tiles;
+  static DevSpec unused;  // kernel parameter of the single-launch path
+  return run_validation(c, a, &unused, out, cap, n_violations, stream);
+}
+
+extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
+  if (!c) return fail(PHOS_E_INVAL, "phos_track_reset: NULL context");
+  DeviceGuard g(c->device);
+  HIP_TRY(launch_fill_u32(c->d_dirty, c->nwords, 0, s));
+  HIP_TRY(launch_fill_u32(c->d_victim, c->nwords, 0, s));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_track_read(phos_ctx *c, uint32_t which, uint32_t *host, uint64_t nw) {
+  if (!c || !host || which > 1 || nw < c->nwords)
+    return fail(PHOS_E_INVAL, "phos_track_read: bad argument");
+  DeviceGuard g(c->device);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(host, which ? c->d_victim : c->d_dirty, c->nwords * 4ull,
+                    hipMemcpyDeviceToHost));
+  return PHOS_OK;
+}
+
+// ---------------------------------------------------------------- protocols
+static phos_status ensure_slot(phos_ctx *c, Slot &s, bool with_list) {
+  if (!s.state) TRY(dalloc(&s.state, c->n_pages));
+  if (!s.counters) TRY(dalloc(&s.counters, 8));
+  if (with_list && !s.list) {
+    TRY(dalloc(&s.list, c->n_pages));
+    TRY(dalloc(&s.list_count, 1));
+  }
+  return PHOS_OK;
+}
+
+static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
+                          unsigned long long *stat) {
+  CopyArgs a;
+  a.pool = reinterpret_cast<uint8_t *>(c->pool_base);
+  a.image = image;
+  a.state = s.state;
+  a.img_page = c->d_img_page;
+  a.stat = stat;
+  a.err = c->d_err;
+  a.page_shift = c->page_shift;
+  a.n_pages = c->n_pages;
+  a.to_image = to_image ? 1u : 0u;
+  a.spin_limit = c->spin_limit;
+  return a;
+}
+
+static uint32_t chunk_pages(phos_ctx *c) {
+  // The paper's preemptible copy unit: 4 MiB (Section 5).
+  return std::max<uint32_t>(1, (4u << 20) >> c->page_shift);
+}
+
+static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
+                                    hipStream_t stream) {
+  const uint32_t cp = chunk_pages(c);
+  const uint32_t nchunks = (c->n_pages + cp - 1) / cp;
+  CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
+  HIP_TRY(launch_background(a, &s.counters[0], nchunks, cp, std::min(c->bg_grid, nchunks), stream));
+  return PHOS_OK;
+}
+
+// Pages of the intervals with any of `modes`, clamped to the pool.
+static PageRanges page_ranges(phos_ctx *c, const HostSpec &h, uint32_t modes) {
+  PageRanges r;
+  memset(&r, 0, sizeof r);
+  const uint64_t end = c->pool_base + c->pool_bytes;
+  for (const phos_interval &x : h.iv) {
+    if (!(x.mode & modes) || x.hi <= x.lo) continue;
+    const uint64_t lo = std::max(x.lo, c->pool_base), hi = std::min(x.hi, end);
+    if (hi <= lo) continue;
+    const uint32_t p0 = (uint32_t)((lo - c->pool_base) >> c->page_shift);
+    const uint32_t p1 = (uint32_t)((hi - 1 - c->pool_base) >> c->page_shift);
+    r.p0[r.n] = p0;
+    r.np[r.n] = p1 - p0 + 1;
+    r.units_prefix[r.n + 1] = r.units_prefix[r.n] + (r.np[r.n] + kUnitPages - 1) / kUnitPages;
+    ++r.n;
+  }
+  return r;
+}
+
+extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t flags, void *image,
+                                       void *host_image, hipStream_t copy, phos_ckpt **out) {
+  if (!c || !image || !out) return fail(PHOS_E_INVAL, "phos_ckpt_begin: NULL argument");
+  if (protocol != PHOS_COW && protocol != PHOS_RECOPY)
+    return fail(PHOS_E_INVAL, "unknown protocol %u", protocol);
+  if (flags & ~PHOS_CKPT_DEFER_BACKGROUND) return fail(PHOS_E_INVAL, "unknown flags 0x%x", flags);
+  if (((uintptr_t)image) & 15) return fail(PHOS_E_INVAL, "image must be 16-byte aligned");
+  if (c->open_ckpt[protocol]) return fail(PHOS_E_STATE, "a checkpoint of this protocol is open");
+  if (c->open_rst) return fail(PHOS_E_STATE, "a restore is open");
+  DeviceGuard g(c->device);
+  Slot &s = c->slots[protocol];
+  TRY(ensure_slot(c, s, protocol == PHOS_RECOPY));
+  // Quiesce point: reset per-page states, counters, and (first open
+  // checkpoint) the write-set tracking bitmaps.
+  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, copy));
+  HIP_TRY(launch_fill_u64(s.counters, 8, 0, copy));
+  if (s.list_count) HIP_TRY(launch_fill_u32(s.list_count, 1, 0, copy));
+  if (!c->open_ckpt[PHOS_COW] && !c->open_ckpt[PHOS_RECOPY]) {
+    HIP_TRY(launch_fill_u32(c->d_dirty, c->nwords, 0, copy));
+    HIP_TRY(launch_fill_u32(c->d_victim, c->nwords, 0, copy));
+  }
+  HIP_TRY(hipStreamSynchronize(copy));
+  phos_ckpt *k = new phos_ckpt;
+  k->ctx = c;
+  k->protocol = protocol;
+  k->flags = flags;
+  k->image = (uint8_t *)image;
+  k->host_image = host_image;
+  k->copy = copy;
+  k->slot = &s;
+  if (!(flags & PHOS_CKPT_DEFER_BACKGROUND)) {
+    phos_status st = start_background(c, s, k->image, true, copy);
+    if (st != PHOS_OK) {
+      delete k;
+      return st;
+    }
+    k->bg_started = true;
+  }
+  c->open_ckpt[protocol] = k;
+  *out = k;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t app) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_cow: NULL checkpoint");
+  if (k->protocol != PHOS_COW) return fail(PHOS_E_STATE, "copy-on-write needs a CoW checkpoint");
+  phos_ctx *c = k->ctx;
+  HostSpec *h = get_spec(c, spec);
+  if (!h) return fail(PHOS_E_INVAL, "phos_ckpt_cow: unknown spec %u", spec);
+  DeviceGuard g(c->device);
+  const PageRanges r = page_ranges(c, *h, PHOS_W);
+  CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
+  HIP_TRY(launch_cow(a, r, c->d_victim, c->nwords, true, app));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_recopy: NULL checkpoint");
+  if (k->protocol != PHOS_RECOPY) return fail(PHOS_E_STATE, "recopy needs a recopy checkpoint");
+  if (k->recopied) return fail(PHOS_E_STATE, "recopy already done");
+  phos_ctx *c = k->ctx;
+  DeviceGuard g(c->device);
+  Slot &s = *k->slot;
+  hipEvent_t e;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // re-quiesce: the copy stream waits for everything the application issued
+  HIP_TRY(hipEventRecord(e, app));
+  HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
+  if (!k->bg_started) {
+    TRY(start_background(c, s, k->image, true, k->copy));
+    k->bg_started = true;
+  }
+  HIP_TRY(launch_pagelist(c->d_dirty, c->d_victim, c->nwords, c->n_pages, s.list, s.list_count,
+                          k->copy));
+  CopyArgs a = copy_args(c, s, k->image, true, &s.counters[3]);
+  HIP_TRY(launch_gather_pages(a, s.list, s.list_count, c->bg_grid, k->copy));
+  // the application resumes after the recopy
+  HIP_TRY(hipEventRecord(e, k->copy));
+  HIP_TRY(hipStreamWaitEvent(app, e, 0));
+  HIP_TRY(hipEventDestroy(e));
+  k->recopied = true;
+  return PHOS_OK;
+}
+
+static phos_status read_err(phos_ctx *c, hipStream_t s, bool *timeout) {
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 8, c->d_err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *timeout = (((uint32_t *)(c->h_pinned + 8))[0] & 1u) != 0;
+  if (*timeout) HIP_TRY(hipMemsetAsync(c->d_err, 0, 4, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_stats *stats) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_end: NULL checkpoint");
+  phos_ctx *c = k->ctx;
+  DeviceGuard g(c->device);
+  Slot &s = *k->slot;
+  hipEvent_t e;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(e, app));
+  HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
+  HIP_TRY(hipEventDestroy(e));
+  if (!k->bg_started) {
+    TRY(start_background(c, s, k->image, true, k->copy));
+    k->bg_started = true;
+  }
+  if (k->host_image && c->image_bytes)
+    HIP_TRY(hipMemcpyAsync(k->host_image, k->image, c->image_bytes, hipMemcpyDeviceToHost, k->copy));
+  HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, k->copy));
+  HIP_TRY(hipStreamSynchronize(k->copy));
+  HIP_TRY(hipStreamSynchronize(app));
+  if (stats) {
+    stats->bg_pages = c->h_pinned[1];
+    stats->cow_pages = c->h_pinned[2];
+    stats->recopy_pages = c->h_pinned[3];
+    stats->image_bytes = c->image_bytes;
+  }
+  bool timeout = false;
+  TRY(read_err(c, k->copy, &timeout));
+  c->open_ckpt[k->protocol] = nullptr;
+  delete k;
+  if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the image is not valid");
+  return PHOS_OK;
+}
+
+static phos_status states_to_host(phos_ctx *c, const uint32_t *state, uint32_t *host, uint64_t nw) {
+  if (nw < c->nwords) return fail(PHOS_E_INVAL, "bitmap needs %u words", c->nwords);
+  uint32_t *tmp = nullptr;
+  TRY(dalloc(&tmp, c->nwords));
+  hipError_t e = launch_states_to_bits(state, c->n_pages, tmp, c->aux);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, c->nwords * 4ull, hipMemcpyDeviceToHost, c->aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(PHOS_E_HIP, "state readback: %s", hipGetErrorString(e));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_copied(phos_ckpt *k, uint32_t *host, uint64_t nw) {
+  if (!k || !host) return fail(PHOS_E_INVAL, "phos_ckpt_copied: NULL argument");
+  DeviceGuard g(k->ctx->device);
+  return states_to_host(k->ctx, k->slot->state, host, nw);
+}
+
+// ------------------------------------------------------------------ restore
+extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const void *image,
+                                          hipStream_t copy, phos_rst **out) {
+  if (!c || !image || !out) return fail(PHOS_E_INVAL, "phos_restore_begin: NULL argument");
+  if (flags & ~(PHOS_RST_DEFER_BACKGROUND | PHOS_RST_PREFETCH_SPEC))
+    return fail(PHOS_E_INVAL, "unknown flags 0x%x", flags);
+  if (((uintptr_t)image) & 15) return fail(PHOS_E_INVAL, "image must be 16-byte aligned");
+  if (c->open_rst) return fail(PHOS_E_STATE, "a restore is already open");
+  if (c->open_ckpt[1] || c->open_ckpt[2]) return fail(PHOS_E_STATE, "a checkpoint is open");
+  DeviceGuard g(c->device);
+  Slot &s = c->slots[0];
+  TRY(ensure_slot(c, s, false));
+  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, copy));
+  HIP_TRY(launch_fill_u64(s.counters, 8, 0, copy));
+  HIP_TRY(hipStreamSynchronize(copy));
+  phos_rst *r = new phos_rst;
+  r->ctx = c;
+  r->flags = flags;
+  r->image = (const uint8_t *)image;
+  r->copy = copy;
+  r->slot = &s;
+  if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
+    phos_status st = start_background(c, s, const_cast<uint8_t *>(r->image), false, copy);
+    if (st != PHOS_OK) {
+      delete r;
+      return st;
+    }
+    r->bg_started = true;
+  }
+  c->open_rst = r;
+  *out = r;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const uint64_t *d_records,
+                                              uint64_t n, hipStream_t app, uint64_t *d_faulted) {
+  if (!r || (n && !d_records)) return fail(PHOS_E_INVAL, "phos_restore_on_demand: bad argument");
+  if (((uintptr_t)d_records) & 7) return fail(PHOS_E_INVAL, "records must be 8-byte aligned");
+  phos_ctx *c = r->ctx;
+  HostSpec *h = get_spec(c, spec);
+  if (!h) return fail(PHOS_E_INVAL, "phos_restore_on_demand: unknown spec %u", spec);
+  DeviceGuard g(c->device);
+  Slot &s = *r->slot;
+  uint8_t *img = const_cast<uint8_t *>(r->image);
+  if (r->flags & PHOS_RST_PREFETCH_SPEC) {
+    const PageRanges pr = page_ranges(c, *h, PHOS_R | PHOS_W);
+    CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
+    HIP_TRY(launch_cow(a, pr, nullptr, 0, true, app));
+  }
+  CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
+  HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, app));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_restore_present(phos_rst *r, uint32_t *host, uint64_t nw) {
+  if (!r || !host) return fail(PHOS_E_INVAL, "phos_restore_present: NULL argument");
+  DeviceGuard g(r->ctx->device);
+  return states_to_host(r->ctx, r->slot->state, host, nw);
+}
+
+extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_stats *stats) {
+  if (!r) return fail(PHOS_E_INVAL, "phos_restore_end: NULL restore");
+  phos_ctx *c = r->ctx;
+  DeviceGuard g(c->device);
+  Slot &s = *r->slot;
+  hipEvent_t e;
+  HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(e, app));
+  HIP_TRY(hipStreamWaitEvent(r->copy, e, 0));
+  HIP_TRY(hipEventDestroy(e));
+  if (!r->bg_started) {
+    TRY(start_background(c, s, const_cast<uint8_t *>(r->image), false, r->copy));
+    r->bg_started = true;
+  }
+  HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, r->copy));
+  HIP_TRY(hipStreamSynchronize(r->copy));
+  HIP_TRY(hipStreamSynchronize(app));
+  if (stats) {
+    stats->bg_pages = c->h_pinned[1];
+    stats->demand_pages = c->h_pinned[2];
+  }
+  bool timeout = false;
+  TRY(read_err(c, r->copy, &timeout));
+  c->open_rst = nullptr;
+  delete r;
+  if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the pool is not valid");
+  return PHOS_OK;
+}

@@ -1,0 +1,809 @@
+"""Benchmark of the validated-speculation checkpoint hot path on one MI355X.
+
+Default workload — the training-step configuration: a 16 GiB pool of 2,000
+buffers (12 layers of bf16 4096x4096 / 4096x14336 weights with fp32 Adam
+moments, 80 activations, 1,848 small buffers), 64 KiB pages, and a step of
+1,000 launches x 1,000,000 accesses (1e9 validated addresses).  One step:
+
+  * open a soft copy-on-write checkpoint (image A, frozen at the step start)
+    and a soft recopy checkpoint (image B, taken at the step end), both with
+    their background copies on one copy stream;
+  * for every launch: validate its access stream (with dirty / victim
+    tracking), copy-on-write of the pages it may write, then the application's
+    launch itself (its writes) — the loop is captured once as a HIP graph;
+  * re-quiesce, recopy the dirty and victim pages into B, close both.
+
+The JSON line's value is the step's snapshot rate: bytes written into the two
+images per second of step time (inputs resident in HBM).  The roofline object
+covers the dominant kernel (the background copy); `cpu_baseline` times the
+CPU oracle on a bounded sample of the same step.
+
+  python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--config 2]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP event pair on a given stream; elapsed ms after synchronization."""
+
+    def __init__(self, torch, stream):
+        self.s = stream
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e1 = torch.cuda.Event(enable_timing=True)
+
+    def start(self):
+        self.e0.record(self.s)
+
+    def stop(self):
+        self.e1.record(self.s)
+
+    def ms(self):
+        return self.e0.elapsed_time(self.e1)
+
+
+class HipGraph:
+    """Stream capture of a launch-bound loop into a HIP graph (ctypes on the HIP
+    runtime): captured once, replayed every step."""
+
+    def __init__(self):
+        import ctypes
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.graph = ctypes.c_void_p()
+        self.exec = ctypes.c_void_p()
+
+    def _ok(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what}: hipError {rc}")
+
+    def capture(self, stream, fn):
+        h = self.hip
+        sp = self.ct.c_void_p(stream.cuda_stream)
+        # relaxed capture mode (2): other streams keep running their copies
+        self._ok(h.hipStreamBeginCapture(sp, 2), "hipStreamBeginCapture")
+        try:
+            fn()
+        finally:
+            self._ok(h.hipStreamEndCapture(sp, self.ct.byref(self.graph)), "hipStreamEndCapture")
+        self._ok(h.hipGraphInstantiate(self.ct.byref(self.exec), self.graph, None, None, 0),
+                 "hipGraphInstantiate")
+
+    def launch(self, stream):
+        self._ok(self.hip.hipGraphLaunch(self.exec, self.ct.c_void_p(stream.cuda_stream)),
+                 "hipGraphLaunch")
+
+    def close(self):
+        if self.exec:
+            self.hip.hipGraphExecDestroy(self.exec)
+        if self.graph:
+            self.hip.hipGraphDestroy(self.graph)
+
+
+def copy_roofs(torch, phos, nbytes=4 << 30, reps=5):
+    """Practical HBM copy roofs on this GPU: the runtime's device-to-device copy
+    and one contiguous segment through the persistent batch kernel
+    (GB/s of HBM traffic = 2 x bytes copied / time)."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(7)
+    s = torch.cuda.Stream()
+    t = Timer(torch, s)
+    out = {}
+    with torch.cuda.stream(s):
+        ts = []
+        for _ in range(reps):
+            t.start()
+            dst.copy_(src)
+            t.stop()
+            s.synchronize()
+            ts.append(t.ms())
+    out["runtime_d2d_GBps"] = round(2 * nbytes / (np.median(ts[1:]) / 1e3) / 1e9, 1)
+    seg = np.zeros(1, dtype=phos.SEG_DTYPE)
+    seg[0] = (src.data_ptr(), dst.data_ptr(), nbytes, 0, 0)
+    b = phos.phos_batch_create(0, 1, 1)
+    phos.phos_batch_load(b, seg, s)
+    ts = []
+    for _ in range(reps):
+        t.start()
+        phos.phos_batch_run(b, s)
+        t.stop()
+        s.synchronize()
+        ts.append(t.ms())
+    phos.phos_batch_destroy(b)
+    out["batch_kernel_contiguous_GBps"] = round(2 * nbytes / (np.median(ts[1:]) / 1e3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+_pinned_keep = []
+
+
+def pinned_tensor(torch, nbytes):
+    """Exactly nbytes of pinned host memory (hipHostMalloc), as a CPU uint8 tensor
+    (torch's pinned allocator rounds sizes up to a power of two)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    p = ctypes.c_void_p()
+    rc = hip.hipHostMalloc(ctypes.byref(p), ctypes.c_size_t(nbytes), 0)
+    if rc != 0:
+        raise RuntimeError(f"hipHostMalloc({nbytes}) failed: {rc}")
+    arr = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(p.value))
+    _pinned_keep.append(p)
+    return torch.from_numpy(arr)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------- config 2
+def run_training_step(args):
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    w = synth.config2_world()
+    n_launch, n_rec = args.launches, 1_000_000
+    launches = synth.config2_launches(w, n_launch, n_rec)
+    page = w.page_bytes
+    log(f"[bench] training-step: {w.n_alloc} buffers, {w.image_bytes / 2**30:.2f} GiB image, "
+        f"{n_launch} launches x {n_rec} accesses")
+    back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    pool = back[base - back.data_ptr(): base - back.data_ptr() + w.pool_bytes]
+    synth.content_device(pool, w.seed)
+    dw = synth.DeviceWorld(w, base)
+    recs = torch.empty(n_launch * n_rec, dtype=torch.int64, device="cuda")
+    for g in range(0, n_launch, 100):
+        synth.records_device(dw, launches[g:g + 100], n_rec, out=recs[g * n_rec:(g + 100) * n_rec])
+    torch.cuda.synchronize()
+    log("[bench] inputs resident")
+
+    ctx = phos.phos_create(0, base, w.pool_bytes, page)
+    phos.phos_buffers_register(ctx, w.buffers(base))
+    nimg = phos.phos_image_bytes(ctx)
+    img_a = torch.empty(nimg, dtype=torch.uint8, device="cuda")
+    img_b = torch.empty(nimg, dtype=torch.uint8, device="cuda")
+    specs = [phos.phos_spec_register(ctx, L.k, L.arg_values(base)) for L in launches]
+    rec_ptrs = [recs.data_ptr() + j * n_rec * 8 for j in range(n_launch)]
+    cap = 4_000_000
+    vout = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+    vcnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    chunk = max(1, args.val_chunk)
+    nchunk = (n_launch + chunk - 1) // chunk
+    lcap = 2_000_000  # per-call violation capacity (the list is reused call to call)
+    lcnt = torch.zeros(nchunk, dtype=torch.int64, device="cuda")
+    app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
+    VFLAGS = phos.V_READS | phos.V_WRITES | phos.V_TRACK
+
+    t_bg_a, t_bg_b = Timer(torch, cpy), Timer(torch, cpy)
+    t_val, t_app = Timer(torch, app), Timer(torch, app)
+    t_rec = Timer(torch, cpy)
+    graph = None
+
+    def app_loop(ca):
+        for j, L in enumerate(launches):
+            if j % chunk == 0:  # validate the next `chunk` launches' access streams
+                c = j // chunk
+                sl = slice(j, min(j + chunk, n_launch))
+                phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], [n_rec] * len(specs[sl]),
+                                         VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
+            phos.phos_ckpt_cow(ca, specs[j], app)
+            synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
+
+    warm = False
+
+    def step():
+        nonlocal graph, warm
+        t_bg_a.start()
+        ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
+        t_bg_a.stop()
+        t_bg_b.start()
+        cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, 0, img_b, None, cpy)
+        t_bg_b.stop()
+        t_app.start()
+        if args.app_graph and warm:
+            if graph is None:
+                graph = HipGraph()
+                graph.capture(app, lambda: app_loop(ca))
+            graph.launch(app)
+        else:
+            app_loop(ca)
+        t_app.stop()
+        t_rec.e0.record(app)  # from the application's last launch to the recopy's end
+        phos.phos_ckpt_recopy(cb, app)
+        t_rec.stop()
+        sa = phos.phos_ckpt_end(ca, app)
+        sb = phos.phos_ckpt_end(cb, app)
+        warm = True  # later steps replay the captured loop
+        return sa, sb
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup step {i} done")
+    torch.cuda.synchronize()
+    rows = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sa, sb = step()
+        rows.append(dict(bg_a=t_bg_a.ms(), bg_b=t_bg_b.ms(), app=t_app.ms(),
+                         rec=t_rec.ms(), bg_a_pages=sa.bg_pages, cow_pages=sa.cow_pages,
+                         bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages))
+        log(f"[bench] step {i}: " + ", ".join(f"{k}={v:.3f}" if isinstance(v, float) else f"{k}={v}"
+                                             for k, v in rows[-1].items()))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1000.0 / args.steps
+    nviol = int(lcnt.sum().item())
+
+    # validation alone (no concurrent copies), with and without dirty tracking
+    alone = {}
+    for name, fl in (("track", VFLAGS), ("plain", phos.V_READS | phos.V_WRITES)):
+        tv = Timer(torch, app)
+        ts = []
+        for _ in range(4):
+            tv.start()
+            phos.phos_validate_batch(ctx, specs, rec_ptrs, [n_rec] * n_launch, fl, vout, cap, vcnt,
+                                     app)
+            tv.stop()
+            app.synchronize()
+            ts.append(tv.ms())
+        alone[name] = float(np.median(ts[1:]))
+    log(f"[bench] validation alone: track {alone['track']:.3f} ms, plain {alone['plain']:.3f} ms")
+    roofs = copy_roofs(torch, phos)
+    log(f"[bench] copy roofs: {roofs}")
+
+    # bytes written into the images per step
+    img_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"])
+                         * page for r in rows])
+    snap_gbps = img_bytes / (ms_step / 1e3) / 1e9
+    # dominant kernel: background copy (2 bytes of HBM traffic per byte copied)
+    bg_ms = np.mean([r["bg_a"] for r in rows] + [r["bg_b"] for r in rows])
+    bg_bytes = np.mean([r["bg_a_pages"] for r in rows] + [r["bg_b_pages"] for r in rows]) * page
+    bg_gbps = 2 * bg_bytes / (bg_ms / 1e3) / 1e9
+    n_addr = n_launch * n_rec
+    log(f"[bench] step {ms_step:.2f} ms; snapshot {snap_gbps:.1f} GB/s; background copy "
+        f"{bg_ms:.2f} ms = {bg_gbps:.0f} GB/s HBM; validated addr/s (batched pass alone) "
+        f"{n_addr / (alone['track'] / 1e3):.3e}")
+
+    result = {
+        "metric": "snapshot GB/s (CoW + recopy images per step time) vs HBM peak; validated addr/s",
+        "value": round(snap_gbps, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded layout, access streams and contents)",
+        "config": {"workload": "training-step: 16 GiB pool, 2000 buffers, 64 KiB pages, "
+                               f"{n_launch} launches x {n_rec} accesses, soft-CoW + recopy",
+                   "image_bytes": int(nimg), "accesses_per_step": n_addr},
+        "validated_addr_per_s": round(n_addr / (alone["track"] / 1e3), 1),
+        "validation_ms_alone": {k: round(v, 4) for k, v in alone.items()},
+        "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
+        "recopy_ms": round(float(np.mean([r["rec"] for r in rows])), 3),
+        "app_loop_graph": bool(args.app_graph),
+        "launches_per_validation_call": chunk,
+        "copy_roofs": roofs,
+        "violations_per_step": nviol,
+        "bytes_into_images_per_step": int(img_bytes),
+        "roofline": {"bound": "hbm", "kernel": "background_kernel",
+                     "achieved": round(bg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(bg_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(2 * bg_bytes),
+                     "avg_launch_ms": round(bg_ms, 4)},
+        "roofline_validate": {"bound": "hbm", "kernel": "validate_kernel (+scan, scatter), alone",
+                              "achieved": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6, 1),
+                              "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                              "frac": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6
+                                            / HBM_PEAK_GBPS, 4)},
+    }
+    if graph is not None:
+        graph.close()
+    phos.phos_destroy(ctx)
+    del recs, img_a, img_b, back
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_training_step(w, launches, base, img_bytes, n_addr)
+    return result
+
+
+# ---------------------------------------------------------------- config 3
+def run_batched(args):
+    """64 simultaneous checkpoint requests (images 100 MiB .. 8 GiB, 50..5000
+    buffers, 5..60 % dirty at 64 KiB pages): every dirty run copied into
+    compact per-request deltas by one persistent graph-captured launch with the
+    autotuned chunk and grid, against 64 plain per-request launches."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    page = 64 << 10
+    reqs = synth.config3_requests()
+    src_bytes = sum(q.pages for q in reqs) * page
+    dst_bytes = sum(q.dirty_pages for q in reqs) * page
+    seed = synth.CFG_SEED + 3
+    log(f"[bench] batched: {len(reqs)} requests, sources {src_bytes / 2**30:.1f} GiB, "
+        f"deltas {dst_bytes / 2**30:.1f} GiB")
+    src = torch.empty(src_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(dst_bytes, dtype=torch.uint8, device="cuda")
+    synth.content_device(src, seed)
+    torch.cuda.synchronize()
+    segs = synth.request_segments(reqs, src.data_ptr(), dst.data_ptr(), page)
+    s = torch.cuda.Stream()
+    # autotune on another seed's requests (a quarter of the count), same arenas
+    treqs = [q for q in synth.batch_requests(seed + 100, 16, 100 << 20, 8 << 30, page)]
+    acc_s = acc_d = 0
+    fit = []
+    for q in treqs:
+        if acc_s + q.pages * page <= src_bytes and acc_d + q.dirty_pages * page <= dst_bytes:
+            q.src_off, q.dst_off = acc_s, acc_d
+            acc_s += q.pages * page
+            acc_d += q.dirty_pages * page
+            fit.append(q)
+    tsegs = synth.request_segments(fit, src.data_ptr(), dst.data_ptr(), page)
+    cache = os.path.join(ROOT, "paper_2405_12079_amd", "tune_cache.txt")
+    t0 = time.perf_counter()
+    cfg, tune_ms = phos.phos_batch_tune(0, tsegs, cache)
+    log(f"[bench] tuned in {time.perf_counter() - t0:.1f} s: chunk {cfg.chunk_bytes >> 10} KiB, "
+        f"{cfg.wg_per_cu} WG/CU, {cfg.threads} threads ({tune_ms:.2f} ms on the tuning set)")
+    b = phos.phos_batch_create(0, len(segs), len(reqs), cfg)
+    phos.phos_batch_load(b, segs, s)
+    lists = [phos.phos_seglist_create(0, synth.request_segments([q], src.data_ptr(), dst.data_ptr(),
+                                                               page)) for q in reqs]
+    tb = Timer(torch, s)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(reqs) + 1)]
+    batched, plain, plain_done, bdone = [], [], [], []
+    for i in range(args.warmup + args.steps):
+        tb.start()
+        phos.phos_batch_run(b, s)
+        tb.stop()
+        s.synchronize()
+        ev[0].record(s)
+        for j, l in enumerate(lists):
+            phos.phos_copy_plain(l, cfg.chunk_bytes, cfg.threads, s)
+            ev[j + 1].record(s)
+        s.synchronize()
+        if i >= args.warmup:
+            batched.append(tb.ms())
+            bdone.append(phos.phos_batch_times(b, len(reqs)))
+            fin = [ev[0].elapsed_time(ev[j + 1]) for j in range(len(reqs))]
+            plain.append(fin[-1])
+            plain_done.append(fin)
+        log(f"[bench] step {i}: batched {tb.ms():.2f} ms, plain {ev[0].elapsed_time(ev[-1]):.2f} ms")
+    # parity: sampled pages of every request against the generator's contents
+    torch.cuda.synchronize()
+    phos.phos_batch_run(b, s)
+    s.synchronize()
+    rng = np.random.default_rng(1)
+    checked = 0
+    for q in reqs:
+        allp = np.concatenate([np.arange(st, st + ln) for st, ln in zip(q.dirty_start, q.dirty_len)])
+        for j in sorted({0, q.dirty_pages - 1, int(rng.integers(q.dirty_pages))}):
+            # page j of the delta is the j-th dirty page of the source
+            want = synth.content_host(seed, q.src_off + int(allp[j]) * page, page)
+            got = dst[q.dst_off + j * page: q.dst_off + (j + 1) * page].cpu().numpy()
+            assert np.array_equal(got, want), f"request {q.r} delta page {j}"
+            checked += 1
+    bt = float(np.median(batched))
+    pt = float(np.median(plain))
+    fin = np.median(np.array(plain_done), axis=0)
+    bfin = np.median(np.array(bdone), axis=0)  # GPU wall-clock completion stamps
+    res = {
+        "metric": "snapshot GB/s vs HBM peak (batched persistent copy); p99 request latency "
+                  "batched vs plain",
+        "value": round(dst_bytes / (bt / 1e3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(bt, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded request sizes, buffer shares, dirty sets, contents)",
+        "config": {"workload": "batched-uneven: 64 checkpoint requests, images 100 MiB-8 GiB, "
+                               "50-5000 buffers, 5-60 % dirty, 64 KiB pages",
+                   "copied_bytes": int(dst_bytes), "segments": int(len(segs))},
+        "batched_ms": round(bt, 3), "plain_ms": round(pt, 3),
+        "plain_GBps": round(dst_bytes / (pt / 1e3) / 1e9, 2),
+        "latency_ms": {"batched_p50": round(float(np.percentile(bfin, 50)), 3),
+                       "batched_p99": round(float(np.percentile(bfin, 99)), 3),
+                       "plain_p50": round(float(np.percentile(fin, 50)), 3),
+                       "plain_p99": round(float(np.percentile(fin, 99)), 3)},
+        "tuned": {"chunk_bytes": cfg.chunk_bytes, "wg_per_cu": cfg.wg_per_cu,
+                  "threads": cfg.threads},
+        "roofline": {"bound": "hbm", "kernel": "batch_copy_kernel",
+                     "achieved": round(2 * dst_bytes / (bt / 1e3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(2 * dst_bytes / (bt / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": int(2 * dst_bytes),
+                     "avg_launch_ms": round(bt, 4)},
+        "parity": f"{checked} sampled delta pages byte-equal to the generator's source pages",
+    }
+    for l in lists:
+        phos.phos_seglist_destroy(l)
+    phos.phos_batch_destroy(b)
+    if not args.no_cpu_baseline:
+        # oracle gather on a bounded sample: 2 GiB of one request's dirty runs
+        q = max(reqs, key=lambda x: x.dirty_pages)
+        nb = min(q.dirty_pages, (2 << 30) // page)
+        runs_s, runs_l, acc = [], [], 0
+        for st, ln in zip(q.dirty_start, q.dirty_len):
+            take = min(int(ln), nb - acc)
+            if take <= 0:
+                break
+            runs_s.append(int(st))
+            runs_l.append(take)
+            acc += take
+        span = (runs_s[-1] + runs_l[-1]) * page
+        srch = synth.content_host(seed, q.src_off, span)
+        out = np.empty(acc * page, np.uint8)
+        so = np.array(runs_s, np.uint64) * np.uint64(page)
+        ln = np.array(runs_l, np.uint64) * np.uint64(page)
+        do = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
+        t0 = time.perf_counter()
+        oracle.gather(srch, out, so, do, ln)
+        tg = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(acc * page / tg / 1e9, 3), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"gather of {acc * page / 2**30:.2f} GiB of request "
+                                         f"{q.r}'s dirty runs", "cpu": cpu_model()}
+    return res
+
+
+# ---------------------------------------------------------------- config 5
+def run_cold_start(args):
+    """Cold-start restore at scale: a 70 GiB image of 500 buffers (16..512 MiB)
+    in pinned host memory is restored into a fresh 70 GiB pool while a
+    decode-like stream of 40,000 launches (2..6 buffers, 262,144 accesses
+    each) runs; each launch first brings in the pages its accesses touch
+    (validation in restore mode), the rest arrives in the background."""
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    w = synth.config5_world()
+    n_launch, n_rec = args.launches5, 262_144
+    page = w.page_bytes
+    launches = synth.config5_launches(w, n_launch, n_rec)
+    log(f"[bench] cold-start: {w.n_alloc} buffers, image {w.image_bytes / 2**30:.1f} GiB, "
+        f"{n_launch} launches x {n_rec} accesses")
+    back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    pool = back[base - back.data_ptr(): base - back.data_ptr() + w.pool_bytes]
+    dw = synth.DeviceWorld(w, base)
+    recs = torch.empty(n_launch * n_rec, dtype=torch.int64, device="cuda")
+    for g in range(0, n_launch, 2000):
+        grp = launches[g:g + 2000]
+        synth.records_device(dw, grp, n_rec, out=recs[g * n_rec:(g + len(grp)) * n_rec])
+    # the image: the pool's initial contents, buffer by buffer, in pinned host memory
+    t0 = time.perf_counter()
+    himg = pinned_tensor(torch, w.image_bytes)
+    log(f"[bench] pinned {w.image_bytes / 2**30:.1f} GiB in {time.perf_counter() - t0:.1f} s")
+    synth.content_device(pool, w.seed)
+    torch.cuda.synchronize()
+    off = 0
+    for o, b in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
+        himg[off:off + b].copy_(pool[o:o + b])
+        off += b
+    torch.cuda.synchronize()
+    ctx = phos.phos_create(0, base, w.pool_bytes, page)
+    phos.phos_buffers_register(ctx, w.buffers(base))
+    specs = [phos.phos_spec_register(ctx, L.k, L.arg_values(base)) for L in launches]
+    app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
+
+    # stop-the-world reference: the whole image copied in before launch 0
+    pool.zero_()
+    torch.cuda.synchronize()
+    t_stw = Timer(torch, app)
+    t_stw.start()
+    with torch.cuda.stream(app):
+        off = 0
+        for o, b in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
+            pool[o:o + b].copy_(himg[off:off + b], non_blocking=True)
+            off += b
+    t_stw.stop()
+    app.synchronize()
+    stw_ms = t_stw.ms()
+    log(f"[bench] stop-the-world restore: {stw_ms:.1f} ms ({w.image_bytes / stw_ms / 1e6:.1f} GB/s)")
+
+    # concurrent restore
+    pool.zero_()
+    torch.cuda.synchronize()
+    e_begin = torch.cuda.Event(enable_timing=True)
+    e_bg = torch.cuda.Event(enable_timing=True)
+    e_end = torch.cuda.Event(enable_timing=True)
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
+    faulted = torch.zeros(1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e_begin.record(app)
+    cpy.wait_event(e_begin)
+    rs = phos.phos_restore_begin(ctx, 0, himg, cpy)
+    e_bg.record(cpy)
+    for j, L in enumerate(launches):
+        r = recs.data_ptr() + j * n_rec * 8
+        ev0[j].record(app)
+        phos.phos_restore_on_demand(rs, specs[j], r, n_rec, app, faulted)
+        ev1[j].record(app)
+        synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, r, n_rec, app)
+    e_end.record(app)
+    st = phos.phos_restore_end(rs, app)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ttfk = e_begin.elapsed_time(ev1[0])
+    full = e_begin.elapsed_time(e_bg)
+    stream_ms = e_begin.elapsed_time(e_end)
+    stalls = np.array([ev0[j].elapsed_time(ev1[j]) for j in range(n_launch)])
+    h2d = w.image_bytes / (max(full, stream_ms) / 1e3) / 1e9
+    log(f"[bench] time to first kernel {ttfk:.2f} ms; fully present {full:.1f} ms; stream "
+        f"{stream_ms:.1f} ms; demand pages {st.demand_pages}, background {st.bg_pages}; "
+        f"stall p50 {np.percentile(stalls, 50) * 1e3:.1f} us p99 {np.percentile(stalls, 99) * 1e3:.1f} us")
+    res = {
+        "metric": "cold-start restore: time-to-first-kernel; PCIe GB/s of the concurrent restore",
+        "value": round(ttfk, 3), "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(stream_ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded layout, decode-like access streams, contents)",
+        "config": {"workload": "cold-start: 70 GiB image of 500 buffers in pinned host memory, "
+                               f"{n_launch} launches x {n_rec} accesses, 64 KiB pages",
+                   "image_bytes": int(w.image_bytes)},
+        "time_to_first_kernel_ms": round(ttfk, 3),
+        "stop_the_world_restore_ms": round(stw_ms, 3),
+        "fully_present_ms": round(full, 3),
+        "stream_ms": round(stream_ms, 3), "wall_s": round(wall, 3),
+        "restore_h2d_GBps": round(h2d, 2),
+        "stop_the_world_h2d_GBps": round(w.image_bytes / stw_ms / 1e6, 2),
+        "demand_pages": int(st.demand_pages), "background_pages": int(st.bg_pages),
+        "stall_ms": {"p50": round(float(np.percentile(stalls, 50)), 4),
+                     "p99": round(float(np.percentile(stalls, 99)), 4),
+                     "max": round(float(stalls.max()), 3)},
+    }
+    if args.parity:
+        # restore + launches == stop-the-world restore + the same launches (Section 6)
+        ref_back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+        rbase = (ref_back.data_ptr() + page - 1) // page * page
+        ref = ref_back[rbase - ref_back.data_ptr(): rbase - ref_back.data_ptr() + w.pool_bytes]
+        off = 0
+        for o, b in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
+            ref[o:o + b].copy_(himg[off:off + b])
+            off += b
+        # the same launches' writes, addressed into the reference pool
+        for j, L in enumerate(launches):
+            r = recs[j * n_rec:(j + 1) * n_rec]
+            shifted = r + (rbase - base)  # same offsets, other pool; bit 0 (write) unchanged
+            synth.apply_writes_device(rbase, rbase, w.pool_bytes, w.seed, L.k, shifted.data_ptr(),
+                                      n_rec, None)
+            if j % 2000 == 1999:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        same = all(torch.equal(pool[o:o + b], ref[o:o + b])
+                   for o, b in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()))
+        res["parity"] = ("restored pool + launches byte-equal to a stop-the-world restore + the "
+                         f"same launches over all {w.n_alloc} buffers: {same}")
+        assert same, "cold-start restore differs from stop-the-world restore"
+        del ref_back
+    phos.phos_destroy(ctx)
+    return res
+
+
+# ---------------------------------------------------------------- config 4
+def serving_inputs(torch, phos, synth, trace, page, src_base, seed):
+    """Marshal a serving trace: segment arrays for checkpoints / restores, device
+    access records and seeded present-page claim words for bursts."""
+    keep, bursts = [], []
+    arr = (phos.phos_serve_req * max(1, len(trace)))()
+    for j, q in enumerate(trace):
+        R = arr[j]
+        R.arrival_s, R.type, R.bytes = q.arrival_s, q.type, q.size
+        if q.type == synth.REQ_BURST:
+            w = synth.burst_world(q, page)
+            L = synth.burst_launch(q, w)
+            rec = synth.records_device(synth.DeviceWorld(w, 0), [L], q.n_rec)
+            state = torch.empty(q.size // page, dtype=torch.int32, device="cuda")
+            synth.present_device(state, seed, q.r)
+            R.d_records, R.nrec = rec.data_ptr(), q.n_rec
+            R.d_state, R.image = state.data_ptr(), src_base + q.src_off
+            keep += [rec, state]
+            bursts.append((q, state))
+            continue
+        if q.type == synth.REQ_CKPT:
+            st, ln = q.runs
+        else:
+            st, ln = np.zeros(1, np.int64), np.array([q.size // page], np.int64)
+        segs = np.zeros(len(st), dtype=phos.SEG_DTYPE)
+        segs["src"] = np.uint64(src_base + q.src_off) + st.astype(np.uint64) * np.uint64(page)
+        segs["dst"] = st.astype(np.uint64) * np.uint64(page)
+        segs["bytes"] = ln.astype(np.uint64) * np.uint64(page)
+        keep.append(segs)
+        R.segs, R.nseg = segs.ctypes.data, len(segs)
+    torch.cuda.synchronize()
+    return arr, keep, bursts
+
+
+def reseed_bursts(torch, synth, bursts, seed):
+    for q, state in bursts:
+        synth.present_device(state, seed, q.r)
+    torch.cuda.synchronize()
+
+
+def latency_stats(trace, outs, t_from, synth):
+    res = {}
+    names = {synth.REQ_CKPT: "checkpoint", synth.REQ_RESTORE: "restore", synth.REQ_BURST: "burst"}
+    sel = [j for j, q in enumerate(trace) if q.arrival_s >= t_from]
+    for ty, name in list(names.items()) + [(None, "all")]:
+        lat = np.array([outs[j].latency_ms for j in sel if ty is None or trace[j].type == ty])
+        if lat.size:
+            res[name] = {"n": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "max_ms": round(float(lat.max()), 3)}
+    return res
+
+
+def run_serving(args):
+    """Poisson arrivals (200 req/s, 30 s after a 2 s warm-up) of checkpoint
+    (70 %), restore (20 %) and on-demand fault-burst (10 %) requests of
+    64 MiB..16 GiB, admitted against a 2e11-byte HBM budget; the same trace is
+    served by the plain FIFO path and by continuous batching."""
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    page, seed = 64 << 10, synth.CFG_SEED + 4
+    arena = 16 << 30
+    warm, dur = 2.0, args.serve_seconds
+    trace = synth.serving_trace(seed, 200.0, warm + dur, 64 << 20, 16 << 30, page, arena)
+    src = torch.empty(arena, dtype=torch.uint8, device="cuda")
+    synth.content_device(src, seed)
+    budget = 200_000_000_000 // page * page
+    dst = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    reqs, keep, bursts = serving_inputs(torch, phos, synth, trace, page, src.data_ptr(), seed)
+    cache = os.path.join(ROOT, "paper_2405_12079_amd", "tune_cache.txt")
+    bcfg = phos.phos_batch_cfg(1 << 20, 2, 512)
+    log(f"[bench] serving: {len(trace)} requests over {warm + dur:.0f} s, "
+        f"{sum(q.size for q in trace) / (warm + dur) / 2**30:.0f} GiB/s offered (request sizes)")
+    out = {}
+    for mode, name in ((phos.SERVE_PLAIN, "plain"), (phos.SERVE_BATCHED, "batched")):
+        reseed_bursts(torch, synth, bursts, seed)
+        cfg = phos.phos_serve_cfg(mode, page, budget, dst.data_ptr(), args.quantum << 20,
+                                  args.iter_mib << 20, bcfg, 0, 0)
+        outs, st = phos.phos_serve_run(0, cfg, reqs, len(trace))
+        lat = latency_stats(trace, outs, warm, synth)
+        out[name] = {"latency": lat, "wall_ms": round(st.wall_ms, 1),
+                     "GBps": round(st.bytes / (st.wall_ms / 1e3) / 1e9, 2),
+                     "copied_bytes": int(st.bytes), "iterations": int(st.iterations),
+                     "max_active": int(st.max_active)}
+        log(f"[bench] {name}: p50 {lat['all']['p50_ms']} ms, p99 {lat['all']['p99_ms']} ms, "
+            f"{out[name]['GBps']} GB/s, max active {st.max_active}, iterations {st.iterations}")
+    del keep
+    bp99, pp99 = out["batched"]["latency"]["all"]["p99_ms"], out["plain"]["latency"]["all"]["p99_ms"]
+    return {
+        "metric": "p99 C/R request latency, batched vs plain per-request path (same trace)",
+        "value": bp99, "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": out["batched"]["wall_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded Poisson trace, sizes, dirty runs, burst accesses, contents)",
+        "config": {"workload": f"serving: Poisson 200 req/s for {dur:.0f} s after {warm:.0f} s, "
+                               "70 % checkpoint / 20 % restore / 10 % fault burst, 64 MiB-16 GiB, "
+                               "2e11-byte HBM budget", "requests": len(trace),
+                   "quantum_bytes": args.quantum << 20, "iteration_bytes": args.iter_mib << 20},
+        "plain_p99_ms": pp99, "batched_p99_ms": bp99,
+        "batched": out["batched"], "plain": out["plain"],
+    }
+
+
+def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
+    """The oracle on a bounded sample of the step: validation + tracking of 100
+    launches and snapshots of 4 GiB of buffers; scaled to the step's work."""
+    import oracle
+    import synth
+    hw = synth.HostWorld(w, base)
+    table = oracle.Table.from_world(w, base)
+    sample = launches[: min(100, len(launches))]
+    t_val = 0.0
+    n_val = 0
+    npg = w.n_pages
+    dirty = np.zeros(npg, np.uint8)
+    vic = np.zeros(npg, np.uint8)
+    for L in sample:
+        rec = synth.records_host(hw, L)
+        t0 = time.perf_counter()
+        iv = oracle.spec_build(table, L.arg_values(base))
+        oracle.validate(iv, rec, table, L.k)
+        oracle.track(iv, rec, table, base, w.page_bytes, npg, dirty, vic)
+        t_val += time.perf_counter() - t0
+        n_val += rec.shape[0]
+    # snapshot sample: the first buffers up to 4 GiB, contents from the generator
+    acc, nb = 0, 0
+    while nb < w.n_alloc and acc + int(w.alloc_bytes[nb]) <= (4 << 30):
+        acc += int(w.alloc_bytes[nb])
+        nb += 1
+    span = int(w.alloc_off[nb - 1] + w.alloc_bytes[nb - 1])
+    pool = synth.content_host(w.seed, 0, span)
+    sub = oracle.Table(table.base[:nb], table.bytes[:nb])
+    t0 = time.perf_counter()
+    img = oracle.snapshot(pool, base, sub)
+    t_snap = time.perf_counter() - t0
+    del img, pool
+    addr_per_s = n_val / t_val
+    snap_bps = acc / t_snap
+    t_step = n_addr / addr_per_s + img_bytes / snap_bps
+    return {"value": round(img_bytes / t_step / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{len(sample)} launches x {sample[0].n_records} accesses validated+tracked "
+                      f"({t_val:.1f} s) and a {acc / 2**30:.1f} GiB snapshot ({t_snap:.2f} s); "
+                      "step time = all accesses / rate + image bytes / memcpy rate",
+            "validated_addr_per_s": round(addr_per_s, 1),
+            "snapshot_GBps": round(snap_bps / 1e9, 3),
+            "cpu": cpu_model()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--launches", type=int, default=1000)
+    ap.add_argument("--val-chunk", type=int, default=50,
+                    help="launches validated per batched validation call inside the step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launches5", type=int, default=40_000)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--quantum", type=int, default=256, help="MiB per request per iteration")
+    ap.add_argument("--iter-mib", type=int, default=2048, help="MiB per batched iteration")
+    ap.add_argument("--no-parity", dest="parity", action="store_false")
+    ap.add_argument("--no-app-graph", dest="app_graph", action="store_false",
+                    help="launch the per-launch copy-on-write + application loop eagerly")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the hot path is per GPU and shards by process "
+              f"(one pool per GPU), so --gpus {args.gpus} is not run.", file=sys.stderr)
+        sys.exit(2)
+    if args.config == 2:
+        res = run_training_step(args)
+    elif args.config == 3:
+        res = run_batched(args)
+    elif args.config == 4:
+        res = run_serving(args)
+    elif args.config == 5:
+        res = run_cold_start(args)
+    else:
+        sys.exit(f"unknown config {args.config}")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -277,6 +277,9 @@ phos_status phos_batch_run(phos_batch *b, hipStream_t stream);
 phos_status phos_batch_copy(phos_batch *b, const phos_copy_seg *segs, uint64_t nseg,
                             hipStream_t stream);
 phos_status phos_batch_done_bytes(phos_batch *b, uint64_t **d_done);
+/* Synchronous: completion time of requests 0..n-1 of the last run, in ms
+ * after the run started, from the GPU wall clock (-1: not completed). */
+phos_status phos_batch_times(phos_batch *b, double *ms, uint32_t n);
 phos_status phos_batch_get_cfg(phos_batch *b, phos_batch_cfg *cfg);
 /* Change the configuration (synchronizes the device and re-captures). */
 phos_status phos_batch_set_cfg(phos_batch *b, const phos_batch_cfg *cfg);
@@ -297,6 +300,66 @@ phos_status phos_copy_plain(const phos_seglist *l, uint64_t chunk_bytes, uint32_
  * distribution (log2 of total bytes, segment count and mean size). */
 phos_status phos_batch_tune(int device, const phos_copy_seg *segs, uint64_t nseg,
                             const char *cache_path, phos_batch_cfg *best, double *best_ms);
+
+/* Run the loaded queue with the plain kernel (one workgroup per chunk, no
+ * graph, no persistence) — the per-request path the batch is compared with. */
+phos_status phos_batch_run_plain(phos_batch *b, hipStream_t stream);
+
+/* ------------------------------------------------------------- serving loop */
+/* No paper analog.  Requests arrive at host-clock times, are admitted in
+ * arrival order when their destination fits in an HBM budget, and complete
+ * when their copies are done.  PHOS_SERVE_PLAIN serves one request at a time
+ * (FIFO, one launch each).  PHOS_SERVE_BATCHED is continuous batching:
+ * admitted bulk requests share each iteration (up to quantum_bytes each,
+ * iter_bytes in total, oldest first) of the persistent graph-captured copy,
+ * two iterations in flight; requests arriving meanwhile join the next
+ * iteration; bursts run at once on their own stream. */
+enum { PHOS_SERVE_PLAIN = 0, PHOS_SERVE_BATCHED = 1 };
+enum { PHOS_REQ_CKPT = 0, PHOS_REQ_RESTORE = 1, PHOS_REQ_BURST = 2 };
+
+typedef struct {
+  double arrival_s;          /* arrival, seconds after the run starts                    */
+  uint32_t type;             /* PHOS_REQ_*                                                */
+  uint32_t nseg;             /* CKPT / RESTORE: copy segments                             */
+  uint64_t bytes;            /* destination bytes to admit (page multiple)                */
+  const phos_copy_seg *segs; /* host array: src = device address, dst = byte offset into
+                                the request's destination allocation                    */
+  const uint64_t *d_records; /* BURST: device access records, addresses are offsets into
+                                the destination (offset | is_write)                      */
+  uint64_t nrec;
+  uint32_t *d_state;         /* BURST: per-page claim words (2 = already present)         */
+  uint64_t image;            /* BURST: device address of the source image of the pages    */
+} phos_serve_req;
+
+typedef struct {
+  uint32_t mode;           /* PHOS_SERVE_*                                      */
+  uint32_t page_bytes;     /* allocation and burst page size                    */
+  uint64_t budget_bytes;   /* destination budget (bytes of d_arena)             */
+  void *d_arena;           /* device memory receiving every destination         */
+  uint64_t quantum_bytes;  /* BATCHED: per request per iteration                */
+  uint64_t iter_bytes;     /* BATCHED: per iteration                            */
+  phos_batch_cfg cfg;      /* copy kernel configuration                         */
+  uint32_t keep;           /* nonzero: never reuse a destination (for checking)  */
+  uint32_t _pad;
+} phos_serve_cfg;
+
+typedef struct {
+  double admit_ms, done_ms, latency_ms; /* host clock, from the run start / arrival */
+  uint64_t dst_off;                     /* destination offset in d_arena           */
+} phos_serve_out;
+
+typedef struct {
+  double wall_ms;        /* first arrival to last completion            */
+  uint64_t bytes;        /* bytes copied (bulk segments + faulted pages) */
+  uint64_t iterations;   /* BATCHED: copy iterations launched           */
+  uint32_t max_active;   /* most requests admitted at once              */
+} phos_serve_stats;
+
+/* Serve n requests (sorted by arrival) on device; out[i] per request.
+ * Destinations are freed at completion (their bytes stay in d_arena until
+ * reused).  E_INVAL if a request cannot ever fit the budget. */
+phos_status phos_serve_run(int device, const phos_serve_cfg *cfg, const phos_serve_req *reqs,
+                           uint32_t n, phos_serve_out *out, phos_serve_stats *stats);
 
 const char *phos_last_error(void);
 

@@ -34,6 +34,9 @@ using namespace phos;
 namespace {
 // Device queue layout: [hdr 4 x u64][prefix (max_segs + 1) x u64][segs max_segs x 32 B]
 size_t queue_bytes(uint64_t max_segs) { return 8 * (4 + max_segs + 1) + 32 * max_segs; }
+size_t stage_bytes(uint64_t max_segs, uint32_t max_reqs) {
+  return queue_bytes(max_segs) + 8ull * max_reqs;
+}
 
 uint32_t cu_count(int device) {
   hipDeviceProp_t p;
@@ -90,9 +93,13 @@ struct phos_batch {
   uint64_t max_segs = 0;
   uint32_t max_reqs = 0;
   uint32_t n_cu = 256;
+  uint32_t loaded_reqs = 0;
+  uint64_t loaded_total = 0;
   phos_batch_cfg cfg{};
   uint8_t *d_queue = nullptr;
   unsigned long long *d_cursor = nullptr, *d_done = nullptr;
+  unsigned long long *d_req_total = nullptr, *d_req_time = nullptr;  // time: [0] start, [1 + r]
+  double clock_khz = 100000.0;  // GPU wall clock
   uint8_t *h_stage = nullptr;
   hipEvent_t stage_evt = nullptr;
   bool stage_used = false;
@@ -107,6 +114,8 @@ struct phos_batch {
     b.segs = reinterpret_cast<const phos_copy_seg *>(d_queue + 8 * (4 + max_segs + 1));
     b.cursor = d_cursor;
     b.done = d_done;
+    b.req_total = d_req_total;
+    b.req_time = d_req_time + 1;
     b.chunk_bytes = cfg.chunk_bytes;
     return b;
   }
@@ -159,6 +168,8 @@ extern "C" phos_status phos_batch_destroy(phos_batch *b) {
   if (b->d_queue) (void)hipFree(b->d_queue);
   if (b->d_cursor) (void)hipFree(b->d_cursor);
   if (b->d_done) (void)hipFree(b->d_done);
+  if (b->d_req_total) (void)hipFree(b->d_req_total);
+  if (b->d_req_time) (void)hipFree(b->d_req_time);
   if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->stage_evt) (void)hipEventDestroy(b->stage_evt);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -183,8 +194,16 @@ extern "C" phos_status phos_batch_create(int device, uint64_t max_segs, uint32_t
   hipError_t e = hipMalloc((void **)&b->d_queue, qb);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_cursor, 8);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_done, 8ull * max_reqs);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_req_total, 8ull * max_reqs);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_req_time, 8ull * (max_reqs + 1));
+  if (e == hipSuccess) e = hipMemset(b->d_req_total, 0xFF, 8ull * max_reqs);
+  int khz = 0;
+  if (e == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) ==
+                             hipSuccess && khz > 0)
+    b->clock_khz = khz;
   if (e == hipSuccess) e = hipMemset(b->d_queue, 0, 8 * 4);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_stage, qb, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&b->h_stage, stage_bytes(max_segs, max_reqs), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->stage_evt, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -218,8 +237,39 @@ extern "C" phos_status phos_batch_load(phos_batch *b, const phos_copy_seg *segs,
   if (nseg)
     HIP_TRY(hipMemcpyAsync(b->d_queue + seg_off, b->h_stage + seg_off, nseg * sizeof(phos_copy_seg),
                            hipMemcpyHostToDevice, stream));
+  // per-request totals (for the completion stamps)
+  unsigned long long *tot = reinterpret_cast<unsigned long long *>(b->h_stage + queue_bytes(b->max_segs));
+  for (uint64_t r = 0; r < nreq; ++r) tot[r] = 0;
+  for (uint64_t i = 0; i < nseg; ++i) tot[segs[i].req] += segs[i].bytes;
+  if (nreq)
+    HIP_TRY(hipMemcpyAsync(b->d_req_total, tot, 8 * nreq, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipEventRecord(b->stage_evt, stream));
   b->stage_used = true;
+  b->loaded_reqs = (uint32_t)nreq;
+  b->loaded_total = total;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_batch_run_plain(phos_batch *b, hipStream_t stream) {
+  if (!b) return fail(PHOS_E_INVAL, "phos_batch_run_plain: NULL");
+  DeviceGuard g(b->device);
+  const uint64_t nchunks = (b->loaded_total + b->cfg.chunk_bytes - 1) / b->cfg.chunk_bytes;
+  if (nchunks > 0x7FFFFFFFull) return fail(PHOS_E_INVAL, "too many chunks");
+  BatchQ q = b->q();
+  HIP_TRY(launch_batch_reset(q, stream));
+  HIP_TRY(launch_plain_copy(q, nchunks, b->cfg.threads, stream));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_batch_times(phos_batch *b, double *ms, uint32_t n) {
+  if (!b || (!ms && n)) return fail(PHOS_E_INVAL, "phos_batch_times: NULL");
+  if (n > b->loaded_reqs) return fail(PHOS_E_INVAL, "only %u requests loaded", b->loaded_reqs);
+  DeviceGuard g(b->device);
+  std::vector<unsigned long long> t(n + 1);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(t.data(), b->d_req_time, 8ull * (n + 1), hipMemcpyDeviceToHost));
+  for (uint32_t r = 0; r < n; ++r)
+    ms[r] = t[r + 1] ? (double)(t[r + 1] - t[0]) / b->clock_khz : -1.0;
   return PHOS_OK;
 }
 
@@ -312,6 +362,8 @@ extern "C" phos_status phos_copy_plain(const phos_seglist *l, uint64_t chunk_byt
   q.segs = reinterpret_cast<const phos_copy_seg *>(l->d_queue + 8 * (4 + l->nseg + 1));
   q.cursor = l->d_cursor;
   q.done = l->d_done;
+  q.req_total = nullptr;
+  q.req_time = nullptr;
   q.chunk_bytes = chunk_bytes;
   const uint64_t nchunks = (l->total + chunk_bytes - 1) / chunk_bytes;
   if (nchunks > 0x7FFFFFFFull) return fail(PHOS_E_INVAL, "too many chunks");

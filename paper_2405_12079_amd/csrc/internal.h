@@ -24,10 +24,11 @@ constexpr uint32_t kVQuantum = kVWaves * kVStep * kVUnroll;  // tile_recs multip
 constexpr uint32_t kWcap = 256;                  // per-wave violation list in LDS
 constexpr uint32_t kTrackWords = 8192;           // LDS dirty-bitmap words (32 KiB)
 constexpr uint32_t kSeg = 1024;                  // tiles per scan segment
+constexpr uint32_t kFuseTiles = 4096;            // calls up to this many tiles use one finish kernel
 
 // Copy kernels.
 constexpr uint32_t kCThreads = 256;
-constexpr uint32_t kUnitPages = 16;  // pages per copy-on-write work unit
+constexpr uint32_t kUnitPages = 64;  // pages per copy-on-write work unit
 
 // Interval in the form the kernel tests: an access at a is inside iff
 // (a - lo) <= span (unsigned), span = hi - lo - 8.  Empty-for-8-byte
@@ -58,7 +59,10 @@ struct VArgs {
   uint64_t pool_base, pool_bytes;
   uint32_t page_shift, n_pages;
   const uint32_t *page_buf;  // per pool page: buffer index or kNone
-  uint32_t *dirty, *victim;  // bitmaps, bit p%32 of word p/32
+  uint8_t *dirty, *victim;   // page maps: one byte per pool page (padded to 32)
+  uint32_t *vlist;           // victim pages newly marked (appended)
+  uint32_t *vmeta;           // [0] appended, [1] CoW cursor, [2] CoW exit ticket, [3] overflow
+  uint32_t vlist_cap;
   phos_violation *scratch;
   uint64_t scratch_cap;
   unsigned long long *cursor;     // scratch append cursor (reset by the scan)
@@ -78,6 +82,7 @@ struct CopyArgs {
   uint32_t page_shift, n_pages;
   uint32_t to_image;           // 1: pool -> image (checkpoint); 0: image -> pool (restore)
   uint32_t spin_limit;
+  uint32_t nt;                 // non-temporal page copies
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.
@@ -88,6 +93,16 @@ struct PageRanges {
   uint32_t np[kMaxIv];
 };
 
+// Victim pages for copy-on-write: the list validation appends to (and the
+// page map, scanned if the list overflowed).
+struct VictimList {
+  const uint32_t *list;
+  uint32_t *meta;  // as VArgs::vmeta; nullptr: no victim work
+  uint32_t cap;
+  const uint8_t *map;
+  uint32_t map_words;
+};
+
 // Batched-copy work queue: segments, exclusive byte prefix, a chunk cursor.
 struct BatchQ {
   const phos_copy_seg *segs;
@@ -95,6 +110,8 @@ struct BatchQ {
   const unsigned long long *hdr;          // [0] nseg, [1] total bytes, [2] requests
   unsigned long long *cursor;             // next chunk (reset before each drain)
   unsigned long long *done;               // per request: bytes copied
+  const unsigned long long *req_total;    // per request: bytes to copy (or nullptr)
+  unsigned long long *req_time;           // per request: completion stamp; [-1] = start
   uint64_t chunk_bytes;
 };
 
@@ -104,15 +121,19 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 hipError_t launch_validate(const VArgs &a, const DevSpec *single, bool track, hipStream_t s);
 hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
                         uint64_t *n_out, unsigned long long *cursor, hipStream_t s);
+hipError_t launch_vfinish(const uint32_t *tile_count, const unsigned long long *tile_off,
+                          uint32_t ntiles, const phos_violation *scratch, uint64_t scratch_cap,
+                          phos_violation *out, uint64_t cap, uint64_t *n_out,
+                          unsigned long long *cursor, unsigned long long *seg_sum, hipStream_t s);
 hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long *tile_off,
                            uint32_t ntiles, const unsigned long long *seg_prefix,
                            const phos_violation *scratch, uint64_t scratch_cap,
                            phos_violation *out, uint64_t cap, hipStream_t s);
-hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const uint32_t *victim_bits,
-                      uint32_t victim_words, bool wait, hipStream_t s);
+hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
+                      uint32_t max_grid, hipStream_t s);
 hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor, uint32_t nchunks,
                              uint32_t chunk_pages, uint32_t grid, hipStream_t s);
-hipError_t launch_pagelist(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s);
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s);
@@ -120,6 +141,8 @@ hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uin
                          unsigned long long *faulted, hipStream_t s);
 hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32_t *bits,
                                  hipStream_t s);
+hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t *bits,
+                                hipStream_t s);
 hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s);
 hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s);
 hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);

@@ -34,25 +34,47 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
   return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
 }
 
-// Set `bits` in a global bitmap word unless they are all set already (a stale
-// read only costs a redundant atomic: bits are never cleared during a pass).
-__device__ __forceinline__ void or_word(uint32_t *w, uint32_t bits) {
-  if ((ld_relaxed(w) & bits) != bits) atomicOr(w, bits);
-}
-
-// Block-cooperative 16-byte copy, four loads in flight per thread.
-__device__ __forceinline__ void block_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
-                                             uint64_t n16) {
+// Block-cooperative 16-byte copy, eight loads in flight per thread;
+// NT: non-temporal (streaming) loads and stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
+                                               uint4 *__restrict__ dst_, uint64_t n16) {
+  const u32x4 *__restrict__ src = reinterpret_cast<const u32x4 *>(src_);
+  u32x4 *__restrict__ dst = reinterpret_cast<u32x4 *>(dst_);
   const uint64_t T = blockDim.x;
   uint64_t i = threadIdx.x;
-  for (; i + 3 * T < n16; i += 4 * T) {
-    const uint4 a = src[i], b = src[i + T], c = src[i + 2 * T], d = src[i + 3 * T];
-    dst[i] = a;
-    dst[i + T] = b;
-    dst[i + 2 * T] = c;
-    dst[i + 3 * T] = d;
+  for (; i + 7 * T < n16; i += 8 * T) {
+    u32x4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = NT ? __builtin_nontemporal_load(src + i + u * T) : src[i + u * T];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (NT) __builtin_nontemporal_store(v[u], dst + i + u * T);
+      else dst[i + u * T] = v[u];
+    }
   }
   for (; i < n16; i += T) dst[i] = src[i];
+}
+__device__ __forceinline__ void block_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                             uint64_t n16, bool nt = false) {
+  if (nt) block_copy16_t<true>(src, dst, n16);
+  else block_copy16_t<false>(src, dst, n16);
+}
+
+// 32 consecutive bytes of a byte map (one per page) as a 32-bit mask.
+__device__ __forceinline__ uint32_t bytes_to_mask(const uint8_t *p) {
+  const uint4 a = *reinterpret_cast<const uint4 *>(p);
+  const uint4 b = *reinterpret_cast<const uint4 *>(p + 16);
+  const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m |= ((w[i] >> (8 * j)) & 0xFFu) ? (1u << (4 * i + j)) : 0u;
+  }
+  return m;
 }
 
 // ============================================================ validation
@@ -127,10 +149,14 @@ __device__ __forceinline__ bool check_record(const VArgs &A, const VShared &S, c
           const uint32_t base = S.seg_base[jw];
           if (base != kNone) atomicOr(&s_track[base + (page >> 5) - S.seg_fw[jw]], bit);
         } else {
-          or_word(&A.dirty[page >> 5], bit);
+          A.dirty[page] = 1;
         }
-      } else if (A.page_buf[page] != kNone) {
-        or_word(&A.victim[page >> 5], bit);
+      } else if (A.page_buf[page] != kNone && A.victim[page] == 0) {
+        // newly marked victim page (a stale read only adds a duplicate)
+        A.victim[page] = 1;
+        const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
+        if (i < A.vlist_cap) A.vlist[i] = page;
+        else A.vmeta[3] = 1;
       }
     }
   }
@@ -287,7 +313,10 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
         const uint32_t b = S.seg_base[j];
         if (b != kNone && b <= w && b >= bb) { jj = j; bb = b; }
       }
-      or_word(&A.dirty[S.seg_fw[jj] + (w - bb)], v);
+      // one plain byte store per page: the page maps need no atomics, and
+      // byte-granular stores from different L2s never clobber each other
+      const uint32_t p0 = (S.seg_fw[jj] + (w - bb)) * 32;
+      for (uint32_t bits = v; bits; bits &= bits - 1) A.dirty[p0 + __ffs(bits) - 1] = 1;
     }
   }
 
@@ -304,11 +333,10 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
     S.off = off;
   }
   __syncthreads();
-  if (wcnt == 0) return;
-
   unsigned long long start = S.off;
   for (uint32_t w = 0; w < wave; ++w) start += S.wcnt[w];
-  if (wcnt <= kWcap) {
+  if (wcnt == 0) {
+  } else if (wcnt <= kWcap) {
     for (uint32_t j = lane; j < wcnt; j += 64) {
       const uint64_t i = wbase + S.list[wave][j];
       emit_violation(A, S, R, fast, niv, i, rec[i], start + j);
@@ -330,6 +358,46 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
       cnt += __popcll(m0) + __popcll(m1);
     }
   }
+}
+
+// Small calls (at most kFuseTiles tiles): one workgroup scans the tile counts
+// and moves every tile's violations to their ordered place, then resets the
+// workspace counters.
+__global__ void __launch_bounds__(1024)
+    vfinish_kernel(const uint32_t *tile_count, const unsigned long long *tile_off, uint32_t ntiles,
+                   const phos_violation *scratch, uint64_t scratch_cap, phos_violation *out,
+                   uint64_t cap, uint64_t *n_out, unsigned long long *cursor,
+                   unsigned long long *seg_sum) {
+  __shared__ unsigned long long s[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (ntiles + 1023) / 1024;
+  const uint32_t t0 = t * per < ntiles ? t * per : ntiles;
+  const uint32_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+  unsigned long long sum = 0;
+  for (uint32_t i = t0; i < t1; ++i) sum += tile_count[i];
+  s[t] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const unsigned long long x = t >= d ? s[t - d] : 0ull;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  unsigned long long dst = s[t] - sum;
+  for (uint32_t i = t0; i < t1; ++i) {
+    const uint32_t c = tile_count[i];
+    if (c) {
+      const unsigned long long src = tile_off[i];
+      for (uint32_t j = 0; j < c; ++j)
+        if (dst + j < cap && src + j < scratch_cap) out[dst + j] = scratch[src + j];
+    }
+    dst += c;
+  }
+  if (t == 1023) {
+    *n_out = s[1023];
+    *cursor = 0;
+  }
+  for (uint32_t i = t; i < (ntiles + kSeg - 1) / kSeg; i += 1024) seg_sum[i] = 0;
 }
 
 // Exclusive scan of per-segment violation counts (one block of 1024).
@@ -393,7 +461,7 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
   uint8_t *img_p = C.image + ((uint64_t)C.img_page[p] << C.page_shift);
   const uint4 *src = reinterpret_cast<const uint4 *>(C.to_image ? pool_p : img_p);
   uint4 *dst = reinterpret_cast<uint4 *>(C.to_image ? img_p : pool_p);
-  block_copy16(src, dst, pb >> 4);
+  block_copy16(src, dst, pb >> 4, C.nt != 0);
 }
 
 // Block-collective: every thread offers at most one candidate page.  Pages
@@ -409,7 +477,11 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   __syncthreads();
   bool wait = false;
   if (cand != kNone && C.img_page[cand] != kNone) {
-    uint32_t st = ld_relaxed(&C.state[cand]);
+    // A plain (possibly L2-stale) read can only lag behind: kDone is final
+    // until the next quiesce, so "done" is trusted and anything else goes
+    // through the compare-and-swap.
+    uint32_t st = C.state[cand];
+    if (st == kClaimed) st = ld_relaxed(&C.state[cand]);
     if (st == kFree) {
       uint32_t exp = kFree;
       if (cas_u32(&C.state[cand], exp, kClaimed)) {
@@ -444,34 +516,69 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   __syncthreads();
 }
 
-// Section 4.2: units over the pages of the write intervals, then units of
-// 256 victim-bitmap words (pages hit by failing writes inside buffers).
+// Section 4.2: work units of kUnitPages pages of the write intervals, then
+// units of 2048 victim pages (pages hit by failing writes inside buffers);
+// a persistent grid strides over them and skips units already copied.
+__device__ __forceinline__ bool unit_needed(const CopyArgs &C, uint32_t cand) {
+  return __syncthreads_or(cand != kNone && C.img_page[cand] != kNone && C.state[cand] != kDone);
+}
+
 __global__ void __launch_bounds__(kCThreads)
-    cow_kernel(CopyArgs C, PageRanges R, const uint32_t *victim_bits, uint32_t victim_words,
-               uint32_t wait) {
-  const uint32_t unit = blockIdx.x;
+    cow_kernel(CopyArgs C, PageRanges R, VictimList V, uint32_t wait) {
   const uint32_t t = threadIdx.x;
   const uint32_t range_units = R.units_prefix[R.n];
-  if (unit < range_units) {
-    uint32_t j = 0;
-    while (j + 1 < R.n && R.units_prefix[j + 1] <= unit) ++j;
-    const uint32_t first = (unit - R.units_prefix[j]) * kUnitPages;
-    const uint32_t cand = (t < kUnitPages && first + t < R.np[j]) ? R.p0[j] + first + t : kNone;
-    if (wait) claim_copy<true>(cand, C, nullptr);
-    else claim_copy<false>(cand, C, nullptr);
-    return;
+  // victim pages marked since the previous call: entries [start, end)
+  uint32_t start = 0, end = 0, map_units = 0;
+  if (V.meta) {
+    start = V.meta[1];
+    end = V.meta[0] < V.cap ? V.meta[0] : V.cap;
+    if (V.meta[3]) map_units = (V.map_words + kCThreads / 4 - 1) / (kCThreads / 4);  // overflowed
   }
-  const uint32_t w = (unit - range_units) * kCThreads + t;
-  uint32_t bits = (victim_bits && w < victim_words) ? victim_bits[w] : 0u;
-  while (__syncthreads_or(bits != 0u)) {
-    uint32_t cand = kNone;
-    if (bits) {
-      const uint32_t p = w * 32 + (__ffs(bits) - 1);
-      bits &= bits - 1;
-      if (p < C.n_pages) cand = p;
+  const uint32_t list_units = end > start ? (end - start + kCThreads - 1) / kCThreads : 0;
+  const uint32_t units = range_units + list_units + map_units;
+  for (uint32_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+    if (unit < range_units) {
+      uint32_t j = 0;
+      while (j + 1 < R.n && R.units_prefix[j + 1] <= unit) ++j;
+      const uint32_t first = (unit - R.units_prefix[j]) * kUnitPages;
+      const uint32_t cand = (t < kUnitPages && first + t < R.np[j]) ? R.p0[j] + first + t : kNone;
+      if (!unit_needed(C, cand)) continue;
+      if (wait) claim_copy<true>(cand, C, nullptr);
+      else claim_copy<false>(cand, C, nullptr);
+      continue;
     }
-    if (wait) claim_copy<true>(cand, C, nullptr);
-    else claim_copy<false>(cand, C, nullptr);
+    if (unit < range_units + list_units) {
+      const uint32_t e = start + (unit - range_units) * kCThreads + t;
+      const uint32_t cand = e < end ? V.list[e] : kNone;
+      if (!unit_needed(C, cand)) continue;
+      if (wait) claim_copy<true>(cand, C, nullptr);
+      else claim_copy<false>(cand, C, nullptr);
+      continue;
+    }
+    // list overflowed: scan the victim page map, 64 words of 32 pages per unit
+    const uint32_t w = (unit - range_units - list_units) * (kCThreads / 4) + t;
+    uint32_t bits = (t < kCThreads / 4 && w < V.map_words) ? bytes_to_mask(V.map + 32ull * w) : 0u;
+    for (uint32_t b = bits; b; b &= b - 1) {
+      const uint32_t p = w * 32 + (__ffs(b) - 1);
+      if (p >= C.n_pages || C.state[p] == kDone) bits &= ~(1u << (__ffs(b) - 1));
+    }
+    while (__syncthreads_or(bits != 0u)) {
+      uint32_t cand = kNone;
+      if (bits) {
+        cand = w * 32 + (__ffs(bits) - 1);
+        bits &= bits - 1;
+      }
+      if (wait) claim_copy<true>(cand, C, nullptr);
+      else claim_copy<false>(cand, C, nullptr);
+    }
+  }
+  // the last block out moves the list cursor past the entries handled here
+  if (V.meta) {
+    __syncthreads();
+    if (t == 0 && atomicAdd(&V.meta[2], 1u) == gridDim.x - 1) {
+      V.meta[1] = end;
+      V.meta[2] = 0;
+    }
   }
 }
 
@@ -494,15 +601,15 @@ __global__ void __launch_bounds__(kCThreads)
   }
 }
 
-// Section 4.3: (dirty | victim) bitmap -> page list, wave64 prefix-sum compaction.
+// Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
 __global__ void __launch_bounds__(256)
-    pagelist_kernel(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+    pagelist_kernel(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                     uint32_t *list, unsigned int *count) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   uint32_t bits = 0;
   if (w < nwords) {
-    bits = a[w] | (b ? b[w] : 0u);
+    bits = bytes_to_mask(a + 32ull * w) | (b ? bytes_to_mask(b + 32ull * w) : 0u);
     const uint64_t last = (uint64_t)w * 32 + 32;
     if (last > n_pages) bits &= (n_pages - w * 32 >= 32) ? ~0u : ((1u << (n_pages - w * 32)) - 1u);
   }
@@ -554,7 +661,7 @@ __global__ void __launch_bounds__(kCThreads)
       const uint64_t off = (rec[i] & ~7ull) - pool_base;
       if (off < pool_bytes) {
         const uint32_t p = (uint32_t)(off >> C.page_shift);
-        if (C.img_page[p] != kNone && ld_relaxed(&C.state[p]) != kDone) cand = p;
+        if (C.img_page[p] != kNone && C.state[p] != kDone) cand = p;
       }
     }
     claim_copy<true>(cand, C, faulted);
@@ -570,6 +677,11 @@ __global__ void states_to_bits_kernel(const uint32_t *state, uint32_t n_pages, u
     if (p < n_pages && state[p] == kDone) v |= 1u << b;
   }
   bits[w] = v;
+}
+
+__global__ void bytes_to_bits_kernel(const uint8_t *bytes, uint32_t nwords, uint32_t *bits) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < nwords) bits[w] = bytes_to_mask(bytes + 32ull * w);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
@@ -607,7 +719,12 @@ __device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, u
       const phos_copy_seg g = Q.segs[s];
       block_copy16(reinterpret_cast<const uint4 *>(g.src + (lo - seg_lo)),
                    reinterpret_cast<uint4 *>(g.dst + (lo - seg_lo)), (hi - lo) >> 4);
-      if (threadIdx.x == 0) atomicAdd(&Q.done[g.req], (unsigned long long)(hi - lo));
+      if (threadIdx.x == 0) {
+        const unsigned long long old = atomicAdd(&Q.done[g.req], (unsigned long long)(hi - lo));
+        // the request's last piece: stamp its completion on the GPU wall clock
+        if (Q.req_total && old + (hi - lo) == Q.req_total[g.req])
+          Q.req_time[g.req] = __builtin_amdgcn_s_memrealtime();
+      }
       pos = hi;
     }
     ++s;
@@ -616,10 +733,16 @@ __device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, u
 
 // Reset the chunk cursor and the per-request completed-byte counters.
 __global__ void batch_reset_kernel(const unsigned long long *hdr, unsigned long long *cursor,
-                                   unsigned long long *done) {
+                                   unsigned long long *done, unsigned long long *req_time) {
   const uint64_t nreq = hdr[2];
-  for (uint64_t i = threadIdx.x; i < nreq; i += blockDim.x) done[i] = 0;
-  if (threadIdx.x == 0) *cursor = 0;
+  for (uint64_t i = threadIdx.x; i < nreq; i += blockDim.x) {
+    done[i] = 0;
+    if (req_time) req_time[i + 1] = 0;
+  }
+  if (threadIdx.x == 0) {
+    *cursor = 0;
+    if (req_time) req_time[0] = __builtin_amdgcn_s_memrealtime();  // start stamp
+  }
 }
 
 // Persistent: resident blocks claim chunk_bytes pieces of the stream in order.
@@ -688,6 +811,15 @@ hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned lon
   return hipGetLastError();
 }
 
+hipError_t launch_vfinish(const uint32_t *tile_count, const unsigned long long *tile_off,
+                          uint32_t ntiles, const phos_violation *scratch, uint64_t scratch_cap,
+                          phos_violation *out, uint64_t cap, uint64_t *n_out,
+                          unsigned long long *cursor, unsigned long long *seg_sum, hipStream_t s) {
+  hipLaunchKernelGGL(vfinish_kernel, dim3(1), dim3(1024), 0, s, tile_count, tile_off, ntiles,
+                     scratch, scratch_cap, out, cap, n_out, cursor, seg_sum);
+  return hipGetLastError();
+}
+
 hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long *tile_off,
                            uint32_t ntiles, const unsigned long long *seg_prefix,
                            const phos_violation *scratch, uint64_t scratch_cap,
@@ -698,13 +830,14 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
   return hipGetLastError();
 }
 
-hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const uint32_t *victim_bits,
-                      uint32_t victim_words, bool wait, hipStream_t s) {
-  uint32_t units = r.units_prefix[r.n];
-  if (victim_bits) units += (victim_words + kCThreads - 1) / kCThreads;
+hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
+                      uint32_t max_grid, hipStream_t s) {
+  // the victim entries are only known on the device: a few extra blocks
+  // stride over them
+  uint32_t units = r.units_prefix[r.n] + (v.meta ? 8 : 0);
   if (!units) return hipSuccess;
-  hipLaunchKernelGGL(cow_kernel, dim3(units), dim3(kCThreads), 0, s, c, r, victim_bits,
-                     victim_words, wait ? 1u : 0u);
+  hipLaunchKernelGGL(cow_kernel, dim3(units < max_grid ? units : max_grid), dim3(kCThreads), 0, s,
+                     c, r, v, wait ? 1u : 0u);
   return hipGetLastError();
 }
 
@@ -716,7 +849,7 @@ hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor
   return hipGetLastError();
 }
 
-hipError_t launch_pagelist(const uint32_t *a, const uint32_t *b, uint32_t nwords, uint32_t n_pages,
+hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s) {
   if (!nwords) return hipSuccess;
   hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, nwords,
@@ -748,8 +881,17 @@ hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32
   return hipGetLastError();
 }
 
+hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t *bits,
+                                hipStream_t s) {
+  if (!nwords) return hipSuccess;
+  hipLaunchKernelGGL(bytes_to_bits_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, bytes,
+                     nwords, bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, q.hdr, q.cursor, q.done);
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, q.hdr, q.cursor, q.done,
+                     q.req_time ? q.req_time - 1 : nullptr);
   return hipGetLastError();
 }
 

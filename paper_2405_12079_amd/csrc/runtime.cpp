@@ -72,7 +72,9 @@ struct phos_ctx {
   uint32_t n_cu = 256;
 
   uint32_t *d_page_buf = nullptr, *d_img_page = nullptr;
-  uint32_t *d_dirty = nullptr, *d_victim = nullptr;
+  uint8_t *d_dirty = nullptr, *d_victim = nullptr;  // page maps, n_pages padded to 32
+  uint32_t *d_vlist = nullptr, *d_vmeta = nullptr;  // victim pages appended by validation
+  uint32_t vlist_cap = 0;
   uint32_t *d_err = nullptr;
 
   // validation workspace
@@ -86,18 +88,28 @@ struct phos_ctx {
   uint64_t seg_cap = 0;
   hipEvent_t v_evt = nullptr;
   bool v_evt_used = false;
+  hipStream_t v_stream = nullptr;  // stream of the last validation
 
-  // batch descriptors: device [VLaunch x n][DevIv x m], pinned staging
-  void *d_vbatch = nullptr;
-  size_t vbatch_cap = 0;
+  // batch descriptors ([VLaunch x n][DevIv x m]) cached on the device by
+  // content, uploaded once through pinned staging
+  struct VBatch {
+    uint64_t hash;
+    std::vector<uint8_t> blob;
+    uint8_t *dev;
+    uint64_t last_use;
+  };
+  std::vector<VBatch> vcache;
+  uint64_t vclock = 0;
   void *h_vstage = nullptr;
   size_t vstage_cap = 0;
-  std::vector<uint8_t> last_vbatch;  // content of the last upload
   hipEvent_t vstage_evt = nullptr;
   bool vstage_used = false;
 
   std::vector<HostSpec> specs;
   std::vector<uint32_t> free_specs;
+  // workspace outgrown by a larger call: kept until destroy, because a
+  // captured graph may still hold its address
+  std::vector<void *> retired;
 
   Slot slots[3];  // [1] CoW, [2] recopy, [0] restore
   phos_ckpt *open_ckpt[3] = {nullptr, nullptr, nullptr};
@@ -106,7 +118,8 @@ struct phos_ctx {
   hipStream_t aux = nullptr;     // private stream for synchronous reads
   unsigned long long *h_pinned = nullptr;  // small pinned readback area
 
-  uint32_t bg_grid = 512, spin_limit = 1u << 24;
+  uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 24, copy_nt = 0;
+  uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
 };
 
 struct phos_ckpt {
@@ -156,9 +169,9 @@ static bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
 // ------------------------------------------------------------------ context
 static phos_status ctx_free(phos_ctx *c) {
   (void)hipDeviceSynchronize();
-  void *ptrs[] = {c->d_page_buf, c->d_img_page, c->d_dirty, c->d_victim, c->d_err, c->d_scratch,
-                  c->d_cursor, c->d_tile_count, c->d_tile_off, c->d_seg_sum, c->d_seg_prefix,
-                  c->d_vbatch};
+  void *ptrs[] = {c->d_page_buf, c->d_img_page, c->d_dirty, c->d_victim, c->d_err, c->d_vlist,
+                  c->d_vmeta, c->d_scratch,
+                  c->d_cursor, c->d_tile_count, c->d_tile_off, c->d_seg_sum, c->d_seg_prefix};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (Slot &s : c->slots) {
@@ -172,6 +185,8 @@ static phos_status ctx_free(phos_ctx *c) {
   if (c->v_evt) (void)hipEventDestroy(c->v_evt);
   if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  for (void *p : c->retired) (void)hipFree(p);
+  for (auto &e : c->vcache) (void)hipFree(e.dev);
   delete c;
   return PHOS_OK;
 }
@@ -202,7 +217,10 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = (uint32_t)prop.multiProcessorCount;
-  c->bg_grid = env_u32("PHOS_BG_GRID", 2 * c->n_cu);
+  c->bg_grid = env_u32("PHOS_BG_GRID", 4 * c->n_cu);
+  c->cow_grid = env_u32("PHOS_COW_GRID", 4 * c->n_cu);
+  c->copy_nt = env_u32("PHOS_COPY_NT", 0);
+  c->finish_tiles = env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles);
   c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
   phos_status st = PHOS_OK;
 #define CK(x)                  \
@@ -215,9 +233,12 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   } while (0)
   CK(dalloc(&c->d_page_buf, c->n_pages));
   CK(dalloc(&c->d_img_page, c->n_pages));
-  CK(dalloc(&c->d_dirty, c->nwords));
-  CK(dalloc(&c->d_victim, c->nwords));
+  CK(dalloc(&c->d_dirty, 32ull * c->nwords));
+  CK(dalloc(&c->d_victim, 32ull * c->nwords));
   CK(dalloc(&c->d_err, 1));
+  c->vlist_cap = 2 * c->n_pages + 4096;
+  CK(dalloc(&c->d_vlist, c->vlist_cap));
+  CK(dalloc(&c->d_vmeta, 4));
   c->scratch_cap = 1u << 20;
   CK(dalloc(&c->d_scratch, c->scratch_cap));
   CK(dalloc(&c->d_cursor, 1));
@@ -236,9 +257,10 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   };
   if (!hipck(hipMemset(c->d_page_buf, 0xFF, c->n_pages * 4ull), "hipMemset") ||
       !hipck(hipMemset(c->d_img_page, 0xFF, c->n_pages * 4ull), "hipMemset") ||
-      !hipck(hipMemset(c->d_dirty, 0, c->nwords * 4ull), "hipMemset") ||
-      !hipck(hipMemset(c->d_victim, 0, c->nwords * 4ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_dirty, 0, c->nwords * 32ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_victim, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_err, 0, 4), "hipMemset") ||
+      !hipck(hipMemset(c->d_vmeta, 0, 16), "hipMemset") ||
       !hipck(hipMemset(c->d_cursor, 0, 8), "hipMemset") ||
       !hipck(hipMemset(c->d_seg_sum, 0, c->seg_cap * 8), "hipMemset") ||
       !hipck(hipEventCreateWithFlags(&c->v_evt, hipEventDisableTiming), "hipEventCreate") ||
@@ -427,10 +449,10 @@ static phos_status ensure_workspace(phos_ctx *c, uint64_t ntiles, uint64_t cap) 
   HIP_TRY(hipDeviceSynchronize());
   if (ntiles > c->tile_cap) {
     uint64_t nc = std::max<uint64_t>(ntiles, c->tile_cap * 2);
-    (void)hipFree(c->d_tile_count);
-    (void)hipFree(c->d_tile_off);
-    (void)hipFree(c->d_seg_sum);
-    (void)hipFree(c->d_seg_prefix);
+    c->retired.push_back(c->d_tile_count);
+    c->retired.push_back(c->d_tile_off);
+    c->retired.push_back(c->d_seg_sum);
+    c->retired.push_back(c->d_seg_prefix);
     c->d_tile_count = nullptr;
     c->d_tile_off = c->d_seg_sum = c->d_seg_prefix = nullptr;
     c->tile_cap = c->seg_cap = 0;
@@ -445,7 +467,7 @@ static phos_status ensure_workspace(phos_ctx *c, uint64_t ntiles, uint64_t cap) 
   }
   if (cap > c->scratch_cap) {
     uint64_t nc = std::max<uint64_t>(cap, c->scratch_cap * 2);
-    (void)hipFree(c->d_scratch);
+    c->retired.push_back(c->d_scratch);
     c->d_scratch = nullptr;
     c->scratch_cap = 0;
     TRY(dalloc(&c->d_scratch, nc));
@@ -455,9 +477,12 @@ static phos_status ensure_workspace(phos_ctx *c, uint64_t ntiles, uint64_t cap) 
   return PHOS_OK;
 }
 
+// Records per workgroup tile: large tiles amortize the per-tile set-up and
+// the dirty-map flush; small calls keep >= ~512 tiles to fill the GPU.
 static uint32_t pick_tile(uint64_t total) {
-  // Small calls: small tiles, so one launch still spreads over the GPU.
-  return total <= (8ull << 20) ? kVQuantum : 4 * kVQuantum;
+  uint64_t t = kVQuantum;
+  while (t * 2 <= 16ull * kVQuantum && t * 2 * 512 <= total) t *= 2;
+  return (uint32_t)t;
 }
 
 static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
@@ -472,6 +497,9 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   a.page_buf = c->d_page_buf;
   a.dirty = c->d_dirty;
   a.victim = c->d_victim;
+  a.vlist = c->d_vlist;
+  a.vmeta = c->d_vmeta;
+  a.vlist_cap = c->vlist_cap;
   a.scratch = c->d_scratch;
   a.scratch_cap = c->scratch_cap;
   a.cursor = c->d_cursor;
@@ -481,17 +509,31 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   return a;
 }
 
+// Validations share the context's workspace, so they are serialized: a call
+// on another stream than the previous one waits for it.  Under stream
+// capture no event is used (captured validations must share one stream).
 static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *single,
                                   phos_violation *out, uint64_t cap, uint64_t *n_out,
                                   hipStream_t s) {
-  if (c->v_evt_used) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs));
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  if (!capturing && c->v_evt_used && s != c->v_stream) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
   HIP_TRY(launch_validate(a, single, (a.flags & PHOS_V_TRACK) != 0, s));
-  const uint32_t nseg = (a.ntiles + kSeg - 1) / kSeg;
-  HIP_TRY(launch_vscan(c->d_seg_sum, nseg, c->d_seg_prefix, n_out, c->d_cursor, s));
-  HIP_TRY(launch_vscatter(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_seg_prefix, c->d_scratch,
-                          c->scratch_cap, out, cap, s));
-  HIP_TRY(hipEventRecord(c->v_evt, s));
-  c->v_evt_used = true;
+  if (a.ntiles <= c->finish_tiles) {
+    HIP_TRY(launch_vfinish(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_scratch, c->scratch_cap,
+                           out, cap, n_out, c->d_cursor, c->d_seg_sum, s));
+  } else {
+    const uint32_t nseg = (a.ntiles + kSeg - 1) / kSeg;
+    HIP_TRY(launch_vscan(c->d_seg_sum, nseg, c->d_seg_prefix, n_out, c->d_cursor, s));
+    HIP_TRY(launch_vscatter(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_seg_prefix,
+                            c->d_scratch, c->scratch_cap, out, cap, s));
+  }
+  if (!capturing) {
+    HIP_TRY(hipEventRecord(c->v_evt, s));
+    c->v_evt_used = true;
+    c->v_stream = s;
+  }
   return PHOS_OK;
 }
 
@@ -540,7 +582,7 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
     total += n[i];
     total_iv += h->iv.size();
   }
-  const uint32_t tile = pick_tile(total / (nlaunch ? nlaunch : 1) * 4);
+  const uint32_t tile = pick_tile(total);
   // host image of the descriptor table and the flat interval table
   std::vector<uint8_t> blob(nlaunch * sizeof(VLaunch) + total_iv * sizeof(DevIv));
   VLaunch *L = reinterpret_cast<VLaunch *>(blob.data());
@@ -559,34 +601,52 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   }
   if (tiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
   DeviceGuard g(c->device);
-  TRY(ensure_workspace(c, tiles, cap));
-  if (blob.size() > c->vbatch_cap) {
-    HIP_TRY(hipDeviceSynchronize());
-    if (c->d_vbatch) (void)hipFree(c->d_vbatch);
-    if (c->h_vstage) (void)hipHostFree(c->h_vstage);
-    c->d_vbatch = c->h_vstage = nullptr;
-    c->vbatch_cap = c->vstage_cap = 0;
-    const size_t cap2 = std::max<size_t>(blob.size(), 1 << 16) * 2;
-    uint8_t *dv = nullptr;
-    TRY(dalloc(&dv, cap2));
-    c->d_vbatch = dv;
-    if (hipHostMalloc(&c->h_vstage, cap2, hipHostMallocDefault) != hipSuccess)
-      return fail(PHOS_E_NOMEM, "hipHostMalloc(%zu)", cap2);
-    c->vbatch_cap = c->vstage_cap = cap2;
-    c->last_vbatch.clear();
-  }
-  if (c->v_evt_used) HIP_TRY(hipStreamWaitEvent(stream, c->v_evt, 0));
-  if (blob != c->last_vbatch) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &cs));
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  if (!capturing) TRY(ensure_workspace(c, tiles, cap));
+  else if (tiles > c->tile_cap || cap > c->scratch_cap)
+    return fail(PHOS_E_STATE, "workspace must be grown by an uncaptured call first");
+  uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the descriptor blob
+  for (uint8_t b : blob) hsh = (hsh ^ b) * 1099511628211ull;
+  phos_ctx::VBatch *hit = nullptr;
+  for (auto &e : c->vcache)
+    if (e.hash == hsh && e.blob == blob) hit = &e;
+  if (!hit) {
+    if (capturing) return fail(PHOS_E_STATE, "batch descriptors must be uploaded before capture");
+    if (c->vcache.size() >= 256) {  // evict the least recently used
+      auto lru = std::min_element(c->vcache.begin(), c->vcache.end(),
+                                  [](const phos_ctx::VBatch &x, const phos_ctx::VBatch &y) {
+                                    return x.last_use < y.last_use;
+                                  });
+      c->retired.push_back(lru->dev);
+      c->vcache.erase(lru);
+    }
+    if (blob.size() > c->vstage_cap) {
+      if (c->vstage_used) HIP_TRY(hipEventSynchronize(c->vstage_evt));
+      if (c->h_vstage) (void)hipHostFree(c->h_vstage);
+      c->h_vstage = nullptr;
+      const size_t cap2 = std::max<size_t>(blob.size(), 1 << 16) * 2;
+      if (hipHostMalloc(&c->h_vstage, cap2, hipHostMallocDefault) != hipSuccess)
+        return fail(PHOS_E_NOMEM, "hipHostMalloc(%zu)", cap2);
+      c->vstage_cap = cap2;
+      c->vstage_used = false;
+    }
+    uint8_t *dev = nullptr;
+    TRY(dalloc(&dev, blob.size()));
     if (c->vstage_used) HIP_TRY(hipEventSynchronize(c->vstage_evt));
     memcpy(c->h_vstage, blob.data(), blob.size());
-    HIP_TRY(hipMemcpyAsync(c->d_vbatch, c->h_vstage, blob.size(), hipMemcpyHostToDevice, stream));
+    if (c->v_evt_used && stream != c->v_stream) HIP_TRY(hipStreamWaitEvent(stream, c->v_evt, 0));
+    HIP_TRY(hipMemcpyAsync(dev, c->h_vstage, blob.size(), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(c->vstage_evt, stream));
     c->vstage_used = true;
-    c->last_vbatch = std::move(blob);
+    c->vcache.push_back({hsh, std::move(blob), dev, 0});
+    hit = &c->vcache.back();
   }
+  hit->last_use = ++c->vclock;
   VArgs a = base_vargs(c, flags, tile);
-  a.launches = reinterpret_cast<const VLaunch *>(c->d_vbatch);
-  a.ivs = reinterpret_cast<const DevIv *>((const uint8_t *)c->d_vbatch + nlaunch * sizeof(VLaunch));
+  a.launches = reinterpret_cast<const VLaunch *>(hit->dev);
+  a.ivs = reinterpret_cast<const DevIv *>(hit->dev + nlaunch * sizeof(VLaunch));
   a.nlaunch = nlaunch;
   a.ntiles = (uint32_t)tiles;
   static DevSpec unused;  // kernel parameter of the single-launch path
@@ -596,8 +656,9 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
 extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
   if (!c) return fail(PHOS_E_INVAL, "phos_track_reset: NULL context");
   DeviceGuard g(c->device);
-  HIP_TRY(launch_fill_u32(c->d_dirty, c->nwords, 0, s));
-  HIP_TRY(launch_fill_u32(c->d_victim, c->nwords, 0, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, s));
+  HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, s));
   return PHOS_OK;
 }
 
@@ -606,8 +667,13 @@ extern "C" phos_status phos_track_read(phos_ctx *c, uint32_t which, uint32_t *ho
     return fail(PHOS_E_INVAL, "phos_track_read: bad argument");
   DeviceGuard g(c->device);
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(host, which ? c->d_victim : c->d_dirty, c->nwords * 4ull,
-                    hipMemcpyDeviceToHost));
+  uint32_t *tmp = nullptr;
+  TRY(dalloc(&tmp, c->nwords));
+  hipError_t e = launch_bytes_to_bits(which ? c->d_victim : c->d_dirty, c->nwords, tmp, c->aux);
+  if (e == hipSuccess) e = hipMemcpyAsync(host, tmp, c->nwords * 4ull, hipMemcpyDeviceToHost, c->aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(PHOS_E_HIP, "track readback: %s", hipGetErrorString(e));
   return PHOS_OK;
 }
 
@@ -635,6 +701,7 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
   a.n_pages = c->n_pages;
   a.to_image = to_image ? 1u : 0u;
   a.spin_limit = c->spin_limit;
+  a.nt = c->copy_nt;
   return a;
 }
 
@@ -685,14 +752,17 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   TRY(ensure_slot(c, s, protocol == PHOS_RECOPY));
   // Quiesce point: reset per-page states, counters, and (first open
   // checkpoint) the write-set tracking bitmaps.
-  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, copy));
-  HIP_TRY(launch_fill_u64(s.counters, 8, 0, copy));
-  if (s.list_count) HIP_TRY(launch_fill_u32(s.list_count, 1, 0, copy));
+  // (On the private stream, synchronized here, so that a second checkpoint
+  // opened beside this one does not wait for this one's background copy.)
+  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, c->aux));
+  HIP_TRY(launch_fill_u64(s.counters, 8, 0, c->aux));
+  if (s.list_count) HIP_TRY(launch_fill_u32(s.list_count, 1, 0, c->aux));
   if (!c->open_ckpt[PHOS_COW] && !c->open_ckpt[PHOS_RECOPY]) {
-    HIP_TRY(launch_fill_u32(c->d_dirty, c->nwords, 0, copy));
-    HIP_TRY(launch_fill_u32(c->d_victim, c->nwords, 0, copy));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, c->aux));
+    HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, c->aux));
+    HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, c->aux));
   }
-  HIP_TRY(hipStreamSynchronize(copy));
+  HIP_TRY(hipStreamSynchronize(c->aux));
   phos_ckpt *k = new phos_ckpt;
   k->ctx = c;
   k->protocol = protocol;
@@ -723,7 +793,8 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   DeviceGuard g(c->device);
   const PageRanges r = page_ranges(c, *h, PHOS_W);
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
-  HIP_TRY(launch_cow(a, r, c->d_victim, c->nwords, true, app));
+  const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords};
+  HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, app));
   return PHOS_OK;
 }
 
@@ -827,9 +898,9 @@ extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const voi
   DeviceGuard g(c->device);
   Slot &s = c->slots[0];
   TRY(ensure_slot(c, s, false));
-  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, copy));
-  HIP_TRY(launch_fill_u64(s.counters, 8, 0, copy));
-  HIP_TRY(hipStreamSynchronize(copy));
+  HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, c->aux));
+  HIP_TRY(launch_fill_u64(s.counters, 8, 0, c->aux));
+  HIP_TRY(hipStreamSynchronize(c->aux));
   phos_rst *r = new phos_rst;
   r->ctx = c;
   r->flags = flags;
@@ -862,7 +933,8 @@ extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const
   if (r->flags & PHOS_RST_PREFETCH_SPEC) {
     const PageRanges pr = page_ranges(c, *h, PHOS_R | PHOS_W);
     CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
-    HIP_TRY(launch_cow(a, pr, nullptr, 0, true, app));
+    const VictimList none{nullptr, nullptr, 0, nullptr, 0};
+    HIP_TRY(launch_cow(a, pr, none, true, c->cow_grid, app));
   }
   CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
   HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, app));

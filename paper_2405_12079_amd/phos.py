@@ -94,6 +94,7 @@ SIGNATURES = [
     ("phos_batch_run", [P, P]),
     ("phos_batch_copy", [P, P, U64, P]),
     ("phos_batch_done_bytes", [P, PP]),
+    ("phos_batch_times", [P, P, U32]),
     ("phos_batch_get_cfg", [P, P]),
     ("phos_batch_set_cfg", [P, P]),
     ("phos_seglist_create", [ctypes.c_int, P, U64, PP]),
@@ -323,6 +324,12 @@ def phos_batch_done_bytes(b) -> int:
     return out.value
 
 
+def phos_batch_times(b, n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    _call("phos_batch_times", b, out.ctypes.data, n)
+    return out
+
+
 def phos_batch_get_cfg(b) -> phos_batch_cfg:
     c = phos_batch_cfg()
     _call("phos_batch_get_cfg", b, ctypes.byref(c))
@@ -355,3 +362,48 @@ def phos_batch_tune(device, segs: np.ndarray, cache_path: Optional[str] = None):
     _call("phos_batch_tune", device, a.ctypes.data, a.shape[0],
           cache_path.encode() if cache_path else None, ctypes.byref(best), ctypes.byref(ms))
     return best, ms.value
+
+
+# ---------------------------------------------------------------- serving
+SERVE_PLAIN, SERVE_BATCHED = 0, 1
+REQ_CKPT, REQ_RESTORE, REQ_BURST = 0, 1, 2
+
+
+class phos_serve_req(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("type", ctypes.c_uint32), ("nseg", ctypes.c_uint32),
+                ("bytes", ctypes.c_uint64), ("segs", ctypes.c_void_p),
+                ("d_records", ctypes.c_void_p), ("nrec", ctypes.c_uint64),
+                ("d_state", ctypes.c_void_p), ("image", ctypes.c_uint64)]
+
+
+class phos_serve_cfg(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("page_bytes", ctypes.c_uint32),
+                ("budget_bytes", ctypes.c_uint64), ("d_arena", ctypes.c_void_p),
+                ("quantum_bytes", ctypes.c_uint64), ("iter_bytes", ctypes.c_uint64),
+                ("cfg", phos_batch_cfg), ("keep", ctypes.c_uint32), ("_pad", ctypes.c_uint32)]
+
+
+class phos_serve_out(ctypes.Structure):
+    _fields_ = [("admit_ms", ctypes.c_double), ("done_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("dst_off", ctypes.c_uint64)]
+
+
+class phos_serve_stats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("bytes", ctypes.c_uint64),
+                ("iterations", ctypes.c_uint64), ("max_active", ctypes.c_uint32)]
+
+
+SIGNATURES += [("phos_batch_run_plain", [P, P]),
+               ("phos_serve_run", [ctypes.c_int, P, P, U32, P, P])]
+
+
+def phos_batch_run_plain(b, stream=None) -> None:
+    _call("phos_batch_run_plain", b, _stream(stream))
+
+
+def phos_serve_run(device: int, cfg: phos_serve_cfg, reqs, n: int):
+    """reqs: ctypes array of phos_serve_req (the caller keeps segment arrays alive)."""
+    out = (phos_serve_out * max(1, n))()
+    st = phos_serve_stats()
+    _call("phos_serve_run", device, ctypes.byref(cfg), reqs, n, out, ctypes.byref(st))
+    return out, st

@@ -34,11 +34,12 @@ M64 = (1 << 64) - 1
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
 
 # stream tags shared with synth_gen.h
-T_INJ, T_KIND, T_POS, T_RW, T_POS2, T_CONTENT, T_WVAL = 1, 2, 3, 4, 5, 6, 7
+T_INJ, T_KIND, T_POS, T_RW, T_POS2, T_CONTENT, T_WVAL, T_PRESENT = 1, 2, 3, 4, 5, 6, 7, 8
 # host-only layout / launch tags
 T_L_SIZE, T_L_GAP, T_L_PERM, T_L_WSET = 16, 17, 18, 19
 T_LN, T_LB, T_LM, T_LI, T_LO, T_LS, T_LSV, T_LW = 20, 21, 22, 23, 24, 25, 26, 27
 T_R_SIZE, T_R_NBUF, T_R_SHARE, T_R_FRAC, T_R_ORDER, T_R_SCAT = 32, 33, 34, 35, 36, 37
+T_S_ARR, T_S_TYPE, T_S_SIZE, T_S_SRC, T_S_FRAC, T_S_RUNS, T_S_PARTS = 48, 49, 50, 51, 52, 53, 54
 
 # argument kinds (same meaning as the launch-argument kinds of the library)
 ARG_SCALAR, ARG_PTR_CONST, ARG_PTR_MUT, ARG_STRUCT, ARG_RANGE = 0, 1, 2, 3, 4
@@ -430,6 +431,8 @@ def host_lib():
         lib.synth_draw_host.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                         ctypes.c_uint64]
         lib.synth_draw_host.restype = ctypes.c_uint64
+        lib.synth_present_host.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                           ctypes.c_void_p]
         lib.synth_below_host.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.synth_below_host.restype = ctypes.c_uint64
         _host = lib
@@ -489,7 +492,9 @@ def dev_lib():
         lib.synth_dev_content.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, P]
         lib.synth_dev_apply_writes.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                                ctypes.c_uint32, P, ctypes.c_uint64, P]
-        for f in (lib.synth_dev_records, lib.synth_dev_content, lib.synth_dev_apply_writes):
+        lib.synth_dev_present.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, P]
+        for f in (lib.synth_dev_records, lib.synth_dev_content, lib.synth_dev_apply_writes,
+                  lib.synth_dev_present):
             f.restype = ctypes.c_int
         _dev = lib
     return _dev
@@ -547,3 +552,175 @@ def apply_writes_device(pool_ptr: int, pool_base: int, pool_bytes: int, seed: in
                         rec_ptr: int, n: int, stream=None):
     _check(dev_lib().synth_dev_apply_writes(pool_ptr, pool_base, pool_bytes, seed, k, rec_ptr, n,
                                             _sh(stream)), "synth_dev_apply_writes")
+
+
+# --------------------------------------------------------------------------
+# Batched checkpoint requests (many processes' dirty pages at once)
+# --------------------------------------------------------------------------
+@dataclass
+class Request:
+    r: int
+    pages: int            # image size in pages
+    dirty_start: np.ndarray  # run starts (pages, ascending)
+    dirty_len: np.ndarray    # run lengths (pages)
+    src_off: int = 0      # offset of the request's memory in the source arena
+    dst_off: int = 0      # offset of its delta in the destination arena
+
+    @property
+    def dirty_pages(self) -> int:
+        return int(self.dirty_len.sum())
+
+
+def request_dirty_runs(seed: int, r: int, pages: int, frac_lo: float = 0.05,
+                       frac_hi: float = 0.60) -> Tuple[np.ndarray, np.ndarray]:
+    """Dirty pages of one request: U{50..5000} buffers with log-uniform shares
+    (>= 1 page each); whole buffers in a seeded order while they fit in 0.9 f,
+    then scattered single pages up to f, f ~ U(frac_lo, frac_hi)."""
+    nb = min(pages, 50 + below(draw(seed, T_R_NBUF, r, 0), 4951))
+    rng = np.random.Generator(np.random.PCG64(draw(seed, T_R_SHARE, r, 0)))
+    raw = np.exp(rng.random(nb) * math.log(1000.0))
+    sizes = np.maximum(1, np.floor(raw / raw.sum() * (pages - nb)).astype(np.int64) + 1)
+    sizes[np.argmax(sizes)] += pages - int(sizes.sum())
+    assert sizes.min() >= 1 and int(sizes.sum()) == pages
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    f = frac_lo + (frac_hi - frac_lo) * unit(draw(seed, T_R_FRAC, r, 0))
+    target = int(f * pages)
+    dirty = np.zeros(pages, dtype=bool)
+    acc = 0
+    for b in rng.permutation(nb):
+        if acc + sizes[b] <= 0.9 * target:
+            dirty[starts[b]:starts[b] + sizes[b]] = True
+            acc += int(sizes[b])
+    free = np.flatnonzero(~dirty)
+    need = max(0, target - acc)
+    if need:
+        dirty[rng.choice(free, size=min(need, free.size), replace=False)] = True
+    d = np.concatenate([[False], dirty, [False]]).astype(np.int8)
+    edges = np.diff(d)
+    rs = np.flatnonzero(edges == 1)
+    re_ = np.flatnonzero(edges == -1)
+    return rs.astype(np.int64), (re_ - rs).astype(np.int64)
+
+
+def batch_requests(seed: int, n_req: int, lo: int, hi: int, page: int) -> List[Request]:
+    """n requests, image sizes log-uniform in [lo, hi] rounded to pages; sources
+    and compact deltas laid out back to back in two arenas."""
+    reqs, so, do = [], 0, 0
+    for r in range(n_req):
+        size = round_up(int(loguniform(draw(seed, T_R_SIZE, r, 0), lo, hi)), page)
+        pages = size // page
+        st, ln = request_dirty_runs(seed, r, pages)
+        q = Request(r, pages, st, ln, so, do)
+        so += size
+        do += q.dirty_pages * page
+        reqs.append(q)
+    return reqs
+
+
+def config3_requests(seed: int = CFG_SEED + 3, n_req: int = 64) -> List[Request]:
+    """64 checkpoint requests, images 100 MiB .. 8 GiB, 64 KiB pages."""
+    return batch_requests(seed, n_req, 100 * MiB, 8 * GiB, 64 * KiB)
+
+
+def request_segments(reqs: Sequence[Request], src_base: int, dst_base: int, page: int,
+                     req_ids: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Copy segments (src, dst, bytes, req) of the requests' dirty runs: each
+    run of the source copied, in ascending page order, into the compact delta."""
+    dt = np.dtype([("src", "<u8"), ("dst", "<u8"), ("bytes", "<u8"), ("req", "<u4"),
+                   ("_p", "<u4")])
+    parts = []
+    for j, q in enumerate(reqs):
+        n = q.dirty_start.shape[0]
+        a = np.zeros(n, dtype=dt)
+        ln = q.dirty_len.astype(np.uint64) * np.uint64(page)
+        a["src"] = np.uint64(src_base + q.src_off) + q.dirty_start.astype(np.uint64) * np.uint64(page)
+        pre = np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.uint64)
+        a["dst"] = np.uint64(dst_base + q.dst_off) + pre
+        a["bytes"] = ln
+        a["req"] = q.r if req_ids is None else req_ids[j]
+        parts.append(a)
+    return np.concatenate(parts) if parts else np.zeros(0, dtype=dt)
+
+
+def present_device(state, seed: int, r: int, stream=None):
+    """Claim words of burst r's pages: 2 (present) with p = 1/2, else 0."""
+    _check(dev_lib().synth_dev_present(state.data_ptr(), state.numel(), seed, r, _sh(stream)),
+           "synth_dev_present")
+
+
+def present_host(seed: int, r: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint8)
+    host_lib().synth_present_host(seed, r, n, out.ctypes.data)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Serving trace: Poisson arrivals of checkpoint / restore / fault-burst requests
+# --------------------------------------------------------------------------
+REQ_CKPT, REQ_RESTORE, REQ_BURST = 0, 1, 2
+
+
+@dataclass
+class ServeReq:
+    r: int
+    arrival_s: float
+    type: int
+    size: int            # bytes (page multiple)
+    src_off: int         # offset of the request's memory / image in the source arena
+    runs: Optional[Tuple[np.ndarray, np.ndarray]] = None  # checkpoint: dirty runs (pages)
+    parts: Optional[List[int]] = None                     # burst: named eighths of the region
+    n_rec: int = 0
+
+
+def serving_trace(seed: int, rate: float, duration_s: float, lo: int, hi: int, page: int,
+                  arena_bytes: int, mix=(0.7, 0.2, 0.1), burst_records: int = 65536,
+                  frac_lo: float = 0.05, frac_hi: float = 0.60) -> List[ServeReq]:
+    """Poisson arrivals (rate per second) over duration_s; sizes log-uniform in
+    [lo, hi]; checkpoints copy dirty runs (f ~ U(frac_lo, frac_hi), 16..255 runs)
+    into a resident image; restores copy the whole image into the process;
+    bursts fault in the pages their accesses touch over 1..8 eighths of the
+    region, with half the pages present beforehand."""
+    out, t, r = [], 0.0, 0
+    while True:
+        t += -math.log(1.0 - unit(draw(seed, T_S_ARR, r, 0))) / rate
+        if t > duration_s:
+            return out
+        v = unit(draw(seed, T_S_TYPE, r, 0))
+        ty = REQ_CKPT if v < mix[0] else (REQ_RESTORE if v < mix[0] + mix[1] else REQ_BURST)
+        size = round_up(int(loguniform(draw(seed, T_S_SIZE, r, 0), lo, hi)), page)
+        size = min(size, arena_bytes // page * page)
+        src_off = page * below(draw(seed, T_S_SRC, r, 0), (arena_bytes - size) // page + 1)
+        q = ServeReq(r, t, ty, size, src_off)
+        pages = size // page
+        if ty == REQ_CKPT:
+            f = frac_lo + (frac_hi - frac_lo) * unit(draw(seed, T_S_FRAC, r, 0))
+            target = max(1, int(f * pages))
+            nr = min(target, 16 + below(draw(seed, T_S_RUNS, r, 0), 240))
+            rng = np.random.Generator(np.random.PCG64(draw(seed, T_S_RUNS, r, 1)))
+            st = np.sort(rng.choice(pages, size=nr, replace=False)).astype(np.int64)
+            nxt = np.append(st[1:], pages)
+            ln = np.minimum(target // nr, nxt - st).astype(np.int64)
+            keep = ln > 0
+            q.runs = (st[keep], ln[keep])
+        elif ty == REQ_BURST:
+            k = 1 + below(draw(seed, T_S_PARTS, r, 0), 8)
+            q.parts = sorted(permutation(seed + r, T_S_PARTS, 8)[:k])
+            q.n_rec = burst_records
+        out.append(q)
+        r += 1
+
+
+def burst_world(q: ServeReq, page: int) -> World:
+    """The burst's region as a pool of 8 equal buffers (whole pages)."""
+    pages = q.size // page
+    per = max(1, pages // 8)
+    offs = [i * per * page for i in range(8)]
+    sizes = [per * page] * 7 + [(pages - 7 * per) * page]
+    keep = [i for i in range(8) if sizes[i] > 0]
+    return World(q.r, q.size, page, np.asarray([offs[i] for i in keep], np.uint64),
+                 np.asarray([sizes[i] for i in keep], np.uint64), 0.0, f"burst{q.r}")
+
+
+def burst_launch(q: ServeReq, w: World) -> Launch:
+    named = [(i, 1) for i in q.parts if i < w.n_alloc]
+    return launch_custom(w, q.r, named, q.n_rec)

@@ -42,6 +42,13 @@ __global__ void synth_apply_writes_kernel(uint8_t *__restrict__ pool, uint64_t p
   }
 }
 
+// Claim words of a burst's pages: page p already present (2) with p = 1/2.
+__global__ void synth_present_kernel(uint32_t *state, uint64_t n, uint64_t key) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (uint64_t)gridDim.x * blockDim.x)
+    state[p] = (synth_at(key, p) & 1u) ? 2u : 0u;
+}
+
 static unsigned grid_for(uint64_t n, unsigned block, unsigned cap) {
   uint64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -74,6 +81,14 @@ int synth_dev_apply_writes(void *d_pool, uint64_t pool_base, uint64_t pool_bytes
   hipLaunchKernelGGL(synth_apply_writes_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, stream,
                      (uint8_t *)d_pool, pool_base, pool_bytes, synth_key(seed, SYNTH_T_WVAL, k),
                      d_rec, n);
+  return (int)hipGetLastError();
+}
+
+int synth_dev_present(uint32_t *d_state, uint64_t n, uint64_t seed, uint32_t r,
+                      hipStream_t stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(synth_present_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, stream,
+                     d_state, n, synth_key(seed, SYNTH_T_PRESENT, r));
   return (int)hipGetLastError();
 }
 

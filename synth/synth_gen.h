@@ -40,7 +40,8 @@ enum {
   SYNTH_T_RW = 4,      /* read / write draw                              */
   SYNTH_T_POS2 = 5,    /* secondary position draw (offset inside buffer) */
   SYNTH_T_CONTENT = 6, /* initial pool contents                          */
-  SYNTH_T_WVAL = 7     /* value stored by the application's writes       */
+  SYNTH_T_WVAL = 7,    /* value stored by the application's writes       */
+  SYNTH_T_PRESENT = 8  /* pages already present before a restore burst   */
 };
 
 /* splitmix64 output function. */

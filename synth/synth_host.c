@@ -47,3 +47,9 @@ uint64_t synth_draw_host(uint64_t seed, uint32_t tag, uint64_t a, uint64_t b) {
   return synth_draw(seed, tag, a, b);
 }
 uint64_t synth_below_host(uint64_t r, uint64_t n) { return synth_below(r, n); }
+
+/* Pages already present (1) before burst r: page p with probability 1/2. */
+void synth_present_host(uint64_t seed, uint32_t r, uint64_t n, uint8_t *out) {
+  uint64_t key = synth_key(seed, SYNTH_T_PRESENT, r), p;
+  for (p = 0; p < n; ++p) out[p] = (uint8_t)(synth_at(key, p) & 1u);
+}

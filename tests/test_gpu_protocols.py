@@ -1,0 +1,306 @@
+"""GPU parity of the protocols on the plain-tiny workload (64 MiB pool, 256
+buffers, 100 launches x 1M accesses, checkpoint opened before launch 20 and
+re-quiesced after launch 79):
+
+* Section 4.2 soft copy-on-write: the image equals the snapshot at t1; with
+  the background copy deferred, the pages copied before each launch are
+  exactly the oracle's copy sets;
+* Section 4.3 soft recopy: the image equals the snapshot at t2 and the
+  recopied pages are exactly the dirty and victim pages;
+* Section 6 concurrent restore: restored pool + launches equals the oracle;
+  with the background restore deferred, the present pages after each launch
+  are exactly the pages touched so far;
+* protocol-order and argument errors.
+Byte copies: the bar is bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_harness import Env, bits_to_pages
+
+pytestmark = pytest.mark.gpu
+N = 1_000_000
+T1, T2 = 20, 80  # begin before launch 20; re-quiesce after launch 79
+V = 1 | 2 | 4    # reads, writes, track
+
+
+@pytest.fixture()
+def env():
+    e = Env(synth.config1_world())
+    yield e
+    e.close()
+
+
+def _buffer_pages(w):
+    m = np.zeros(w.n_pages, np.uint8)
+    for o, b in zip(w.alloc_off, w.alloc_bytes):
+        m[int(o) // w.page_bytes:(int(o) + int(b)) // w.page_bytes] = 1
+    return m
+
+
+class Stream:
+    """The plain-tiny launches, generated on the device in groups of 20."""
+
+    def __init__(self, env, launches):
+        self.env, self.launches = env, launches
+        self.cache = {}
+
+    def records(self, j):
+        g = j // 20
+        if g not in self.cache:
+            self.env.T.cuda.synchronize()  # earlier records may still be read by queued kernels
+            self.cache.clear()
+            self.cache[g] = self.env.records(self.launches[g * 20:(g + 1) * 20], N)
+        return self.cache[g][(j % 20) * N:(j % 20 + 1) * N]
+
+
+def _run_plain(env, st, host_pool, j0, j1):
+    """Launches j0..j1-1 with no checkpoint open (device and host)."""
+    for j in range(j0, j1):
+        L = st.launches[j]
+        r = st.records(j)
+        env.mutate(L, r.data_ptr(), N)
+        synth.apply_writes_host(host_pool, env.base, env.world.seed, L.k,
+                                synth.records_host(env.hw, L))
+    env.app.synchronize()
+
+
+def _validate(env, spec, r, out, cnt, flags=V):
+    env.phos.phos_validate(env.ctx, spec, r, N, flags, out, N, cnt, env.app)
+
+
+@pytest.mark.parametrize("defer", [True, False])
+def test_soft_cow_config1(env, defer):
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(0,), cow_window=(0, T2 - T1), keep_violations=False)
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND if defer else 0,
+                              image, None, env.copy)
+    out, cnt = env.violations_buffers(N)
+    cum = np.zeros(w.n_pages, np.uint8)
+    for j in range(T1, T2):
+        L = launches[j]
+        s = env.spec(L)
+        r = st.records(j)
+        _validate(env, s, r, out, cnt)
+        phos.phos_ckpt_cow(ck, s, env.app)
+        env.mutate(L, r.data_ptr(), N)
+        cum[res.cow_sets[j - T1].astype(np.int64)] = 1
+        if defer and (j - T1) % 7 == 0:
+            env.app.synchronize()
+            got = bits_to_pages(phos.phos_ckpt_copied(ck, w.n_pages), w.n_pages)
+            assert np.array_equal(got, cum), f"copy set after launch {j}"
+        phos.phos_spec_release(env.ctx, s)
+    stats = phos.phos_ckpt_end(ck, env.app)
+    assert np.array_equal(image.cpu().numpy(), res.snapshots[0]), "CoW image != snapshot at t1"
+    n_img_pages = env.image_bytes // w.page_bytes
+    assert stats.bg_pages + stats.cow_pages == n_img_pages
+    if defer:
+        assert stats.cow_pages == int(cum.sum())
+    assert stats.recopy_pages == 0
+    # the application's own writes went to the pool, unaffected by the checkpoint
+    assert np.array_equal(env.pool_host(), host)
+
+
+@pytest.mark.parametrize("drain", [False, True])
+def test_soft_recopy_config1(env, drain):
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(T2 - T1,), window=(0, T2 - T1), keep_violations=False)
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    himg = T.empty(env.image_bytes, dtype=T.uint8, pin_memory=True) if drain else None
+    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, himg, env.copy)
+    out, cnt = env.violations_buffers(N)
+    for j in range(T1, T2):
+        L = launches[j]
+        s = env.spec(L)
+        r = st.records(j)
+        _validate(env, s, r, out, cnt)
+        env.mutate(L, r.data_ptr(), N)
+        phos.phos_spec_release(env.ctx, s)
+    phos.phos_ckpt_recopy(ck, env.app)
+    d = phos.phos_track_read(env.ctx, 0, w.n_pages)
+    v = phos.phos_track_read(env.ctx, 1, w.n_pages)
+    assert np.array_equal(d, oracle.pages_to_bitmap(res.dirty, w.n_pages))
+    assert np.array_equal(v, oracle.pages_to_bitmap(res.victim, w.n_pages))
+    stats = phos.phos_ckpt_end(ck, env.app)
+    want = res.snapshots[T2 - T1]
+    assert np.array_equal(image.cpu().numpy(), want), "recopy image != snapshot at t2"
+    if drain:
+        assert np.array_equal(himg.numpy(), want), "drained host image differs"
+    rset = (res.dirty | res.victim) & _buffer_pages(w)
+    assert stats.recopy_pages == int(rset.sum())
+    # launches after t2 leave the image unchanged
+    _run_plain(env, st, host, T2, T2 + 5)
+    assert np.array_equal(image.cpu().numpy(), want)
+
+
+def test_both_protocols_open_together(env):
+    """A CoW checkpoint (t1 image) and a recopy checkpoint (t2 image) over one window."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)[:40]
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    res = oracle.run_stream(w, launches, env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(0, 40), keep_violations=False)
+    img_a = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    img_b = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    copy2 = T.cuda.Stream()
+    ca = phos.phos_ckpt_begin(env.ctx, phos.COW, 0, img_a, None, env.copy)
+    cb = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, img_b, None, copy2)
+    with pytest.raises(phos.PhosError):
+        phos.phos_ckpt_begin(env.ctx, phos.COW, 0, img_a, None, env.copy)
+    out, cnt = env.violations_buffers(N)
+    for j, L in enumerate(launches):
+        s = env.spec(L)
+        r = st.records(j)
+        _validate(env, s, r, out, cnt)
+        phos.phos_ckpt_cow(ca, s, env.app)
+        env.mutate(L, r.data_ptr(), N)
+        phos.phos_spec_release(env.ctx, s)
+    phos.phos_ckpt_recopy(cb, env.app)
+    phos.phos_ckpt_end(ca, env.app)
+    phos.phos_ckpt_end(cb, env.app)
+    assert np.array_equal(img_a.cpu().numpy(), res.snapshots[0])
+    assert np.array_equal(img_b.cpu().numpy(), res.snapshots[40])
+
+
+def test_cow_straight_to_pinned_host(env):
+    """No device staging: the image is pinned host memory written over PCIe."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)[:10]
+    st = Stream(env, launches)
+    want = oracle.snapshot(synth.content_host(w.seed, 0, w.pool_bytes), env.base, env.table)
+    himg = T.empty(env.image_bytes, dtype=T.uint8, pin_memory=True)
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, 0, himg, None, env.copy)
+    out, cnt = env.violations_buffers(N)
+    for j, L in enumerate(launches):
+        s = env.spec(L)
+        r = st.records(j)
+        _validate(env, s, r, out, cnt)
+        phos.phos_ckpt_cow(ck, s, env.app)
+        env.mutate(L, r.data_ptr(), N)
+        phos.phos_spec_release(env.ctx, s)
+    phos.phos_ckpt_end(ck, env.app)
+    assert np.array_equal(himg.numpy(), want)
+
+
+@pytest.mark.parametrize("mode", ["background", "deferred", "prefetch", "host_image"])
+def test_concurrent_restore_config1(env, mode):
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)[:20]
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    image_h = oracle.snapshot(host, env.base, env.table)
+    if mode == "host_image":
+        image = T.from_numpy(image_h.copy()).pin_memory()
+    else:
+        image = T.from_numpy(image_h.copy()).cuda()
+    env.pool.fill_(0xAB)  # the pool before restore holds garbage
+    T.cuda.synchronize()
+    flags = {"background": 0, "deferred": phos.RST_DEFER_BACKGROUND,
+             "prefetch": phos.RST_DEFER_BACKGROUND | phos.RST_PREFETCH_SPEC,
+             "host_image": 0}[mode]
+    rs = phos.phos_restore_begin(env.ctx, flags, image, env.copy)
+    faulted = T.zeros(1, dtype=T.int64, device="cuda")
+    present = np.zeros(w.n_pages, np.uint8)
+    for j, L in enumerate(launches):
+        s = env.spec(L)
+        r = st.records(j)
+        phos.phos_restore_on_demand(rs, s, r, N, env.app, faulted)
+        env.mutate(L, r.data_ptr(), N)
+        rec_h = synth.records_host(env.hw, L)
+        t = np.zeros(w.n_pages, np.uint8)
+        oracle.touched_pages(rec_h, env.table, env.base, w.page_bytes, w.n_pages, t)
+        if mode == "prefetch":
+            oracle.write_interval_pages(oracle.spec_build(env.table, L.arg_values(env.base)),
+                                        env.base, w.page_bytes, w.n_pages, t)
+            iv = oracle.spec_build(env.table, L.arg_values(env.base))
+            for x in iv:  # read intervals too
+                p0 = (int(x["lo"]) - env.base) // w.page_bytes
+                p1 = (int(x["hi"]) - 1 - env.base) // w.page_bytes
+                t[p0:p1 + 1] = 1
+            t &= _buffer_pages(w)
+        present |= t
+        if mode in ("deferred", "prefetch") and j % 5 == 0:
+            env.app.synchronize()
+            got = bits_to_pages(phos.phos_restore_present(rs, w.n_pages), w.n_pages)
+            assert np.array_equal(got, present), f"present pages after launch {j}"
+            if mode == "deferred":
+                assert int(faulted.item()) == int(present.sum())
+        synth.apply_writes_host(host, env.base, w.seed, L.k, rec_h)
+        phos.phos_spec_release(env.ctx, s)
+    stats = phos.phos_restore_end(rs, env.app)
+    assert stats.bg_pages + stats.demand_pages == env.image_bytes // w.page_bytes
+    inbuf = np.repeat(_buffer_pages(w).astype(bool), w.page_bytes)
+    got = env.pool_host()
+    assert np.array_equal(got[inbuf], host[inbuf]), "restored pool + launches != oracle"
+
+
+def test_restore_without_launches_is_the_image(env):
+    phos, w, T = env.phos, env.world, env.T
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    image_h = oracle.snapshot(host, env.base, env.table)
+    image = T.from_numpy(image_h.copy()).cuda()
+    env.pool.zero_()
+    T.cuda.synchronize()
+    rs = phos.phos_restore_begin(env.ctx, 0, image, env.copy)
+    phos.phos_restore_end(rs, env.app)
+    got = env.pool_host()
+    assert np.array_equal(oracle.snapshot(got, env.base, env.table), image_h)
+
+
+def test_protocol_errors(env):
+    phos, T = env.phos, env.T
+    image = T.empty(env.image_bytes + 16, dtype=T.uint8, device="cuda")
+    L = synth.config1_launches(env.world, 1, 1)[0]
+    s = env.spec(L)
+    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, None, env.copy)
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_ckpt_cow(ck, s, env.app)
+    assert e.value.status == phos.E_STATE
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_buffers_register(env.ctx, env.world.buffers(env.base))
+    assert e.value.status == phos.E_STATE
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_restore_begin(env.ctx, 0, image, env.copy)
+    assert e.value.status == phos.E_STATE
+    phos.phos_ckpt_recopy(ck, env.app)
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_ckpt_recopy(ck, env.app)
+    assert e.value.status == phos.E_STATE
+    phos.phos_ckpt_end(ck, env.app)
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_ckpt_begin(env.ctx, phos.COW, 0, image[8:], None, env.copy)
+    assert e.value.status == phos.E_INVAL
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, 0, image, None, env.copy)
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_ckpt_recopy(ck, env.app)
+    assert e.value.status == phos.E_STATE
+    phos.phos_ckpt_end(ck, env.app)
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_validate(env.ctx, 12345, 0, 0, 3, 0, 0, 0, env.app)
+    assert e.value.status == phos.E_INVAL
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_spec_register(env.ctx, 0, [(4, 0, env.base, 64)])  # range without mode
+    assert e.value.status == phos.E_INVAL
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_buffers_register(env.ctx, [(env.base + 100, 4096)])  # misaligned
+    assert e.value.status == phos.E_INVAL
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_create(0, env.base + 8, 1 << 20, 4096)
+    assert e.value.status == phos.E_INVAL
+    phos.phos_spec_release(env.ctx, s)

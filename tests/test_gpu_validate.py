@@ -106,8 +106,14 @@ def test_validate_config1_all_launches(env1):
     assert 90_000 < total < 110_000  # 0.1 % of 1e8
 
 
-def test_validate_batch_matches_per_launch(env1):
+@pytest.mark.parametrize("scan_path", [False, True])
+def test_validate_batch_matches_per_launch(env1, scan_path, monkeypatch):
+    """Batched validation, ordered by the one-workgroup finish or (forced) by the
+    segment scan + scatter kernels."""
     from paper_2405_12079_amd import phos
+    if scan_path:
+        monkeypatch.setenv("PHOS_VFINISH_MAX_TILES", "0")
+        env1 = Env(env1.world)
     w = env1.world
     launches = synth.config1_launches(w, 40, 250_000)
     recs = env1.records(launches, 250_000)
@@ -124,8 +130,16 @@ def test_validate_batch_matches_per_launch(env1):
         want.append(oracle.validate(iv, synth.records_host(env1.hw, L), env1.table, L.k))
     want = np.concatenate(want)
     assert n == len(want) and np.array_equal(got, want)
+    # a second call with identical descriptors reuses the device copy
+    out.zero_()
+    phos.phos_validate_batch(env1.ctx, specs, ptrs, [250_000] * 40, FLAGS, out, cap, cnt, env1.app)
+    env1.app.synchronize()
+    n2, got2 = Env.read_violations(out, cnt, cap)
+    assert n2 == n and np.array_equal(got2, want)
     for s in specs:
         phos.phos_spec_release(env1.ctx, s)
+    if scan_path:
+        env1.close()
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 127, 2047, 2048, 2049, 8193, 70001])

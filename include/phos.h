@@ -228,6 +228,14 @@ phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nword
 phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
                                hipStream_t copy_stream, phos_rst **out);
 
+/* As phos_restore_begin, with the image split into nchunks pieces of
+ * chunk_bytes each (a multiple of the page size; the last may be partly
+ * used): image byte i lives at chunks[i / chunk_bytes] + i % chunk_bytes.
+ * For host images too large for one pinned allocation. */
+phos_status phos_restore_begin_chunked(phos_ctx *ctx, uint32_t flags, const void *const *chunks,
+                                       uint32_t nchunks, uint64_t chunk_bytes,
+                                       hipStream_t copy_stream, phos_rst **out);
+
 /* Section 6: before a launch runs on app_stream, bring in every page inside a
  * buffer that its records touch (and, with PHOS_RST_PREFETCH_SPEC, every page
  * of its speculated intervals) that is not present yet.  d_faulted: optional
@@ -311,9 +319,9 @@ phos_status phos_batch_run_plain(phos_batch *b, hipStream_t stream);
  * when their copies are done.  PHOS_SERVE_PLAIN serves one request at a time
  * (FIFO, one launch each).  PHOS_SERVE_BATCHED is continuous batching:
  * admitted bulk requests share each iteration (up to quantum_bytes each,
- * iter_bytes in total, oldest first) of the persistent graph-captured copy,
- * two iterations in flight; requests arriving meanwhile join the next
- * iteration; bursts run at once on their own stream. */
+ * iter_bytes in total, shortest remaining work first) of the persistent
+ * graph-captured copy, two iterations in flight; requests arriving meanwhile
+ * join the next iteration; bursts run at once on their own stream. */
 enum { PHOS_SERVE_PLAIN = 0, PHOS_SERVE_BATCHED = 1 };
 enum { PHOS_REQ_CKPT = 0, PHOS_REQ_RESTORE = 1, PHOS_REQ_BURST = 2 };
 
@@ -344,8 +352,11 @@ typedef struct {
 } phos_serve_cfg;
 
 typedef struct {
-  double admit_ms, done_ms, latency_ms; /* host clock, from the run start / arrival */
-  uint64_t dst_off;                     /* destination offset in d_arena           */
+  double admit_ms;   /* host clock, ms after the run start                        */
+  double done_ms;    /* completion: the copy kernel's GPU wall-clock stamp mapped
+                        to the host clock (bursts: when the host saw it finish)   */
+  double latency_ms; /* done_ms - arrival                                        */
+  uint64_t dst_off;  /* destination offset in d_arena                             */
 } phos_serve_out;
 
 typedef struct {

@@ -169,7 +169,7 @@ extern "C" phos_status phos_batch_destroy(phos_batch *b) {
   if (b->d_cursor) (void)hipFree(b->d_cursor);
   if (b->d_done) (void)hipFree(b->d_done);
   if (b->d_req_total) (void)hipFree(b->d_req_total);
-  if (b->d_req_time) (void)hipFree(b->d_req_time);
+  if (b->d_req_time) (void)hipHostFree(b->d_req_time);
   if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->stage_evt) (void)hipEventDestroy(b->stage_evt);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -195,7 +195,9 @@ extern "C" phos_status phos_batch_create(int device, uint64_t max_segs, uint32_t
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_cursor, 8);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_done, 8ull * max_reqs);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_req_total, 8ull * max_reqs);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_req_time, 8ull * (max_reqs + 1));
+  // completion stamps live in pinned host memory: the host reads them in place
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&b->d_req_time, 8ull * (max_reqs + 1), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemset(b->d_req_total, 0xFF, 8ull * max_reqs);
   int khz = 0;
   if (e == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) ==
@@ -250,6 +252,11 @@ extern "C" phos_status phos_batch_load(phos_batch *b, const phos_copy_seg *segs,
   return PHOS_OK;
 }
 
+namespace phos {
+const volatile unsigned long long *batch_stamps(const phos_batch *b) { return b->d_req_time; }
+double batch_clock_khz(const phos_batch *b) { return b->clock_khz; }
+}  // namespace phos
+
 extern "C" phos_status phos_batch_run_plain(phos_batch *b, hipStream_t stream) {
   if (!b) return fail(PHOS_E_INVAL, "phos_batch_run_plain: NULL");
   DeviceGuard g(b->device);
@@ -267,7 +274,7 @@ extern "C" phos_status phos_batch_times(phos_batch *b, double *ms, uint32_t n) {
   DeviceGuard g(b->device);
   std::vector<unsigned long long> t(n + 1);
   HIP_TRY(hipDeviceSynchronize());
-  HIP_TRY(hipMemcpy(t.data(), b->d_req_time, 8ull * (n + 1), hipMemcpyDeviceToHost));
+  for (uint32_t i = 0; i <= n; ++i) t[i] = b->d_req_time[i];  // pinned host memory
   for (uint32_t r = 0; r < n; ++r)
     ms[r] = t[r + 1] ? (double)(t[r + 1] - t[0]) / b->clock_khz : -1.0;
   return PHOS_OK;

@@ -72,17 +72,21 @@ struct VArgs {
 };
 
 // Page-granular copy between the pool and an image under per-page states.
+// Every field defaults to zero / null, so a field added later can never reach
+// a kernel as stack garbage.
 struct CopyArgs {
-  uint8_t *pool;               // byte at pool_base
-  uint8_t *image;              // byte 0 of the image
-  uint32_t *state;             // per pool page: kFree / kClaimed / kDone
-  const uint32_t *img_page;    // per pool page: image page or kNone
-  unsigned long long *stat;    // pages copied by this kernel family
-  uint32_t *err;               // bit 0: a bounded wait expired
-  uint32_t page_shift, n_pages;
-  uint32_t to_image;           // 1: pool -> image (checkpoint); 0: image -> pool (restore)
-  uint32_t spin_limit;
-  uint32_t nt;                 // non-temporal page copies
+  uint8_t *pool = nullptr;               // byte at pool_base
+  uint8_t *image = nullptr;              // byte 0 of the image
+  uint32_t *state = nullptr;             // per pool page: kFree / kClaimed / kDone
+  const uint32_t *img_page = nullptr;    // per pool page: image page or kNone
+  unsigned long long *stat = nullptr;    // pages copied by this kernel family
+  uint32_t *err = nullptr;               // bit 0: a bounded wait expired
+  uint32_t page_shift = 0, n_pages = 0;
+  uint32_t to_image = 0;                 // 1: pool -> image (checkpoint); 0: image -> pool (restore)
+  uint32_t spin_limit = 0;
+  uint32_t nt = 0;                       // non-temporal page copies
+  uint32_t chunk_pages = 0;              // pages per image piece (with image_chunks)
+  const unsigned long long *image_chunks = nullptr;  // image pieces (device table) or nullptr
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.
@@ -144,7 +148,13 @@ hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32
 hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t *bits,
                                 hipStream_t s);
 hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s);
+hipError_t launch_read_clock(unsigned long long *out, hipStream_t s);  // GPU wall clock
 hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s);
 hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);
+
+// Completion stamps of a batch's last run ([0] start, [1 + r] request r),
+// host-visible (pinned), and the GPU wall-clock rate in kHz.
+const volatile unsigned long long *batch_stamps(const phos_batch *b);
+double batch_clock_khz(const phos_batch *b);
 
 }  // namespace phos

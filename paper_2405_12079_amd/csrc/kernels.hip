@@ -13,6 +13,9 @@
 
 #include "internal.h"
 
+#define GLOBAL_AS __attribute__((address_space(1)))
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 namespace phos {
 namespace {
 
@@ -30,13 +33,9 @@ __device__ __forceinline__ bool cas_u32(uint32_t *p, uint32_t &expected, uint32_
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
-  return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
-}
 
 // Block-cooperative 16-byte copy, eight loads in flight per thread;
 // NT: non-temporal (streaming) loads and stores.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <bool NT>
 __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
                                                uint4 *__restrict__ dst_, uint64_t n16) {
@@ -78,100 +77,150 @@ __device__ __forceinline__ uint32_t bytes_to_mask(const uint8_t *p) {
 }
 
 // ============================================================ validation
+// Interval bounds in scalar registers: an access at a is inside interval j
+// iff lo[j] <= a <= hi8[j] (hi8 = hi - 8); empty intervals get lo = ~0,
+// hi8 = 0.  Mode bits are wave-uniform, so the mode folding is scalar logic.
 struct IvRegs {
-  uint64_t lo[8], span[8];
+  uint64_t lo[8], hi8[8];
   uint32_t mode[8];
-  uint32_t n;
 };
 
 // 0 = valid; 1 = in no interval; 2 = inside but the mode bit is missing.
-// jw: an interval that validates a write (for dirty tracking).
-template <bool TRACK>
-__device__ __forceinline__ uint32_t classify_fast(const IvRegs &R, uint64_t a, uint32_t w, int &jw) {
-  bool inside = false, ok = false;
+template <int NIV>
+__device__ __forceinline__ uint32_t classify_n(const IvRegs &R, uint64_t a, uint32_t w) {
+  bool any = false, okr = false, okw = false;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    if (j < (int)R.n) {
-      const bool in = (a - R.lo[j]) <= R.span[j];
-      const bool m = (R.mode[j] >> w) & 1u;
-      inside |= in;
-      if (in && m) {
-        ok = true;
-        if (TRACK) jw = j;
-      }
-    }
+  for (int j = 0; j < NIV; ++j) {
+    const bool in = (a >= R.lo[j]) & (a <= R.hi8[j]);
+    any |= in;
+    if (R.mode[j] & PHOS_R) okr |= in;
+    if (R.mode[j] & PHOS_W) okw |= in;
   }
-  return ok ? 0u : (inside ? 2u : 1u);
+  return (w ? okw : okr) ? 0u : (any ? 2u : 1u);
 }
 
-template <bool TRACK>
-__device__ __forceinline__ uint32_t classify_slow(const DevSpec &S, uint32_t niv, uint64_t a,
-                                                  uint32_t w, int &jw) {
-  bool inside = false, ok = false;
+// Any number of intervals, from the LDS table.
+__device__ __forceinline__ uint32_t classify_lds(const DevSpec &S, uint32_t niv, uint64_t a,
+                                                 uint32_t w) {
+  bool any = false, ok = false;
   for (uint32_t j = 0; j < niv; ++j) {
-    const bool in = (a - S.iv[j].lo) <= S.iv[j].span;
-    const bool m = (S.iv[j].mode >> w) & 1u;
-    inside |= in;
-    if (in && m) {
-      ok = true;
-      if (TRACK) jw = (int)j;
-    }
+    const DevIv iv = S.iv[j];
+    const bool in = (a - iv.lo) <= iv.span;
+    any |= in;
+    ok |= in & (((iv.mode >> w) & 1u) != 0);
   }
-  return ok ? 0u : (inside ? 2u : 1u);
+  return ok ? 0u : (any ? 2u : 1u);
 }
 
 struct VShared {
   DevSpec spec;
   uint32_t list[kVWaves][kWcap];
   uint32_t wcnt[kVWaves];
-  uint32_t seg_base[kMaxIv], seg_fw[kMaxIv];
-  uint32_t seg_nw;  // LDS dirty words in use, or kNone (global path)
+  uint32_t win_fw;   // first global dirty-map word of the LDS window
+  uint32_t win_nw;   // window words in use, or kNone (write pages straight to the map)
   VLaunch L;
   unsigned long long off;
 };
 
+// Tracking for one record (Section 4.3): a validated write marks its page in
+// the LDS window (or straight in the dirty map); a failing write inside a
+// buffer marks the victim map and is appended to the victim list.
 template <bool TRACK>
-__device__ __forceinline__ bool check_record(const VArgs &A, const VShared &S, const IvRegs &R,
-                                             bool fast, uint32_t niv, uint32_t *s_track,
-                                             uint64_t r, bool valid) {
-  const uint64_t a = r & ~7ull;
-  const uint32_t w = (uint32_t)(r & 1u);
-  int jw = -1;
-  const uint32_t reason = fast ? classify_fast<TRACK>(R, a, w, jw)
-                               : classify_slow<TRACK>(S.spec, niv, a, w, jw);
-  if (TRACK && valid && w) {
-    const uint64_t off = a - A.pool_base;
-    if (off < A.pool_bytes) {
-      const uint32_t page = (uint32_t)(off >> A.page_shift);
-      const uint32_t bit = 1u << (page & 31);
-      if (reason == 0) {
-        if (S.seg_nw != kNone) {
-          const uint32_t base = S.seg_base[jw];
-          if (base != kNone) atomicOr(&s_track[base + (page >> 5) - S.seg_fw[jw]], bit);
-        } else {
-          A.dirty[page] = 1;
-        }
-      } else if (A.page_buf[page] != kNone && A.victim[page] == 0) {
-        // newly marked victim page (a stale read only adds a duplicate)
-        A.victim[page] = 1;
-        const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
-        if (i < A.vlist_cap) A.vlist[i] = page;
-        else A.vmeta[3] = 1;
+__device__ __forceinline__ void track_record(const VArgs &A, const VShared &S, uint32_t *s_track,
+                                             uint32_t *s_sum, uint64_t a, uint32_t reason) {
+  if (!TRACK) return;
+  const uint64_t off = a - A.pool_base;
+  if (off >= A.pool_bytes) return;
+  const uint32_t page = (uint32_t)(off >> A.page_shift);
+  if (reason == 0) {
+    if (S.win_nw != kNone) {
+      const uint32_t lw = (page >> 5) - S.win_fw;
+      if (atomicOr(&s_track[lw], 1u << (page & 31)) == 0) atomicOr(&s_sum[lw >> 5], 1u << (lw & 31));
+    } else {
+      A.dirty[page] = 1;
+    }
+  } else if (A.page_buf[page] != kNone && A.victim[page] == 0) {
+    // newly marked victim page (a stale read only adds a duplicate)
+    A.victim[page] = 1;
+    const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
+    if (i < A.vlist_cap) A.vlist[i] = page;
+    else A.vmeta[3] = 1;
+  }
+}
+
+// Rank the step's violating records inside the wave (two records per lane,
+// interleaved in index order) and keep their local indices in LDS.
+__device__ __forceinline__ void rank_violations(VShared &S, uint32_t wave, uint64_t lt, bool b0,
+                                                bool b1, uint32_t local, uint32_t &wcnt) {
+  const uint64_t m0 = __ballot(b0), m1 = __ballot(b1);
+  if (__builtin_expect((m0 | m1) != 0, 0)) {
+    const uint32_t rk = wcnt + __popcll(m0 & lt) + __popcll(m1 & lt);
+    if (b0 && rk < kWcap) S.list[wave][rk] = local;
+    const uint32_t rk1 = rk + (b0 ? 1u : 0u);
+    if (b1 && rk1 < kWcap) S.list[wave][rk1] = local + 1;
+    wcnt += __popcll(m0) + __popcll(m1);
+  }
+}
+
+// One wave's range [wbase, wend) of records; NIV < 0: intervals from LDS.
+template <int NIV, bool TRACK>
+__device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint32_t *s_track,
+                                               uint32_t *s_sum, uint32_t niv,
+                                               const GLOBAL_AS uint64_t *rec8, bool al16,
+                                               uint64_t wbase, uint64_t wend, uint32_t wave,
+                                               uint32_t lane) {
+  // this specialization's bounds, from LDS into registers (uniform values;
+  // kept in VGPRs: scalar registers are needed for the comparison masks)
+  IvRegs R;
+#pragma unroll
+  for (int j = 0; j < (NIV > 0 ? NIV : 0); ++j) {
+    const DevIv iv = S.spec.iv[j];
+    R.lo[j] = iv.lo;
+    R.hi8[j] = iv.lo == ~0ull ? 0ull : iv.lo + iv.span;
+    R.mode[j] = rfl(iv.mode);
+  }
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t wcnt = 0;
+  uint64_t c = wbase;
+  auto one = [&](uint64_t r, bool valid) -> bool {
+    const uint64_t a = r & ~7ull;
+    const uint32_t w = (uint32_t)(r & 1u);
+    const uint32_t reason = NIV >= 0 ? classify_n<(NIV >= 0 ? NIV : 0)>(R, a, w)
+                                     : classify_lds(S.spec, niv, a, w);
+    if (TRACK && valid && w) track_record<TRACK>(A, S, s_track, s_sum, a, reason);
+    return valid && reason != 0 && ((A.flags >> w) & 1u);
+  };
+  // main body: whole steps only, four 16-byte loads in flight, no branches
+  if (al16) {
+    const GLOBAL_AS u32x4 *__restrict__ rec4 = (const GLOBAL_AS u32x4 *)rec8;
+    for (; c + kVStep * kVUnroll <= wend; c += kVStep * kVUnroll) {
+      u32x4 q[kVUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
+#pragma unroll
+      for (uint32_t u = 0; u < kVUnroll; ++u) {
+        const bool b0 = one(((uint64_t)q[u].y << 32) | q[u].x, true);
+        const bool b1 = one(((uint64_t)q[u].w << 32) | q[u].z, true);
+        rank_violations(S, wave, lt, b0, b1, (uint32_t)(c - wbase) + u * kVStep + 2 * lane, wcnt);
       }
     }
   }
-  return valid && reason != 0 && ((A.flags >> w) & 1u);
+  // tail (and 8-byte-aligned arrays): 128 records per step, guarded loads
+  for (; c < wend; c += kVStep) {
+    const uint64_t i0 = c + 2 * lane;
+    const bool v0 = i0 < wend, v1 = i0 + 1 < wend;
+    const bool b0 = one(v0 ? rec8[i0] : 0, v0);
+    const bool b1 = one(v1 ? rec8[i0 + 1] : 0, v1);
+    rank_violations(S, wave, lt, b0, b1, (uint32_t)(i0 - wbase), wcnt);
+  }
+  return wcnt;
 }
 
-__device__ __forceinline__ void emit_violation(const VArgs &A, const VShared &S, const IvRegs &R,
-                                               bool fast, uint32_t niv, uint64_t idx, uint64_t r,
-                                               unsigned long long pos) {
+__device__ __forceinline__ void emit_violation(const VArgs &A, const VShared &S, uint32_t niv,
+                                               uint64_t idx, uint64_t r, unsigned long long pos) {
   if (pos >= A.scratch_cap) return;
   const uint64_t a = r & ~7ull;
   const uint32_t w = (uint32_t)(r & 1u);
-  int jw = -1;
-  const uint32_t reason =
-      fast ? classify_fast<false>(R, a, w, jw) : classify_slow<false>(S.spec, niv, a, w, jw);
   const uint64_t off = a - A.pool_base;
   const uint32_t b = off < A.pool_bytes ? A.page_buf[off >> A.page_shift] : kNone;
   phos_violation v;
@@ -179,7 +228,7 @@ __device__ __forceinline__ void emit_violation(const VArgs &A, const VShared &S,
   v.addr = a;
   v.launch_id = S.L.launch_id;
   v.is_write = (uint8_t)w;
-  v.reason = (uint8_t)reason;
+  v.reason = (uint8_t)classify_lds(S.spec, niv, a, w);
   v._p = 0;
   v.victim = (int32_t)b;
   v._q = 0;
@@ -190,6 +239,7 @@ template <bool BATCH, bool TRACK>
 __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec single) {
   __shared__ VShared S;
   __shared__ uint32_t s_track[TRACK ? kTrackWords : 1];
+  __shared__ uint32_t s_sum[TRACK ? kTrackWords / 32 : 1];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t tile = blockIdx.x;
 
@@ -213,110 +263,71 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
 
   if (TRACK) {
     if (tid == 0) {
-      // LDS segment per write interval, aligned to global bitmap words.
-      uint32_t nw = 0;
+      // one LDS window of whole dirty-map words spanning every write interval
+      uint32_t fw = kNone, lw = 0;
       const uint64_t pool_end = A.pool_base + A.pool_bytes;
       for (uint32_t j = 0; j < niv; ++j) {
         const DevIv iv = S.spec.iv[j];
-        S.seg_base[j] = kNone;
         if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
         const uint64_t hi = iv.lo + iv.span + 8;
         const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
         const uint64_t hi_c = hi < pool_end ? hi : pool_end;
         if (hi_c <= lo_c) continue;
-        const uint32_t fw = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
-        const uint32_t lw = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
-        S.seg_fw[j] = fw;
-        S.seg_base[j] = nw;
-        nw += lw - fw + 1;
-        if (nw > kTrackWords) break;
+        const uint32_t f = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
+        const uint32_t l = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
+        fw = f < fw ? f : fw;
+        lw = l > lw ? l : lw;
       }
-      S.seg_nw = nw <= kTrackWords ? nw : kNone;
+      S.win_fw = fw;
+      S.win_nw = (fw != kNone && lw - fw + 1 <= kTrackWords) ? lw - fw + 1 : (fw == kNone ? 0u : kNone);
     }
     __syncthreads();
-    if (S.seg_nw != kNone)
-      for (uint32_t j = tid; j < S.seg_nw; j += kVThreads) s_track[j] = 0;
-    __syncthreads();
-  }
-
-  IvRegs R;
-  const bool fast = niv <= 8;
-  R.n = fast ? niv : 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    if (j < (int)R.n) {
-      R.lo[j] = rfl64(S.spec.iv[j].lo);
-      R.span[j] = rfl64(S.spec.iv[j].span);
-      R.mode[j] = rfl(S.spec.iv[j].mode);
-    } else {
-      R.lo[j] = ~0ull;
-      R.span[j] = 0;
-      R.mode[j] = 0;
+    if (S.win_nw != kNone) {
+      for (uint32_t j = tid; j < S.win_nw; j += kVThreads) s_track[j] = 0;
+      for (uint32_t j = tid; j < (S.win_nw + 31) / 32; j += kVThreads) s_sum[j] = 0;
     }
+    __syncthreads();
   }
 
   const uint64_t n = S.L.n;
-  const uint64_t *__restrict__ rec = S.L.rec;
+  const uint64_t *rec = S.L.rec;
+  // the record pointer came through LDS: restate that it is global memory so
+  // the loads are global (not flat) loads
+  const GLOBAL_AS uint64_t *__restrict__ rec8 = (const GLOBAL_AS uint64_t *)rec;
   const uint32_t Q = A.tile_recs / kVWaves;
   const uint64_t wbase = (uint64_t)(tile - S.L.tile0) * A.tile_recs + (uint64_t)wave * Q;
+  const uint64_t wend = wbase + Q < n ? wbase + Q : n;
   const bool al16 = (((uintptr_t)rec) & 15u) == 0;
-  const uint64_t lt = (1ull << lane) - 1ull;
   uint32_t wcnt = 0;
-
-  for (uint32_t c = 0; c < Q; c += kVStep * kVUnroll) {
-    if (wbase + c >= n) break;
-    uint64_t r0[kVUnroll], r1[kVUnroll];
-#pragma unroll
-    for (uint32_t u = 0; u < kVUnroll; ++u) {
-      const uint64_t i0 = wbase + c + u * kVStep + 2 * lane;
-      r0[u] = 0;
-      r1[u] = 0;
-      if (i0 + 1 < n) {
-        if (al16) {
-          const uint4 q = *reinterpret_cast<const uint4 *>(rec + i0);
-          r0[u] = ((uint64_t)q.y << 32) | q.x;
-          r1[u] = ((uint64_t)q.w << 32) | q.z;
-        } else {
-          r0[u] = rec[i0];
-          r1[u] = rec[i0 + 1];
-        }
-      } else if (i0 < n) {
-        r0[u] = rec[i0];
-      }
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kVUnroll; ++u) {
-      const uint32_t local = c + u * kVStep + 2 * lane;
-      const uint64_t i0 = wbase + local;
-      const bool b0 = check_record<TRACK>(A, S, R, fast, niv, s_track, r0[u], i0 < n);
-      const bool b1 = check_record<TRACK>(A, S, R, fast, niv, s_track, r1[u], i0 + 1 < n);
-      const uint64_t m0 = __ballot(b0), m1 = __ballot(b1);
-      if (m0 | m1) {
-        const uint32_t rk = wcnt + __popcll(m0 & lt) + __popcll(m1 & lt);
-        if (b0 && rk < kWcap) S.list[wave][rk] = local;
-        const uint32_t rk1 = rk + (b0 ? 1u : 0u);
-        if (b1 && rk1 < kWcap) S.list[wave][rk1] = local + 1;
-        wcnt += __popcll(m0) + __popcll(m1);
-      }
-    }
+#define PHOS_SCAN(N)                                                                          \
+  wcnt = scan_range<N, TRACK>(A, S, s_track, s_sum, niv, rec8, al16, wbase, wend, wave, lane)
+  switch (niv) {
+    case 0: PHOS_SCAN(0); break;
+    case 1: PHOS_SCAN(1); break;
+    case 2: PHOS_SCAN(2); break;
+    case 3: PHOS_SCAN(3); break;
+    case 4: PHOS_SCAN(4); break;
+    case 5: PHOS_SCAN(5); break;
+    case 6: PHOS_SCAN(6); break;
+    case 7: PHOS_SCAN(7); break;
+    case 8: PHOS_SCAN(8); break;
+    default: PHOS_SCAN(-1); break;
   }
+#undef PHOS_SCAN
 
   if (lane == 0) S.wcnt[wave] = wcnt;
   __syncthreads();
 
-  if (TRACK && S.seg_nw != kNone) {
-    for (uint32_t w = tid; w < S.seg_nw; w += kVThreads) {
-      const uint32_t v = s_track[w];
-      if (!v) continue;
-      uint32_t jj = 0, bb = 0;
-      for (uint32_t j = 0; j < niv; ++j) {
-        const uint32_t b = S.seg_base[j];
-        if (b != kNone && b <= w && b >= bb) { jj = j; bb = b; }
+  if (TRACK && S.win_nw != kNone && S.win_nw) {
+    // flush the touched words of the window: one plain byte store per page
+    // (the page maps need no atomics, and byte-granular stores from
+    // different L2s never clobber each other)
+    for (uint32_t sw = tid; sw < (S.win_nw + 31) / 32; sw += kVThreads) {
+      for (uint32_t m = s_sum[sw]; m; m &= m - 1) {
+        const uint32_t lw = sw * 32 + __ffs(m) - 1;
+        const uint32_t p0 = (S.win_fw + lw) * 32;
+        for (uint32_t bits = s_track[lw]; bits; bits &= bits - 1) A.dirty[p0 + __ffs(bits) - 1] = 1;
       }
-      // one plain byte store per page: the page maps need no atomics, and
-      // byte-granular stores from different L2s never clobber each other
-      const uint32_t p0 = (S.seg_fw[jj] + (w - bb)) * 32;
-      for (uint32_t bits = v; bits; bits &= bits - 1) A.dirty[p0 + __ffs(bits) - 1] = 1;
     }
   }
 
@@ -339,22 +350,24 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   } else if (wcnt <= kWcap) {
     for (uint32_t j = lane; j < wcnt; j += 64) {
       const uint64_t i = wbase + S.list[wave][j];
-      emit_violation(A, S, R, fast, niv, i, rec[i], start + j);
+      emit_violation(A, S, niv, i, rec8[i], start + j);
     }
   } else {
     // More violations than the LDS list holds: rescan this wave's range in
     // order and write each one at its rank (rare: degenerate launches).
+    const uint64_t lt = (1ull << lane) - 1ull;
     uint32_t cnt = 0;
-    for (uint32_t c = 0; c < Q; c += kVStep) {
-      if (wbase + c >= n) break;
-      const uint64_t i0 = wbase + c + 2 * lane;
-      const uint64_t r0 = i0 < n ? rec[i0] : 0, r1 = i0 + 1 < n ? rec[i0 + 1] : 0;
-      const bool b0 = check_record<false>(A, S, R, fast, niv, nullptr, r0, i0 < n);
-      const bool b1 = check_record<false>(A, S, R, fast, niv, nullptr, r1, i0 + 1 < n);
+    for (uint64_t cc = wbase; cc < wend; cc += kVStep) {
+      const uint64_t i0 = cc + 2 * lane;
+      const uint64_t r0 = i0 < wend ? rec8[i0] : 0, r1 = i0 + 1 < wend ? rec8[i0 + 1] : 0;
+      const bool b0 = i0 < wend && classify_lds(S.spec, niv, r0 & ~7ull, (uint32_t)(r0 & 1u)) &&
+                      ((A.flags >> (r0 & 1u)) & 1u);
+      const bool b1 = i0 + 1 < wend && classify_lds(S.spec, niv, r1 & ~7ull, (uint32_t)(r1 & 1u)) &&
+                      ((A.flags >> (r1 & 1u)) & 1u);
       const uint64_t m0 = __ballot(b0), m1 = __ballot(b1);
       const uint32_t rk = cnt + __popcll(m0 & lt) + __popcll(m1 & lt);
-      if (b0) emit_violation(A, S, R, fast, niv, i0, r0, start + rk);
-      if (b1) emit_violation(A, S, R, fast, niv, i0 + 1, r1, start + rk + (b0 ? 1u : 0u));
+      if (b0) emit_violation(A, S, niv, i0, r0, start + rk);
+      if (b1) emit_violation(A, S, niv, i0 + 1, r1, start + rk + (b0 ? 1u : 0u));
       cnt += __popcll(m0) + __popcll(m1);
     }
   }
@@ -458,7 +471,15 @@ __global__ void __launch_bounds__(1024)
 __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
   const uint64_t pb = 1ull << C.page_shift;
   uint8_t *pool_p = C.pool + ((uint64_t)p << C.page_shift);
-  uint8_t *img_p = C.image + ((uint64_t)C.img_page[p] << C.page_shift);
+  const uint32_t ip = C.img_page[p];
+  uint8_t *img_p;
+  if (C.image_chunks) {  // image in pieces of chunk_pages pages
+    const uint32_t c = ip / C.chunk_pages;
+    img_p = reinterpret_cast<uint8_t *>(C.image_chunks[c]) +
+            ((uint64_t)(ip - c * C.chunk_pages) << C.page_shift);
+  } else {
+    img_p = C.image + ((uint64_t)ip << C.page_shift);
+  }
   const uint4 *src = reinterpret_cast<const uint4 *>(C.to_image ? pool_p : img_p);
   uint4 *dst = reinterpret_cast<uint4 *>(C.to_image ? img_p : pool_p);
   block_copy16(src, dst, pb >> 4, C.nt != 0);
@@ -496,9 +517,23 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   __syncthreads();
   const uint32_t nwon = s_nwon;
   for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i]);
-  if (nwon) __threadfence();
+  // Publishing "done".  Checkpoint direction: a waiter only needs this
+  // block's reads of the pool to have returned (the image is read after the
+  // kernel ends), so waiting for every outstanding access is enough.
+  // Restore direction: the pool writes must reach memory before anyone on
+  // another XCD reads them, which takes a device-scope release.
+  if (nwon) {
+    if (C.to_image) __builtin_amdgcn_s_waitcnt(0);
+    else __threadfence();
+  }
   __syncthreads();
-  if (threadIdx.x < nwon) st_release(&C.state[s_won[threadIdx.x]], kDone);
+  if (threadIdx.x < nwon) {
+    if (C.to_image)
+      __hip_atomic_store(&C.state[s_won[threadIdx.x]], kDone, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    else
+      st_release(&C.state[s_won[threadIdx.x]], kDone);
+  }
   if (threadIdx.x == 0 && nwon) {
     atomicAdd(C.stat, (unsigned long long)nwon);
     if (extra) atomicAdd(extra, (unsigned long long)nwon);
@@ -769,6 +804,8 @@ __global__ void plain_copy_kernel(BatchQ Q) {
   copy_stream_range(Q, nseg, b0, b0 + Q.chunk_bytes < total ? b0 + Q.chunk_bytes : total);
 }
 
+__global__ void clock_kernel(unsigned long long *out) { *out = __builtin_amdgcn_s_memrealtime(); }
+
 unsigned grid_cap(uint64_t n, unsigned block, unsigned cap) {
   uint64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -886,6 +923,11 @@ hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t 
   if (!nwords) return hipSuccess;
   hipLaunchKernelGGL(bytes_to_bits_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, bytes,
                      nwords, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_clock(unsigned long long *out, hipStream_t s) {
+  hipLaunchKernelGGL(clock_kernel, dim3(1), dim3(1), 0, s, out);
   return hipGetLastError();
 }
 

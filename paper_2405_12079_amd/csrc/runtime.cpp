@@ -131,6 +131,10 @@ struct phos_ckpt {
   Slot *slot;
   bool recopied = false;
   bool bg_started = false;
+  hipEvent_t bg_done = nullptr;  // recorded after the background copy
+  bool bg_known_done = false;
+  hipStream_t cow_stream = nullptr;  // the one stream CoW calls came from
+  bool cow_streams_many = false;
 };
 
 struct phos_rst {
@@ -140,6 +144,8 @@ struct phos_rst {
   hipStream_t copy;
   Slot *slot;
   bool bg_started = false;
+  unsigned long long *d_chunks = nullptr;  // image pieces (device table) or nullptr
+  uint32_t chunk_pages = 0;
 };
 
 #define HIP_TRY(x)                                                                  \
@@ -217,7 +223,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = (uint32_t)prop.multiProcessorCount;
-  c->bg_grid = env_u32("PHOS_BG_GRID", 4 * c->n_cu);
+  c->bg_grid = env_u32("PHOS_BG_GRID", c->n_cu);
   c->cow_grid = env_u32("PHOS_COW_GRID", 4 * c->n_cu);
   c->copy_nt = env_u32("PHOS_COPY_NT", 0);
   c->finish_tiles = env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles);
@@ -702,6 +708,8 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
   a.to_image = to_image ? 1u : 0u;
   a.spin_limit = c->spin_limit;
   a.nt = c->copy_nt;
+  a.chunk_pages = 0;
+  a.image_chunks = nullptr;
   return a;
 }
 
@@ -710,13 +718,17 @@ static uint32_t chunk_pages(phos_ctx *c) {
   return std::max<uint32_t>(1, (4u << 20) >> c->page_shift);
 }
 
-static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
-                                    hipStream_t stream) {
+static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a,
+                                         hipStream_t stream) {
   const uint32_t cp = chunk_pages(c);
   const uint32_t nchunks = (c->n_pages + cp - 1) / cp;
-  CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
   HIP_TRY(launch_background(a, &s.counters[0], nchunks, cp, std::min(c->bg_grid, nchunks), stream));
   return PHOS_OK;
+}
+
+static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
+                                    hipStream_t stream) {
+  return start_background_args(c, s, copy_args(c, s, image, to_image, &s.counters[1]), stream);
 }
 
 // Pages of the intervals with any of `modes`, clamped to the pool.
@@ -773,7 +785,11 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   k->slot = &s;
   if (!(flags & PHOS_CKPT_DEFER_BACKGROUND)) {
     phos_status st = start_background(c, s, k->image, true, copy);
+    if (st == PHOS_OK && (hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming) != hipSuccess ||
+                          hipEventRecord(k->bg_done, copy) != hipSuccess))
+      st = fail(PHOS_E_HIP, "background completion event");
     if (st != PHOS_OK) {
+      if (k->bg_done) (void)hipEventDestroy(k->bg_done);
       delete k;
       return st;
     }
@@ -791,6 +807,22 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   HostSpec *h = get_spec(c, spec);
   if (!h) return fail(PHOS_E_INVAL, "phos_ckpt_cow: unknown spec %u", spec);
   DeviceGuard g(c->device);
+  // Once the background copy is known to have finished, every page has been
+  // copied or claimed by an earlier copy-on-write on this same stream, so
+  // there is nothing left to do (not under stream capture: a graph may be
+  // replayed while a later checkpoint's background copy still runs).
+  if (k->cow_stream && k->cow_stream != app) k->cow_streams_many = true;
+  k->cow_stream = app;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(app, &cs));
+  if (cs == hipStreamCaptureStatusNone && k->bg_done && !k->cow_streams_many) {
+    if (!k->bg_known_done) {
+      const hipError_t q = hipEventQuery(k->bg_done);
+      if (q == hipSuccess) k->bg_known_done = true;
+      else if (q != hipErrorNotReady) return fail(PHOS_E_HIP, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+    if (k->bg_known_done) return PHOS_OK;
+  }
   const PageRanges r = page_ranges(c, *h, PHOS_W);
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
   const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords};
@@ -863,6 +895,7 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
   bool timeout = false;
   TRY(read_err(c, k->copy, &timeout));
   c->open_ckpt[k->protocol] = nullptr;
+  if (k->bg_done) (void)hipEventDestroy(k->bg_done);
   delete k;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the image is not valid");
   return PHOS_OK;
@@ -887,9 +920,43 @@ extern "C" phos_status phos_ckpt_copied(phos_ckpt *k, uint32_t *host, uint64_t n
 }
 
 // ------------------------------------------------------------------ restore
+static CopyArgs rst_args(phos_rst *r, unsigned long long *stat) {
+  CopyArgs a = copy_args(r->ctx, *r->slot, const_cast<uint8_t *>(r->image), false, stat);
+  a.image_chunks = r->d_chunks;
+  a.chunk_pages = r->chunk_pages;
+  return a;
+}
+
+static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
+                                const void *const *chunks, uint32_t nchunks, uint64_t chunk_bytes,
+                                hipStream_t copy, phos_rst **out);
+
 extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const void *image,
                                           hipStream_t copy, phos_rst **out) {
+  if (!image) return fail(PHOS_E_INVAL, "phos_restore_begin: NULL image");
+  return restore_open(c, flags, image, nullptr, 0, 0, copy, out);
+}
+
+extern "C" phos_status phos_restore_begin_chunked(phos_ctx *c, uint32_t flags,
+                                                  const void *const *chunks, uint32_t nchunks,
+                                                  uint64_t chunk_bytes, hipStream_t copy,
+                                                  phos_rst **out) {
+  if (!c || !chunks || !nchunks) return fail(PHOS_E_INVAL, "phos_restore_begin_chunked: NULL");
+  if (!chunk_bytes || chunk_bytes % c->page_bytes || (chunk_bytes >> c->page_shift) > 0xFFFFFFFFull)
+    return fail(PHOS_E_INVAL, "chunk_bytes must be a multiple of the page size");
+  if ((uint64_t)nchunks * chunk_bytes < c->image_bytes)
+    return fail(PHOS_E_INVAL, "the pieces hold less than the image");
+  for (uint32_t i = 0; i < nchunks; ++i)
+    if (!chunks[i] || ((uintptr_t)chunks[i] & 15))
+      return fail(PHOS_E_INVAL, "piece %u NULL or not 16-byte aligned", i);
+  return restore_open(c, flags, chunks[0], chunks, nchunks, chunk_bytes, copy, out);
+}
+
+static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
+                                const void *const *chunks, uint32_t nchunks, uint64_t chunk_bytes,
+                                hipStream_t copy, phos_rst **out) {
   if (!c || !image || !out) return fail(PHOS_E_INVAL, "phos_restore_begin: NULL argument");
+  *out = nullptr;
   if (flags & ~(PHOS_RST_DEFER_BACKGROUND | PHOS_RST_PREFETCH_SPEC))
     return fail(PHOS_E_INVAL, "unknown flags 0x%x", flags);
   if (((uintptr_t)image) & 15) return fail(PHOS_E_INVAL, "image must be 16-byte aligned");
@@ -907,8 +974,19 @@ extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const voi
   r->image = (const uint8_t *)image;
   r->copy = copy;
   r->slot = &s;
+  if (chunks) {
+    std::vector<unsigned long long> tab(nchunks);
+    for (uint32_t i = 0; i < nchunks; ++i) tab[i] = reinterpret_cast<uintptr_t>(chunks[i]);
+    if (hipMalloc((void **)&r->d_chunks, 8ull * nchunks) != hipSuccess ||
+        hipMemcpy(r->d_chunks, tab.data(), 8ull * nchunks, hipMemcpyHostToDevice) != hipSuccess) {
+      if (r->d_chunks) (void)hipFree(r->d_chunks);
+      delete r;
+      return fail(PHOS_E_NOMEM, "restore piece table");
+    }
+    r->chunk_pages = (uint32_t)(chunk_bytes >> c->page_shift);
+  }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
-    phos_status st = start_background(c, s, const_cast<uint8_t *>(r->image), false, copy);
+    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1]), copy);
     if (st != PHOS_OK) {
       delete r;
       return st;
@@ -929,14 +1007,12 @@ extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const
   if (!h) return fail(PHOS_E_INVAL, "phos_restore_on_demand: unknown spec %u", spec);
   DeviceGuard g(c->device);
   Slot &s = *r->slot;
-  uint8_t *img = const_cast<uint8_t *>(r->image);
   if (r->flags & PHOS_RST_PREFETCH_SPEC) {
     const PageRanges pr = page_ranges(c, *h, PHOS_R | PHOS_W);
-    CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
     const VictimList none{nullptr, nullptr, 0, nullptr, 0};
-    HIP_TRY(launch_cow(a, pr, none, true, c->cow_grid, app));
+    HIP_TRY(launch_cow(rst_args(r, &s.counters[2]), pr, none, true, c->cow_grid, app));
   }
-  CopyArgs a = copy_args(c, s, img, false, &s.counters[2]);
+  CopyArgs a = rst_args(r, &s.counters[2]);
   HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, app));
   return PHOS_OK;
 }
@@ -958,7 +1034,7 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   HIP_TRY(hipStreamWaitEvent(r->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!r->bg_started) {
-    TRY(start_background(c, s, const_cast<uint8_t *>(r->image), false, r->copy));
+    TRY(start_background_args(c, s, rst_args(r, &s.counters[1]), r->copy));
     r->bg_started = true;
   }
   HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, r->copy));
@@ -971,6 +1047,7 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   bool timeout = false;
   TRY(read_err(c, r->copy, &timeout));
   c->open_rst = nullptr;
+  if (r->d_chunks) (void)hipFree(r->d_chunks);
   delete r;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the pool is not valid");
   return PHOS_OK;

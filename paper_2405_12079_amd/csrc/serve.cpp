@@ -86,7 +86,7 @@ struct Iter {        // one iteration of the batched copy
   phos_batch *b = nullptr;
   hipEvent_t ev = nullptr;
   bool busy = false;
-  std::vector<uint32_t> finishing;  // requests whose last bytes ride on it
+  std::vector<std::pair<uint32_t, uint32_t>> finishing;  // (request, id in the iteration)
 };
 
 class Server {
@@ -108,8 +108,12 @@ class Server {
   phos_status launch_burst(uint32_t i, uint64_t dst, hipStream_t s);
   phos_status run_plain();
   phos_status run_batched();
-  void complete(uint32_t i) {
-    out_[i].done_ms = now_ms();
+  // GPU wall-clock stamp -> host clock (ms since the run start)
+  double stamp_ms(unsigned long long s, double khz) const {
+    return host0_ms_ + ((double)s - (double)gpu0_) / khz;
+  }
+  void complete(uint32_t i, double done_ms = -1.0) {
+    out_[i].done_ms = done_ms >= 0 ? done_ms : now_ms();
     out_[i].latency_ms = out_[i].done_ms - reqs_[i].arrival_s * 1e3;
     if (!cfg_.keep) arena_.release(out_[i].dst_off, reqs_[i].bytes);
     --active_;
@@ -131,6 +135,8 @@ class Server {
   uint32_t done_ = 0, active_ = 0, max_active_ = 0;
   uint64_t bulk_bytes_ = 0, iterations_ = 0;
   uint32_t page_shift_ = 16;
+  unsigned long long gpu0_ = 0, *h_clock_ = nullptr;  // clock calibration
+  double host0_ms_ = 0;
 
   hipStream_t bulk_ = nullptr, burst_ = nullptr;
   Iter iters_[2];
@@ -176,6 +182,7 @@ phos_status Server::setup() {
   HIP_TRY(hipMalloc((void **)&d_identity_, 4 * max_pages));
   HIP_TRY(hipMemcpy(d_identity_, ident.data(), 4 * max_pages, hipMemcpyHostToDevice));
   HIP_TRY(hipMalloc((void **)&d_err_, 4));
+  HIP_TRY(hipHostMalloc((void **)&h_clock_, 8, hipHostMallocDefault));
   HIP_TRY(hipMalloc((void **)&d_faulted_, 8));
   HIP_TRY(hipMemset(d_err_, 0, 4));
   HIP_TRY(hipMemset(d_faulted_, 0, 8));
@@ -203,6 +210,8 @@ void Server::cleanup() {
   plain_ = nullptr;
   for (hipEvent_t e : ev_pool_) (void)hipEventDestroy(e);
   ev_pool_.clear();
+  if (h_clock_) (void)hipHostFree(h_clock_);
+  h_clock_ = nullptr;
   if (d_identity_) (void)hipFree(d_identity_);
   if (d_err_) (void)hipFree(d_err_);
   if (d_faulted_) (void)hipFree(d_faulted_);
@@ -229,6 +238,8 @@ phos_status Server::launch_burst(uint32_t i, uint64_t dst, hipStream_t s) {
   c.to_image = 0;
   c.spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
   c.nt = 0;
+  c.chunk_pages = 0;
+  c.image_chunks = nullptr;  // the request's image is one piece
   HIP_TRY(launch_demand(c, r.d_records, r.nrec, 0, nullptr, s));
   return PHOS_OK;
 }
@@ -266,7 +277,8 @@ phos_status Server::run_plain() {
       bulk_bytes_ += seg_bytes(i);
     }
     HIP_TRY(hipStreamSynchronize(bulk_));
-    complete(i);
+    const unsigned long long st = r.type != PHOS_REQ_BURST ? batch_stamps(plain_)[1] : 0;
+    complete(i, st ? stamp_ms(st, batch_clock_khz(plain_)) : -1.0);
   }
   return PHOS_OK;
 }
@@ -320,7 +332,11 @@ phos_status Server::run_batched() {
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) return fail(PHOS_E_HIP, "iteration: %s", hipGetErrorString(q));
       it.busy = false;
-      for (uint32_t i : it.finishing) complete(i);
+      const volatile unsigned long long *st = batch_stamps(it.b);
+      for (auto &f : it.finishing) {
+        const unsigned long long s = st[1 + f.second];
+        complete(f.first, s ? stamp_ms(s, batch_clock_khz(it.b)) : -1.0);
+      }
       it.finishing.clear();
       progress = true;
     }
@@ -337,9 +353,13 @@ phos_status Server::run_batched() {
       bursts.pop_back();
       progress = true;
     }
-    // issue iterations into free slots: oldest first, up to quantum each
+    // issue iterations into free slots: shortest remaining work first (a
+    // small request never waits behind a large one; the largest takes what
+    // is left of each iteration), at most quantum bytes per request
     for (Iter &it : iters_) {
       if (it.busy || bulk.empty()) continue;
+      std::stable_sort(bulk.begin(), bulk.end(),
+                       [](const Bulk &x, const Bulk &y) { return x.left < y.left; });
       segbuf_.clear();
       uint64_t budget = cfg_.iter_bytes;
       uint32_t nreq = 0;
@@ -368,7 +388,7 @@ phos_status Server::run_batched() {
             b->seg_off = 0;
           }
         }
-        if (!b->left) it.finishing.push_back(b->idx);
+        if (!b->left) it.finishing.emplace_back(b->idx, rid);
         if (segbuf_.size() + 4096 > kIterMaxSegs) break;
       }
       while (!bulk.empty() && !bulk.front().left) bulk.pop_front();
@@ -396,6 +416,14 @@ phos_status Server::run(phos_serve_stats *stats) {
   for (uint32_t i = 0; i < n_; ++i) out_[i] = phos_serve_out{-1.0, -1.0, -1.0, 0};
   HIP_TRY(hipDeviceSynchronize());
   t0_ = Clock::now();
+  {  // map the GPU wall clock onto the host clock
+    const double a = now_ms();
+    HIP_TRY(launch_read_clock(h_clock_, bulk_));
+    HIP_TRY(hipStreamSynchronize(bulk_));
+    const double b = now_ms();
+    gpu0_ = *(volatile unsigned long long *)h_clock_;
+    host0_ms_ = 0.5 * (a + b);
+  }
   phos_status st = cfg_.mode == PHOS_SERVE_BATCHED ? run_batched() : run_plain();
   HIP_TRY(hipDeviceSynchronize());
   const double wall = now_ms() - (n_ ? reqs_[0].arrival_s * 1e3 : 0.0);

@@ -85,6 +85,7 @@ SIGNATURES = [
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
+    ("phos_restore_begin_chunked", [P, U32, P, U32, U64, P, PP]),
     ("phos_restore_on_demand", [P, U32, P, U64, P, P]),
     ("phos_restore_present", [P, P, U64]),
     ("phos_restore_end", [P, P, P]),
@@ -265,6 +266,14 @@ def phos_ckpt_copied(ck, n_pages: int) -> np.ndarray:
 def phos_restore_begin(ctx, flags, image, copy_stream) -> int:
     out = ctypes.c_void_p()
     _call("phos_restore_begin", ctx, flags, _ptr(image), _stream(copy_stream), ctypes.byref(out))
+    return out.value
+
+
+def phos_restore_begin_chunked(ctx, flags, chunks, chunk_bytes, copy_stream) -> int:
+    tab = (ctypes.c_void_p * len(chunks))(*[_ptr(x) for x in chunks])
+    out = ctypes.c_void_p()
+    _call("phos_restore_begin_chunked", ctx, flags, tab, len(chunks), chunk_bytes,
+          _stream(copy_stream), ctypes.byref(out))
     return out.value
 
 

@@ -198,23 +198,36 @@ def test_cow_straight_to_pinned_host(env):
     assert np.array_equal(himg.numpy(), want)
 
 
-@pytest.mark.parametrize("mode", ["background", "deferred", "prefetch", "host_image"])
+@pytest.mark.parametrize("mode", ["background", "deferred", "prefetch", "host_image", "chunked"])
 def test_concurrent_restore_config1(env, mode):
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)[:20]
     st = Stream(env, launches)
     host = synth.content_host(w.seed, 0, w.pool_bytes)
     image_h = oracle.snapshot(host, env.base, env.table)
+    chunks = None
     if mode == "host_image":
         image = T.from_numpy(image_h.copy()).pin_memory()
+    elif mode == "chunked":
+        # the image in pinned host pieces of 3 MiB (the last one partly used)
+        cb = 3 << 20
+        chunks = []
+        for o in range(0, image_h.size, cb):
+            piece = T.zeros(cb, dtype=T.uint8).pin_memory()
+            piece[:min(cb, image_h.size - o)] = T.from_numpy(image_h[o:o + cb].copy())
+            chunks.append(piece)
+        image = None
     else:
         image = T.from_numpy(image_h.copy()).cuda()
     env.pool.fill_(0xAB)  # the pool before restore holds garbage
     T.cuda.synchronize()
     flags = {"background": 0, "deferred": phos.RST_DEFER_BACKGROUND,
              "prefetch": phos.RST_DEFER_BACKGROUND | phos.RST_PREFETCH_SPEC,
-             "host_image": 0}[mode]
-    rs = phos.phos_restore_begin(env.ctx, flags, image, env.copy)
+             "host_image": 0, "chunked": 0}[mode]
+    if chunks is not None:
+        rs = phos.phos_restore_begin_chunked(env.ctx, flags, chunks, 3 << 20, env.copy)
+    else:
+        rs = phos.phos_restore_begin(env.ctx, flags, image, env.copy)
     faulted = T.zeros(1, dtype=T.int64, device="cuda")
     present = np.zeros(w.n_pages, np.uint8)
     for j, L in enumerate(launches):

@@ -8,15 +8,16 @@ moments, 80 activations, 1,848 small buffers), 64 KiB pages, and a step of
   * open a soft copy-on-write checkpoint (image A, frozen at the step start)
     and a soft recopy checkpoint (image B, taken at the step end), both with
     their background copies on one copy stream;
-  * for every launch: validate its access stream (with dirty / victim
-    tracking), copy-on-write of the pages it may write, then the application's
-    launch itself (its writes) — the loop is captured once as a HIP graph;
+  * validate the launches' access streams (with dirty / victim tracking) in
+    batched calls, then for every launch: copy-on-write of the pages it may
+    write, then the application's launch itself (its writes);
   * re-quiesce, recopy the dirty and victim pages into B, close both.
 
-The JSON line's value is the step's snapshot rate: bytes written into the two
-images per second of step time (inputs resident in HBM).  The roofline object
-covers the dominant kernel (the background copy); `cpu_baseline` times the
-CPU oracle on a bounded sample of the same step.
+The JSON line's value is the step's snapshot rate: bytes of the two finished
+checkpoint images per second of step time (inputs resident in HBM); the bytes
+actually copied into them (a page may be copied twice) are reported beside.
+The roofline object covers the dominant kernel (the background copy);
+`cpu_baseline` times the CPU oracle on a bounded sample of the same step.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--config 2]
 """
@@ -32,6 +33,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
+KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary (profiles/<kernel>_<workload>_pmc.txt), or None
+    when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+    if fields.get("kernels_hip_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
 
 
 def log(*a):
@@ -142,6 +163,7 @@ def pinned_tensor(torch, nbytes):
     p = ctypes.c_void_p()
     rc = hip.hipHostMalloc(ctypes.byref(p), ctypes.c_size_t(nbytes), 0)
     if rc != 0:
+        hip.hipGetLastError()  # do not leave the error for the next HIP call to report
         raise RuntimeError(f"hipHostMalloc({nbytes}) failed: {rc}")
     arr = np.ctypeslib.as_array((ctypes.c_uint8 * nbytes).from_address(p.value))
     _pinned_keep.append(p)
@@ -296,12 +318,22 @@ def run_training_step(args):
     app_alone_ms = float(np.median(ts))
     log(f"[bench] background copy alone {bg_alone_ms:.3f} ms; application launches alone "
         f"{app_alone_ms:.3f} ms")
+    # the Section 5 drain of a finished image to pinned host memory (PCIe)
+    host_img = pinned_tensor(torch, nimg)
+    ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, host_img.data_ptr(), cpy)
+    cpy.synchronize()
+    t0d = time.perf_counter()
+    phos.phos_ckpt_end(ca, cpy)
+    d2h_s = time.perf_counter() - t0d
+    log(f"[bench] D2H drain of the image: {nimg / d2h_s / 1e9:.1f} GB/s")
     roofs = copy_roofs(torch, phos)
     log(f"[bench] copy roofs: {roofs}")
 
-    # bytes written into the images per step
-    img_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"])
-                         * page for r in rows])
+    # checkpoint image bytes finished per step (two images), and the bytes
+    # actually copied into them
+    img_bytes = 2 * nimg
+    copied_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"])
+                            * page for r in rows])
     snap_gbps = img_bytes / (ms_step / 1e3) / 1e9
     # dominant kernel: background copy (2 bytes of HBM traffic per byte copied)
     bg_ms = np.mean([r["bg_a"] for r in rows] + [r["bg_b"] for r in rows])
@@ -336,10 +368,12 @@ def run_training_step(args):
         "launches_per_validation_call": chunk,
         "copy_roofs": roofs,
         "violations_per_step": nviol,
-        "bytes_into_images_per_step": int(img_bytes),
+        "image_bytes_per_step": int(img_bytes),
+        "bytes_copied_into_images_per_step": int(copied_bytes),
         "roofline": {"bound": "hbm", "kernel": "background_kernel",
                      "achieved": round(bg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(bg_gbps / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(bg_gbps / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic("background_kernel", "training_step"),
                      "algorithmic_bytes_per_launch": int(2 * bg_bytes),
                      "avg_launch_ms": round(bg_ms, 4)},
         "roofline_background_alone": {"bound": "hbm", "kernel": "background_kernel, nothing beside it",
@@ -348,6 +382,7 @@ def run_training_step(args):
                                        "frac": round(2 * nimg / bg_alone_ms / 1e6 / HBM_PEAK_GBPS, 4),
                                        "avg_launch_ms": round(bg_alone_ms, 4)},
         "application_alone_ms": round(app_alone_ms, 3),
+        "d2h_drain_GBps": round(nimg / d2h_s / 1e9, 2),
         "roofline_validate": {"bound": "hbm", "kernel": "validate_kernel (+scan, scatter), alone",
                               "achieved": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6, 1),
                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -470,7 +505,8 @@ def run_batched(args):
                      "achieved": round(2 * dst_bytes / (bt / 1e3) / 1e9, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(2 * dst_bytes / (bt / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "algorithmic_bytes_per_launch": int(2 * dst_bytes),
+                     "traffic": measured_traffic("batch_copy_kernel", "batched_uneven"),
+                     "algorithmic_bytes_per_launch": int(2 * dst_bytes),
                      "avg_launch_ms": round(bt, 4)},
         "parity": f"{checked} sampled delta pages byte-equal to the generator's source pages",
     }
@@ -532,14 +568,23 @@ def run_cold_start(args):
     for g in range(0, n_launch, 2000):
         grp = launches[g:g + 2000]
         synth.records_device(dw, grp, n_rec, out=recs[g * n_rec:(g + len(grp)) * n_rec])
-    # the image: the pool's initial contents, buffer by buffer, in pinned host
-    # memory, in pieces of at most 32 GiB (one pinned allocation of 70 GiB is
-    # more than the box grants)
+    # the image: the pool's initial contents, buffer by buffer, in host memory,
+    # in pieces of 32 GiB; pinned as far as the system grants it (on the
+    # MI355X host used here one process can pin 64 GiB), the rest pageable,
+    # which the library moves by DMA instead of from its kernels
     t0 = time.perf_counter()
     cb = 32 << 30
-    pieces = [pinned_tensor(torch, min(cb, w.image_bytes - o)) for o in range(0, w.image_bytes, cb)]
-    log(f"[bench] pinned {w.image_bytes / 2**30:.1f} GiB in {len(pieces)} pieces in "
-        f"{time.perf_counter() - t0:.1f} s")
+    pieces, pinned_bytes = [], 0
+    for o in range(0, w.image_bytes, cb):
+        n = min(cb, w.image_bytes - o)
+        try:
+            pieces.append(pinned_tensor(torch, n))
+            pinned_bytes += n
+        except RuntimeError:
+            pieces.append(torch.empty(n, dtype=torch.uint8))
+    log(f"[bench] image in {len(pieces)} pieces: {pinned_bytes / 2**30:.1f} GiB pinned, "
+        f"{(w.image_bytes - pinned_bytes) / 2**30:.1f} GiB pageable "
+        f"({time.perf_counter() - t0:.1f} s)")
 
     def image_spans(o, b, off):
         """(pool offset, piece, offset in piece, bytes) covering image bytes [off, off+b)."""
@@ -609,7 +654,8 @@ def run_cold_start(args):
     stalls = np.array([ev0[j].elapsed_time(ev1[j]) for j in range(n_launch)])
     h2d = w.image_bytes / (max(full, stream_ms) / 1e3) / 1e9
     log(f"[bench] time to first kernel {ttfk:.2f} ms; fully present {full:.1f} ms; stream "
-        f"{stream_ms:.1f} ms; demand pages {st.demand_pages}, background {st.bg_pages}; "
+        f"{stream_ms:.1f} ms; demand pages {st.demand_pages}, background {st.bg_pages}, "
+        f"DMA {st.dma_pages}; "
         f"stall p50 {np.percentile(stalls, 50) * 1e3:.1f} us p99 {np.percentile(stalls, 99) * 1e3:.1f} us")
     res = {
         "metric": "cold-start restore: time-to-first-kernel; PCIe GB/s of the concurrent restore",
@@ -617,9 +663,10 @@ def run_cold_start(args):
         "ms_per_step": round(stream_ms, 3), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8",
         "data": "synthetic (seeded layout, decode-like access streams, contents)",
-        "config": {"workload": "cold-start: 70 GiB image of 500 buffers in pinned host memory, "
+        "config": {"workload": "cold-start: 70 GiB image of 500 buffers in host memory, "
                                f"{n_launch} launches x {n_rec} accesses, 64 KiB pages",
-                   "image_bytes": int(w.image_bytes)},
+                   "image_bytes": int(w.image_bytes), "pinned_bytes": int(pinned_bytes),
+                   "pageable_bytes": int(w.image_bytes - pinned_bytes)},
         "time_to_first_kernel_ms": round(ttfk, 3),
         "stop_the_world_restore_ms": round(stw_ms, 3),
         "fully_present_ms": round(full, 3),
@@ -627,6 +674,7 @@ def run_cold_start(args):
         "restore_h2d_GBps": round(h2d, 2),
         "stop_the_world_h2d_GBps": round(w.image_bytes / stw_ms / 1e6, 2),
         "demand_pages": int(st.demand_pages), "background_pages": int(st.bg_pages),
+        "dma_pages": int(st.dma_pages),
         "stall_ms": {"p50": round(float(np.percentile(stalls, 50)), 4),
                      "p99": round(float(np.percentile(stalls, 99)), 4),
                      "max": round(float(stalls.max()), 3)},
@@ -734,14 +782,14 @@ def run_serving(args):
     dst = torch.empty(budget, dtype=torch.uint8, device="cuda")
     reqs, keep, bursts = serving_inputs(torch, phos, synth, trace, page, src.data_ptr(), seed)
     cache = os.path.join(ROOT, "paper_2405_12079_amd", "tune_cache.txt")
-    bcfg = phos.phos_batch_cfg(1 << 20, 2, 512)
+    bcfg = phos.phos_batch_cfg(64 << 10, 1, 512)  # the contiguous-copy optimum measured here
     log(f"[bench] serving: {len(trace)} requests over {warm + dur:.0f} s, "
         f"{sum(q.size for q in trace) / (warm + dur) / 2**30:.0f} GiB/s offered (request sizes)")
     out = {}
     for mode, name in ((phos.SERVE_PLAIN, "plain"), (phos.SERVE_BATCHED, "batched")):
         reseed_bursts(torch, synth, bursts, seed)
         cfg = phos.phos_serve_cfg(mode, page, budget, dst.data_ptr(), args.quantum << 20,
-                                  args.iter_mib << 20, bcfg, 0, 0)
+                                  args.iter_mib << 20, bcfg, 0, 0, args.small_mib << 20)
         outs, st = phos.phos_serve_run(0, cfg, reqs, len(trace))
         lat = latency_stats(trace, outs, warm, synth)
         out[name] = {"latency": lat, "wall_ms": round(st.wall_ms, 1),
@@ -825,11 +873,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launches5", type=int, default=40_000)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
-    ap.add_argument("--quantum", type=int, default=512, help="MiB per request per iteration")
-    ap.add_argument("--iter-mib", type=int, default=512, help="MiB per batched iteration")
+    ap.add_argument("--quantum", type=int, default=2048, help="MiB per request per iteration")
+    ap.add_argument("--iter-mib", type=int, default=2048, help="MiB per batched iteration")
+    ap.add_argument("--small-mib", type=int, default=1024,
+                    help="batched order: requests with at most this many MiB left go first")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
-    ap.add_argument("--no-app-graph", dest="app_graph", action="store_false",
-                    help="launch the per-launch copy-on-write + application loop eagerly")
+    ap.add_argument("--app-graph", action="store_true",
+                    help="replay the per-launch copy-on-write + application loop as one HIP "
+                         "graph (eager is faster: it skips copy-on-write once the background "
+                         "copy is known done)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the hot path is per GPU and shards by process "

@@ -119,6 +119,7 @@ typedef struct {
 typedef struct {
   uint64_t bg_pages;     /* pages brought in by the background restore */
   uint64_t demand_pages; /* pages brought in before a launch           */
+  uint64_t dma_pages;    /* pages of pageable image pieces (DMA)       */
 } phos_rst_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -181,7 +182,8 @@ phos_status phos_validate_batch(phos_ctx *ctx, const phos_spec *specs,
                                 uint32_t nlaunch, uint32_t flags, phos_violation *out,
                                 uint64_t cap, uint64_t *n_violations, hipStream_t stream);
 
-/* Clear the dirty and victim bitmaps (asynchronous on stream). */
+/* Clear the dirty and victim bitmaps (asynchronous on stream).  E_STATE while
+ * a recopy checkpoint is open: its recopy list is read from these maps. */
 phos_status phos_track_reset(phos_ctx *ctx, hipStream_t stream);
 /* Synchronous copy of a bitmap to host: which 0 = dirty, 1 = victim.  Bit p%32
  * of word p/32 is pool page p; nwords >= ceil(pool pages / 32). */
@@ -209,29 +211,39 @@ phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream)
 
 /* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every
  * dirty or victim page into the image after the background copy; app_stream
- * then waits for the recopy.  PROTOCOL RECOPY only. */
+ * then waits for the recopy.  PROTOCOL RECOPY only.  The background copy of
+ * a recopy checkpoint skips pages already marked dirty or victim when it
+ * reaches them: the recopy copies those pages anyway, so the image is the
+ * same and the concurrent copy moves fewer bytes. */
 phos_status phos_ckpt_recopy(phos_ckpt *ck, hipStream_t app_stream);
 
 /* Finish: wait for every copy (and app_stream), drain image to host_image if
- * given, free the handle.  E_TIMEOUT if a device wait expired. */
+ * given, free the handle.  A recopy checkpoint not yet recopied is recopied
+ * first (ending is a quiesce point).  E_TIMEOUT if a device wait expired. */
 phos_status phos_ckpt_end(phos_ckpt *ck, hipStream_t app_stream, phos_ckpt_stats *stats);
 
-/* Synchronous: copied-page bitmap of an open checkpoint (bit p = pool page p). */
+/* Synchronous: copied-page bitmap of an open checkpoint (bit p = pool page p);
+ * for a recopy checkpoint, the pages its background copy has copied. */
 phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nwords);
 
 /* ----------------------------------------------------------------- restore */
 
-/* Section 6: open a concurrent restore from `image` (device or pinned host
- * memory, phos_image_bytes() bytes, layout as written by a checkpoint).  The
- * background copy of every page into the pool starts on copy_stream unless
- * PHOS_RST_DEFER_BACKGROUND.  One restore per context at a time. */
+/* Section 6: open a concurrent restore from `image` (phos_image_bytes()
+ * bytes, layout as written by a checkpoint).  The background copy of every
+ * page into the pool starts on copy_stream unless PHOS_RST_DEFER_BACKGROUND.
+ * Device or pinned host memory is read by the kernels directly; a pageable
+ * host image cannot be, so its pages are claimed at begin and moved by DMA
+ * from a library thread on a private stream (launches that need them wait
+ * until they land).  One restore per context at a time. */
 phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
                                hipStream_t copy_stream, phos_rst **out);
 
 /* As phos_restore_begin, with the image split into nchunks pieces of
  * chunk_bytes each (a multiple of the page size; the last may be partly
  * used): image byte i lives at chunks[i / chunk_bytes] + i % chunk_bytes.
- * For host images too large for one pinned allocation. */
+ * For host images too large for one pinned allocation, or larger than the
+ * host lets a process pin: each piece may be device, pinned or pageable
+ * memory, pageable pieces going the DMA way described above. */
 phos_status phos_restore_begin_chunked(phos_ctx *ctx, uint32_t flags, const void *const *chunks,
                                        uint32_t nchunks, uint64_t chunk_bytes,
                                        hipStream_t copy_stream, phos_rst **out);
@@ -349,6 +361,10 @@ typedef struct {
   phos_batch_cfg cfg;      /* copy kernel configuration                         */
   uint32_t keep;           /* nonzero: never reuse a destination (for checking)  */
   uint32_t _pad;
+  uint64_t small_bytes;    /* BATCHED order inside an iteration: requests with at
+                              most this many bytes left go first, shortest first;
+                              the rest follow in arrival order (UINT64_MAX:
+                              shortest remaining first for every request)       */
 } phos_serve_cfg;
 
 typedef struct {

@@ -28,6 +28,8 @@ constexpr uint32_t kFuseTiles = 4096;            // calls up to this many tiles 
 
 // Copy kernels.
 constexpr uint32_t kCThreads = 256;
+constexpr uint32_t kBgCopyThreads = 512;            // copying waves of a background block
+constexpr uint32_t kBgThreads = kBgCopyThreads + 64; // plus one claiming wave
 constexpr uint32_t kUnitPages = 64;  // pages per copy-on-write work unit
 
 // Interval in the form the kernel tests: an access at a is inside iff
@@ -54,6 +56,7 @@ struct VArgs {
   const VLaunch *launches;  // device table (batch) or nullptr (single launch below)
   VLaunch single;
   const DevIv *ivs;         // flat interval table (batch)
+  const uint32_t *tile_launch;  // launch of every tile (batch)
   uint32_t nlaunch, ntiles;
   uint32_t flags, tile_recs;
   uint64_t pool_base, pool_bytes;
@@ -87,6 +90,9 @@ struct CopyArgs {
   uint32_t nt = 0;                       // non-temporal page copies
   uint32_t chunk_pages = 0;              // pages per image piece (with image_chunks)
   const unsigned long long *image_chunks = nullptr;  // image pieces (device table) or nullptr
+  // Recopy background only: pages already marked in either page map are left
+  // to the recopy (nullptr: copy every page).
+  const uint8_t *skip_dirty = nullptr, *skip_victim = nullptr;
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.
@@ -135,8 +141,11 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
                            phos_violation *out, uint64_t cap, hipStream_t s);
 hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
                       uint32_t max_grid, hipStream_t s);
-hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor, uint32_t nchunks,
-                             uint32_t chunk_pages, uint32_t grid, hipStream_t s);
+hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
+                              uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
+                              unsigned long long *count, hipStream_t s);
+hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
+                             hipStream_t s);
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s);
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,

@@ -38,11 +38,12 @@ __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_re
 // NT: non-temporal (streaming) loads and stores.
 template <bool NT>
 __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
-                                               uint4 *__restrict__ dst_, uint64_t n16) {
+                                               uint4 *__restrict__ dst_, uint64_t n16,
+                                               uint32_t tid, uint32_t nthreads) {
   const u32x4 *__restrict__ src = reinterpret_cast<const u32x4 *>(src_);
   u32x4 *__restrict__ dst = reinterpret_cast<u32x4 *>(dst_);
-  const uint64_t T = blockDim.x;
-  uint64_t i = threadIdx.x;
+  const uint64_t T = nthreads;
+  uint64_t i = tid;
   for (; i + 7 * T < n16; i += 8 * T) {
     u32x4 v[8];
 #pragma unroll
@@ -56,10 +57,17 @@ __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
   }
   for (; i < n16; i += T) dst[i] = src[i];
 }
+// tid / nthreads: this thread among the threads sharing the copy (default:
+// the whole block)
 __device__ __forceinline__ void block_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
-                                             uint64_t n16, bool nt = false) {
-  if (nt) block_copy16_t<true>(src, dst, n16);
-  else block_copy16_t<false>(src, dst, n16);
+                                             uint64_t n16, bool nt = false,
+                                             uint32_t tid = ~0u, uint32_t nthreads = 0) {
+  if (tid == ~0u) {
+    tid = threadIdx.x;
+    nthreads = blockDim.x;
+  }
+  if (nt) block_copy16_t<true>(src, dst, n16, tid, nthreads);
+  else block_copy16_t<false>(src, dst, n16, tid, nthreads);
 }
 
 // 32 consecutive bytes of a byte map (one per page) as a 32-bit mask.
@@ -127,15 +135,14 @@ struct VShared {
 // buffer marks the victim map and is appended to the victim list.
 template <bool TRACK>
 __device__ __forceinline__ void track_record(const VArgs &A, const VShared &S, uint32_t *s_track,
-                                             uint32_t *s_sum, uint64_t a, uint32_t reason) {
+                                             uint64_t a, uint32_t reason) {
   if (!TRACK) return;
   const uint64_t off = a - A.pool_base;
   if (off >= A.pool_bytes) return;
   const uint32_t page = (uint32_t)(off >> A.page_shift);
   if (reason == 0) {
     if (S.win_nw != kNone) {
-      const uint32_t lw = (page >> 5) - S.win_fw;
-      if (atomicOr(&s_track[lw], 1u << (page & 31)) == 0) atomicOr(&s_sum[lw >> 5], 1u << (lw & 31));
+      atomicOr(&s_track[(page >> 5) - S.win_fw], 1u << (page & 31));  // result unused: no return
     } else {
       A.dirty[page] = 1;
     }
@@ -165,7 +172,7 @@ __device__ __forceinline__ void rank_violations(VShared &S, uint32_t wave, uint6
 // One wave's range [wbase, wend) of records; NIV < 0: intervals from LDS.
 template <int NIV, bool TRACK>
 __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint32_t *s_track,
-                                               uint32_t *s_sum, uint32_t niv,
+                                               uint32_t niv,
                                                const GLOBAL_AS uint64_t *rec8, bool al16,
                                                uint64_t wbase, uint64_t wend, uint32_t wave,
                                                uint32_t lane) {
@@ -187,22 +194,34 @@ __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint3
     const uint32_t w = (uint32_t)(r & 1u);
     const uint32_t reason = NIV >= 0 ? classify_n<(NIV >= 0 ? NIV : 0)>(R, a, w)
                                      : classify_lds(S.spec, niv, a, w);
-    if (TRACK && valid && w) track_record<TRACK>(A, S, s_track, s_sum, a, reason);
+    if (TRACK && valid && w) track_record<TRACK>(A, S, s_track, a, reason);
     return valid && reason != 0 && ((A.flags >> w) & 1u);
   };
-  // main body: whole steps only, four 16-byte loads in flight, no branches
-  if (al16) {
+  // main body: whole steps only, software pipelined: the next step's four
+  // 16-byte loads are in flight while this step is classified (the last
+  // step reloads itself instead of branching)
+  constexpr uint64_t kS = (uint64_t)kVStep * kVUnroll;
+  if (al16 && c + kS <= wend) {
     const GLOBAL_AS u32x4 *__restrict__ rec4 = (const GLOBAL_AS u32x4 *)rec8;
-    for (; c + kVStep * kVUnroll <= wend; c += kVStep * kVUnroll) {
-      u32x4 q[kVUnroll];
+    u32x4 q[kVUnroll];
 #pragma unroll
-      for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
+    for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
+    for (;;) {
+      const bool more = c + 2 * kS <= wend;
+      const uint64_t cn = more ? c + kS : c;
+      u32x4 nq[kVUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kVUnroll; ++u) nq[u] = rec4[((cn + u * kVStep) >> 1) + lane];
 #pragma unroll
       for (uint32_t u = 0; u < kVUnroll; ++u) {
         const bool b0 = one(((uint64_t)q[u].y << 32) | q[u].x, true);
         const bool b1 = one(((uint64_t)q[u].w << 32) | q[u].z, true);
         rank_violations(S, wave, lt, b0, b1, (uint32_t)(c - wbase) + u * kVStep + 2 * lane, wcnt);
       }
+      c += kS;
+      if (!more) break;
+#pragma unroll
+      for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = nq[u];
     }
   }
   // tail (and 8-byte-aligned arrays): 128 records per step, guarded loads
@@ -239,18 +258,12 @@ template <bool BATCH, bool TRACK>
 __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec single) {
   __shared__ VShared S;
   __shared__ uint32_t s_track[TRACK ? kTrackWords : 1];
-  __shared__ uint32_t s_sum[TRACK ? kTrackWords / 32 : 1];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t tile = blockIdx.x;
 
   if (tid == 0) {
     if (BATCH) {
-      uint32_t lo = 0, hi = A.nlaunch;  // last launch with tile0 <= tile
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (A.launches[mid].tile0 <= tile) lo = mid; else hi = mid;
-      }
-      S.L = A.launches[lo];
+      S.L = A.launches[A.tile_launch[tile]];
     } else {
       S.L = A.single;
     }
@@ -282,10 +295,8 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
       S.win_nw = (fw != kNone && lw - fw + 1 <= kTrackWords) ? lw - fw + 1 : (fw == kNone ? 0u : kNone);
     }
     __syncthreads();
-    if (S.win_nw != kNone) {
+    if (S.win_nw != kNone)
       for (uint32_t j = tid; j < S.win_nw; j += kVThreads) s_track[j] = 0;
-      for (uint32_t j = tid; j < (S.win_nw + 31) / 32; j += kVThreads) s_sum[j] = 0;
-    }
     __syncthreads();
   }
 
@@ -300,7 +311,7 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   const bool al16 = (((uintptr_t)rec) & 15u) == 0;
   uint32_t wcnt = 0;
 #define PHOS_SCAN(N)                                                                          \
-  wcnt = scan_range<N, TRACK>(A, S, s_track, s_sum, niv, rec8, al16, wbase, wend, wave, lane)
+  wcnt = scan_range<N, TRACK>(A, S, s_track, niv, rec8, al16, wbase, wend, wave, lane)
   switch (niv) {
     case 0: PHOS_SCAN(0); break;
     case 1: PHOS_SCAN(1); break;
@@ -319,15 +330,16 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   __syncthreads();
 
   if (TRACK && S.win_nw != kNone && S.win_nw) {
-    // flush the touched words of the window: one plain byte store per page
-    // (the page maps need no atomics, and byte-granular stores from
-    // different L2s never clobber each other)
-    for (uint32_t sw = tid; sw < (S.win_nw + 31) / 32; sw += kVThreads) {
-      for (uint32_t m = s_sum[sw]; m; m &= m - 1) {
-        const uint32_t lw = sw * 32 + __ffs(m) - 1;
-        const uint32_t p0 = (S.win_fw + lw) * 32;
-        for (uint32_t bits = s_track[lw]; bits; bits &= bits - 1) A.dirty[p0 + __ffs(bits) - 1] = 1;
-      }
+    // Flush the window, one word (32 pages) per thread: a plain byte store
+    // per page not yet marked (the page maps need no atomics, and byte
+    // stores from different L2s never clobber each other).  The map only
+    // gains marks between quiesces, so a stale read can only cause a
+    // redundant store, never a missing one.
+    for (uint32_t lw = tid; lw < S.win_nw; lw += kVThreads) {
+      const uint32_t bits = s_track[lw];
+      if (!bits) continue;
+      uint8_t *d = A.dirty + 32ull * (S.win_fw + lw);
+      for (uint32_t m = bits & ~bytes_to_mask(d); m; m &= m - 1) d[__ffs(m) - 1] = 1;
     }
   }
 
@@ -468,10 +480,11 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ============================================================ page copies
-__device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
+// Pool page p <-> image page ip.
+__device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p, uint32_t ip,
+                                          uint32_t tid = ~0u, uint32_t nthreads = 0) {
   const uint64_t pb = 1ull << C.page_shift;
   uint8_t *pool_p = C.pool + ((uint64_t)p << C.page_shift);
-  const uint32_t ip = C.img_page[p];
   uint8_t *img_p;
   if (C.image_chunks) {  // image in pieces of chunk_pages pages
     const uint32_t c = ip / C.chunk_pages;
@@ -482,7 +495,7 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
   }
   const uint4 *src = reinterpret_cast<const uint4 *>(C.to_image ? pool_p : img_p);
   uint4 *dst = reinterpret_cast<uint4 *>(C.to_image ? img_p : pool_p);
-  block_copy16(src, dst, pb >> 4, C.nt != 0);
+  block_copy16(src, dst, pb >> 4, C.nt != 0, tid, nthreads);
 }
 
 // Block-collective: every thread offers at most one candidate page.  Pages
@@ -492,12 +505,13 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p) {
 // before it waits, so no wait can form a cycle.
 template <bool WAIT>
 __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long *extra) {
-  __shared__ uint32_t s_won[kCThreads];
+  __shared__ uint32_t s_won[kCThreads], s_won_ip[kCThreads];
   __shared__ uint32_t s_nwon;
   if (threadIdx.x == 0) s_nwon = 0;
   __syncthreads();
   bool wait = false;
-  if (cand != kNone && C.img_page[cand] != kNone) {
+  const uint32_t ip = cand != kNone ? C.img_page[cand] : kNone;
+  if (ip != kNone) {
     // A plain (possibly L2-stale) read can only lag behind: kDone is final
     // until the next quiesce, so "done" is trusted and anything else goes
     // through the compare-and-swap.
@@ -506,7 +520,9 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
     if (st == kFree) {
       uint32_t exp = kFree;
       if (cas_u32(&C.state[cand], exp, kClaimed)) {
-        s_won[atomicAdd(&s_nwon, 1u)] = cand;
+        const uint32_t slot = atomicAdd(&s_nwon, 1u);
+        s_won[slot] = cand;
+        s_won_ip[slot] = ip;  // image page read once, here
         st = kDone;  // ours: published below
       } else {
         st = exp;
@@ -516,7 +532,7 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   }
   __syncthreads();
   const uint32_t nwon = s_nwon;
-  for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i]);
+  for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i], s_won_ip[i]);
   // Publishing "done".  Checkpoint direction: a waiter only needs this
   // block's reads of the pool to have returned (the image is read after the
   // kernel ends), so waiting for every outstanding access is enough.
@@ -617,23 +633,97 @@ __global__ void __launch_bounds__(kCThreads)
   }
 }
 
-// Background copy: persistent blocks take 4 MiB chunks of pages in order.
-__global__ void __launch_bounds__(kCThreads)
-    background_kernel(CopyArgs C, unsigned long long *chunk_cursor, uint32_t nchunks,
-                      uint32_t chunk_pages) {
-  __shared__ uint32_t s_chunk;
-  for (;;) {
-    if (threadIdx.x == 0) s_chunk = (uint32_t)atomicAdd(chunk_cursor, 1ull);
+// Background copy.  Persistent blocks walk the pool in groups of `grab`
+// pages (64 KiB per group): block b copies groups b, b + grid, b + 2 grid, ...
+// so the whole grid streams through one narrow window of the pool (the
+// measured HBM copy rate falls as the active window widens).  Waves 0..7 copy
+// batch i (`batch` groups) while wave 8 claims batch i + 1, so the claim
+// round trips (image page, page maps, state, compare-and-swap) never stall
+// the copy.
+constexpr uint32_t kBgMaxBatch = 256;  // candidate pages per batch
+
+__device__ __forceinline__ bool bg_live(uint64_t i, uint32_t batch, uint32_t grab, uint32_t n_pages) {
+  return ((i * batch) * gridDim.x + blockIdx.x) * (uint64_t)grab < n_pages;
+}
+
+// Claimer wave: claim the candidate pages of batch i into (s_p, s_ip, *s_n).
+__device__ __forceinline__ void bg_claim_batch(const CopyArgs &C, uint64_t i, uint32_t batch,
+                                               uint32_t grab, uint32_t *s_p, uint32_t *s_ip,
+                                               uint32_t *s_n) {
+  const uint32_t lane = threadIdx.x - kBgCopyThreads;
+  if (lane == 0) *s_n = 0;  // same wave as every append below: ordered
+  const uint32_t nb = batch * grab;
+  for (uint32_t k = lane; k < nb; k += 64) {
+    const uint64_t g = (i * batch + k / grab) * gridDim.x + blockIdx.x;
+    const uint64_t p = g * grab + k % grab;
+    const bool in = p < C.n_pages;
+    const uint64_t q = in ? p : 0;
+    // the independent reads first, so their round trips overlap
+    const uint32_t ip = C.img_page[q];
+    uint32_t st = C.state[q];  // a plain read can only lag: "done" is final
+    // Section 4.3: a page already traced as written is copied by the recopy
+    // anyway; copying it now would be wasted (a stale 0 only means a
+    // redundant copy)
+    const uint32_t traced = C.skip_dirty ? (C.skip_dirty[q] | C.skip_victim[q]) : 0u;
+    if (!in || ip == kNone || traced) continue;
+    if (st == kClaimed) st = ld_relaxed(&C.state[p]);
+    if (st != kFree) continue;
+    uint32_t exp = kFree;
+    if (!cas_u32(&C.state[p], exp, kClaimed)) continue;
+    const uint32_t slot = atomicAdd(s_n, 1u);
+    s_p[slot] = (uint32_t)p;
+    s_ip[slot] = ip;
+  }
+}
+
+__global__ void __launch_bounds__(kBgThreads)
+    background_kernel(CopyArgs C, uint32_t grab, uint32_t batch) {
+  __shared__ uint32_t s_p[2][kBgMaxBatch], s_ip[2][kBgMaxBatch], s_n[2];
+  const uint32_t t = threadIdx.x;
+  const bool claimer = t >= kBgCopyThreads;
+  if (claimer) bg_claim_batch(C, 0, batch, grab, s_p[0], s_ip[0], &s_n[0]);
+  __syncthreads();
+  uint32_t cur = 0, copied = 0;
+  for (uint64_t i = 0; bg_live(i, batch, grab, C.n_pages); ++i) {
+    if (claimer) {
+      bg_claim_batch(C, i + 1, batch, grab, s_p[cur ^ 1], s_ip[cur ^ 1], &s_n[cur ^ 1]);
+    } else {
+      const uint32_t n = s_n[cur];
+      for (uint32_t m = 0; m < n; ++m) copy_page(C, s_p[cur][m], s_ip[cur][m], t, kBgCopyThreads);
+      // towards the pool the writes must reach memory before other XCDs
+      // read the page; towards the image the barrier below is enough (the
+      // host reads the image after the kernel, and the barrier's wait for
+      // this block's loads is what a copy-on-write waiter needs)
+      if (!C.to_image && n) __threadfence();
+    }
     __syncthreads();
-    const uint32_t c = s_chunk;
-    __syncthreads();
-    if (c >= nchunks) break;
-    for (uint32_t g = 0; g < chunk_pages; g += kCThreads) {
-      const uint64_t p = (uint64_t)c * chunk_pages + g + threadIdx.x;
-      const uint32_t cand = (g + threadIdx.x < chunk_pages && p < C.n_pages) ? (uint32_t)p : kNone;
-      claim_copy<false>(cand, C, nullptr);
+    const uint32_t n = s_n[cur];
+    for (uint32_t m = t; m < n; m += kBgThreads)
+      __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    copied += n;
+    __syncthreads();  // list `cur` is free for the claim after next
+    cur ^= 1;
+  }
+  if (t == 0 && copied) atomicAdd(C.stat, (unsigned long long)copied);
+}
+
+// Set the state of every pool page whose image page lies in a flagged image
+// piece (pieces the kernels cannot read, moved by DMA instead); count them.
+__global__ void __launch_bounds__(256)
+    mark_pieces_kernel(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
+                       uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
+                       unsigned long long *count) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  if (p < n_pages) {
+    const uint32_t ip = img_page[p];
+    if (ip != kNone && flag[ip / chunk_pages]) {
+      state[p] = value;
+      hit = true;
     }
   }
+  const uint64_t m = __ballot(hit);
+  if (count && (threadIdx.x & 63u) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
 }
 
 // Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
@@ -667,16 +757,22 @@ __global__ void __launch_bounds__(256)
 }
 
 // Copy the listed pages (no claims: the application is quiesced).
-__global__ void __launch_bounds__(kCThreads)
+__global__ void __launch_bounds__(kBgCopyThreads)
     gather_pages_kernel(CopyArgs C, const uint32_t *list, const unsigned int *count) {
   const uint32_t cnt = *count;
   uint32_t nw = 0;
+  // the next page's list entry and image page are read before this page's copy
+  uint32_t p = blockIdx.x < cnt ? list[blockIdx.x] : kNone;
+  uint32_t ip = p < C.n_pages ? C.img_page[p] : kNone;
   for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const uint32_t p = list[i];
-    if (p < C.n_pages && C.img_page[p] != kNone) {
-      copy_page(C, p);
+    const uint32_t pn = i + gridDim.x < cnt ? list[i + gridDim.x] : kNone;
+    const uint32_t ipn = pn < C.n_pages ? C.img_page[pn] : kNone;
+    if (ip != kNone) {
+      copy_page(C, p, ip);
       ++nw;
     }
+    p = pn;
+    ip = ipn;
   }
   if (threadIdx.x == 0 && nw) atomicAdd(C.stat, (unsigned long long)nw);
 }
@@ -878,11 +974,22 @@ hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &
   return hipGetLastError();
 }
 
-hipError_t launch_background(const CopyArgs &c, unsigned long long *chunk_cursor, uint32_t nchunks,
-                             uint32_t chunk_pages, uint32_t grid, hipStream_t s) {
-  if (!nchunks) return hipSuccess;
-  hipLaunchKernelGGL(background_kernel, dim3(grid), dim3(kCThreads), 0, s, c, chunk_cursor, nchunks,
-                     chunk_pages);
+hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
+                             hipStream_t s) {
+  if (!c.n_pages || !grid) return hipSuccess;
+  if (grab == 0 || grab > kBgMaxBatch) return hipErrorInvalidValue;
+  if (batch == 0) batch = 1;
+  if (batch * grab > kBgMaxBatch) batch = kBgMaxBatch / grab;
+  hipLaunchKernelGGL(background_kernel, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
+                              uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
+                              unsigned long long *count, hipStream_t s) {
+  if (!n_pages) return hipSuccess;
+  hipLaunchKernelGGL(mark_pieces_kernel, dim3((n_pages + 255) / 256), dim3(256), 0, s, img_page,
+                     state, n_pages, chunk_pages, flag, value, count);
   return hipGetLastError();
 }
 
@@ -896,7 +1003,7 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
 
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(gather_pages_kernel, dim3(grid), dim3(kCThreads), 0, s, c, list, count);
+  hipLaunchKernelGGL(gather_pages_kernel, dim3(grid), dim3(kBgCopyThreads), 0, s, c, list, count);
   return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -120,6 +122,9 @@ struct phos_ctx {
 
   uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 24, copy_nt = 0;
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
+  uint32_t tile_max = 8 * kVQuantum;    // largest validation tile (records)
+  uint32_t tile_max_track = 16 * kVQuantum;  // ... with dirty tracking (fewer map flushes)
+  uint32_t bg_batch = 16;               // background groups claimed at once per block
 };
 
 struct phos_ckpt {
@@ -146,6 +151,17 @@ struct phos_rst {
   bool bg_started = false;
   unsigned long long *d_chunks = nullptr;  // image pieces (device table) or nullptr
   uint32_t chunk_pages = 0;
+  // pieces in pageable host memory: the kernels cannot read them, so their
+  // pages are claimed at begin, moved by DMA on a private stream from a
+  // host thread, and published as present when the DMA has landed
+  uint8_t *d_pageable = nullptr;           // per piece: 1 = pageable
+  hipStream_t dma = nullptr;
+  std::thread dma_thread;
+  phos_status dma_status = PHOS_OK;
+  std::string dma_error;
+  ~phos_rst() {
+    if (dma_thread.joinable()) dma_thread.join();
+  }
 };
 
 #define HIP_TRY(x)                                                                  \
@@ -225,8 +241,13 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
     c->n_cu = (uint32_t)prop.multiProcessorCount;
   c->bg_grid = env_u32("PHOS_BG_GRID", c->n_cu);
   c->cow_grid = env_u32("PHOS_COW_GRID", 4 * c->n_cu);
-  c->copy_nt = env_u32("PHOS_COPY_NT", 0);
+  c->bg_batch = env_u32("PHOS_BG_BATCH", 16);
+  c->copy_nt = env_u32("PHOS_COPY_NT", 1);  // streaming copies: keep the application's L2 lines
   c->finish_tiles = env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles);
+  c->tile_max = std::max<uint32_t>(kVQuantum, env_u32("PHOS_VTILE_MAX", 8 * kVQuantum) /
+                                                  kVQuantum * kVQuantum);
+  c->tile_max_track = std::max<uint32_t>(
+      kVQuantum, env_u32("PHOS_VTILE_MAX", 16 * kVQuantum) / kVQuantum * kVQuantum);
   c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
   phos_status st = PHOS_OK;
 #define CK(x)                  \
@@ -484,10 +505,13 @@ static phos_status ensure_workspace(phos_ctx *c, uint64_t ntiles, uint64_t cap) 
 }
 
 // Records per workgroup tile: large tiles amortize the per-tile set-up and
-// the dirty-map flush; small calls keep >= ~512 tiles to fill the GPU.
-static uint32_t pick_tile(uint64_t total) {
+// the dirty-map flush, small ones keep the grid's active window of the
+// record stream narrow (measured faster on HBM); small calls keep >= ~512
+// tiles to fill the GPU.
+static uint32_t pick_tile(const phos_ctx *c, uint64_t total, uint32_t flags) {
+  const uint64_t cap = (flags & PHOS_V_TRACK) ? c->tile_max_track : c->tile_max;
   uint64_t t = kVQuantum;
-  while (t * 2 <= 16ull * kVQuantum && t * 2 * 512 <= total) t *= 2;
+  while (t * 2 <= cap && t * 2 * 512 <= total) t *= 2;
   return (uint32_t)t;
 }
 
@@ -553,7 +577,7 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   if ((n && !d_records) || (cap && !out) || !n_violations || (flags & ~kFlagMask))
     return fail(PHOS_E_INVAL, "phos_validate: bad argument");
   if (((uintptr_t)d_records) & 7) return fail(PHOS_E_INVAL, "records must be 8-byte aligned");
-  const uint32_t tile = pick_tile(n);
+  const uint32_t tile = pick_tile(c, n, flags);
   const uint64_t ntiles = (n + tile - 1) / tile;
   if (ntiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
   DeviceGuard g(c->device);
@@ -588,12 +612,19 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
     total += n[i];
     total_iv += h->iv.size();
   }
-  const uint32_t tile = pick_tile(total);
-  // host image of the descriptor table and the flat interval table
-  std::vector<uint8_t> blob(nlaunch * sizeof(VLaunch) + total_iv * sizeof(DevIv));
+  const uint32_t tile = pick_tile(c, total, flags);
+  uint64_t tiles = 0;
+  for (uint32_t i = 0; i < nlaunch; ++i) tiles += (n[i] + tile - 1) / tile;
+  if (tiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
+  // host image of the descriptor table, the flat interval table and the
+  // launch of every tile
+  const size_t head = nlaunch * sizeof(VLaunch) + total_iv * sizeof(DevIv);
+  std::vector<uint8_t> blob(head + 4 * tiles);
   VLaunch *L = reinterpret_cast<VLaunch *>(blob.data());
   DevIv *IV = reinterpret_cast<DevIv *>(blob.data() + nlaunch * sizeof(VLaunch));
-  uint64_t tiles = 0, ivo = 0;
+  uint32_t *TL = reinterpret_cast<uint32_t *>(blob.data() + head);
+  uint64_t ivo = 0;
+  tiles = 0;
   for (uint32_t i = 0; i < nlaunch; ++i) {
     const HostSpec &h = c->specs[specs[i]];
     L[i].rec = d_records[i];
@@ -603,9 +634,10 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
     L[i].launch_id = h.launch_id;
     L[i].tile0 = (uint32_t)tiles;
     for (const phos_interval &x : h.iv) IV[ivo++] = to_dev(x);
-    tiles += (n[i] + tile - 1) / tile;
+    const uint64_t nt = (n[i] + tile - 1) / tile;
+    for (uint64_t t = 0; t < nt; ++t) TL[tiles + t] = i;
+    tiles += nt;
   }
-  if (tiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
   DeviceGuard g(c->device);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &cs));
@@ -613,8 +645,8 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   if (!capturing) TRY(ensure_workspace(c, tiles, cap));
   else if (tiles > c->tile_cap || cap > c->scratch_cap)
     return fail(PHOS_E_STATE, "workspace must be grown by an uncaptured call first");
-  uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the descriptor blob
-  for (uint8_t b : blob) hsh = (hsh ^ b) * 1099511628211ull;
+  uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the descriptors (the tile map follows)
+  for (size_t i = 0; i < head; ++i) hsh = (hsh ^ blob[i]) * 1099511628211ull;
   phos_ctx::VBatch *hit = nullptr;
   for (auto &e : c->vcache)
     if (e.hash == hsh && e.blob == blob) hit = &e;
@@ -653,6 +685,7 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   VArgs a = base_vargs(c, flags, tile);
   a.launches = reinterpret_cast<const VLaunch *>(hit->dev);
   a.ivs = reinterpret_cast<const DevIv *>(hit->dev + nlaunch * sizeof(VLaunch));
+  a.tile_launch = reinterpret_cast<const uint32_t *>(hit->dev + head);
   a.nlaunch = nlaunch;
   a.ntiles = (uint32_t)tiles;
   static DevSpec unused;  // kernel parameter of the single-launch path
@@ -661,6 +694,8 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
 
 extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
   if (!c) return fail(PHOS_E_INVAL, "phos_track_reset: NULL context");
+  if (c->open_ckpt[PHOS_RECOPY])
+    return fail(PHOS_E_STATE, "the page maps of an open recopy checkpoint cannot be reset");
   DeviceGuard g(c->device);
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, s));
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, s));
@@ -713,22 +748,25 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
   return a;
 }
 
-static uint32_t chunk_pages(phos_ctx *c) {
-  // The paper's preemptible copy unit: 4 MiB (Section 5).
-  return std::max<uint32_t>(1, (4u << 20) >> c->page_shift);
-}
-
 static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a,
                                          hipStream_t stream) {
-  const uint32_t cp = chunk_pages(c);
-  const uint32_t nchunks = (c->n_pages + cp - 1) / cp;
-  HIP_TRY(launch_background(a, &s.counters[0], nchunks, cp, std::min(c->bg_grid, nchunks), stream));
+  (void)s;
+  // groups of 64 KiB: one page at 64 KiB pages, 16 at 4 KiB pages
+  const uint32_t grab = std::max<uint32_t>(1, (64u << 10) >> c->page_shift);
+  const uint32_t groups = (c->n_pages + grab - 1) / grab;
+  HIP_TRY(launch_background(a, grab, std::max<uint32_t>(1, c->bg_batch), std::min(c->bg_grid, groups),
+                            stream));
   return PHOS_OK;
 }
 
 static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
-                                    hipStream_t stream) {
-  return start_background_args(c, s, copy_args(c, s, image, to_image, &s.counters[1]), stream);
+                                    hipStream_t stream, bool skip_traced = false) {
+  CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
+  if (skip_traced) {  // recopy: pages traced as written are left to the recopy
+    a.skip_dirty = c->d_dirty;
+    a.skip_victim = c->d_victim;
+  }
+  return start_background_args(c, s, a, stream);
 }
 
 // Pages of the intervals with any of `modes`, clamped to the pool.
@@ -784,7 +822,7 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   k->copy = copy;
   k->slot = &s;
   if (!(flags & PHOS_CKPT_DEFER_BACKGROUND)) {
-    phos_status st = start_background(c, s, k->image, true, copy);
+    phos_status st = start_background(c, s, k->image, true, copy, protocol == PHOS_RECOPY);
     if (st == PHOS_OK && (hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming) != hipSuccess ||
                           hipEventRecord(k->bg_done, copy) != hipSuccess))
       st = fail(PHOS_E_HIP, "background completion event");
@@ -843,7 +881,7 @@ extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
   HIP_TRY(hipEventRecord(e, app));
   HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
   if (!k->bg_started) {
-    TRY(start_background(c, s, k->image, true, k->copy));
+    TRY(start_background(c, s, k->image, true, k->copy, true));
     k->bg_started = true;
   }
   HIP_TRY(launch_pagelist(c->d_dirty, c->d_victim, c->nwords, c->n_pages, s.list, s.list_count,
@@ -871,6 +909,9 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
   if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_end: NULL checkpoint");
   phos_ctx *c = k->ctx;
   DeviceGuard g(c->device);
+  // ending is a quiesce point: a recopy checkpoint not yet recopied is
+  // recopied now (its background copy left the traced pages to the recopy)
+  if (k->protocol == PHOS_RECOPY && !k->recopied) TRY(phos_ckpt_recopy(k, app));
   Slot &s = *k->slot;
   hipEvent_t e;
   HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -931,9 +972,27 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
                                 const void *const *chunks, uint32_t nchunks, uint64_t chunk_bytes,
                                 hipStream_t copy, phos_rst **out);
 
+// Can this device's kernels read the memory at p (device memory or pinned
+// host memory)?  Pageable host memory cannot be read without page faults.
+static bool device_readable(const void *p) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type != hipMemoryTypeUnregistered;
+}
+
 extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const void *image,
                                           hipStream_t copy, phos_rst **out) {
   if (!image) return fail(PHOS_E_INVAL, "phos_restore_begin: NULL image");
+  if (c && !device_readable(image)) {
+    // a pageable image is one piece that the DMA path moves
+    const uint64_t cb = std::max<uint64_t>(c->page_bytes, (c->image_bytes + c->page_bytes - 1) /
+                                                              c->page_bytes * c->page_bytes);
+    const void *one[1] = {image};
+    return restore_open(c, flags, image, one, 1, cb, copy, out);
+  }
   return restore_open(c, flags, image, nullptr, 0, 0, copy, out);
 }
 
@@ -974,16 +1033,77 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
   r->image = (const uint8_t *)image;
   r->copy = copy;
   r->slot = &s;
+  bool any_pageable = false;
+  std::function<void()> start_dma;
   if (chunks) {
     std::vector<unsigned long long> tab(nchunks);
-    for (uint32_t i = 0; i < nchunks; ++i) tab[i] = reinterpret_cast<uintptr_t>(chunks[i]);
-    if (hipMalloc((void **)&r->d_chunks, 8ull * nchunks) != hipSuccess ||
-        hipMemcpy(r->d_chunks, tab.data(), 8ull * nchunks, hipMemcpyHostToDevice) != hipSuccess) {
-      if (r->d_chunks) (void)hipFree(r->d_chunks);
-      delete r;
-      return fail(PHOS_E_NOMEM, "restore piece table");
+    std::vector<uint8_t> pageable(nchunks, 0);
+    for (uint32_t i = 0; i < nchunks; ++i) {
+      pageable[i] = device_readable(chunks[i]) ? 0 : 1;
+      any_pageable |= pageable[i] != 0;
+      // a pageable piece's address never reaches a kernel
+      tab[i] = pageable[i] ? 0 : reinterpret_cast<uintptr_t>(chunks[i]);
     }
     r->chunk_pages = (uint32_t)(chunk_bytes >> c->page_shift);
+    hipError_t e = hipMalloc((void **)&r->d_chunks, 8ull * nchunks);
+    if (e == hipSuccess) e = hipMemcpy(r->d_chunks, tab.data(), 8ull * nchunks, hipMemcpyHostToDevice);
+    if (e == hipSuccess && any_pageable) {
+      e = hipMalloc((void **)&r->d_pageable, nchunks);
+      if (e == hipSuccess) e = hipMemcpy(r->d_pageable, pageable.data(), nchunks, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->dma, hipStreamNonBlocking);
+      // claim the pageable pieces' pages before any kernel can claim them
+      if (e == hipSuccess)
+        e = launch_mark_pieces(c->d_img_page, s.state, c->n_pages, r->chunk_pages, r->d_pageable,
+                               kClaimed, nullptr, c->aux);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
+    }
+    if (e != hipSuccess) {
+      if (r->d_chunks) (void)hipFree(r->d_chunks);
+      if (r->d_pageable) (void)hipFree(r->d_pageable);
+      if (r->dma) (void)hipStreamDestroy(r->dma);
+      delete r;
+      return fail(PHOS_E_NOMEM, "restore piece table: %s", hipGetErrorString(e));
+    }
+    if (any_pageable) {
+      // the DMA of the pageable pieces runs from its own host thread (a copy
+      // from pageable memory can block the thread that issues it), started
+      // once the background copy is enqueued
+      std::vector<const uint8_t *> src(reinterpret_cast<const uint8_t *const *>(chunks),
+                                       reinterpret_cast<const uint8_t *const *>(chunks) + nchunks);
+      std::vector<uint8_t> pg(pageable);
+      start_dma = [r, c, src, pg, chunk_bytes, &s]() {
+        if (hipSetDevice(c->device) != hipSuccess) {
+          r->dma_status = PHOS_E_HIP;
+          r->dma_error = "hipSetDevice in the restore DMA thread";
+          return;
+        }
+        uint64_t io = 0;  // image offset of the buffer (buffers back to back)
+        for (const phos_buffer &b : c->bufs) {
+          for (uint64_t off = 0; off < b.bytes;) {
+            const uint64_t x = io + off, k = x / chunk_bytes, in = x - k * chunk_bytes;
+            const uint64_t n = std::min(b.bytes - off, chunk_bytes - in);
+            if (pg[k]) {
+              const hipError_t e2 = hipMemcpyAsync(reinterpret_cast<void *>(b.base + off), src[k] + in,
+                                                   n, hipMemcpyHostToDevice, r->dma);
+              if (e2 != hipSuccess) {
+                r->dma_status = PHOS_E_HIP;
+                r->dma_error = hipGetErrorString(e2);
+                return;
+              }
+            }
+            off += n;
+          }
+          io += b.bytes;
+        }
+        // present once the DMA has landed (stream order)
+        const hipError_t e3 = launch_mark_pieces(c->d_img_page, s.state, c->n_pages, r->chunk_pages,
+                                                 r->d_pageable, kDone, &s.counters[3], r->dma);
+        if (e3 != hipSuccess) {
+          r->dma_status = PHOS_E_HIP;
+          r->dma_error = hipGetErrorString(e3);
+        }
+      };
+    }
   }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
     phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1]), copy);
@@ -993,6 +1113,7 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     }
     r->bg_started = true;
   }
+  if (start_dma) r->dma_thread = std::thread(start_dma);
   c->open_rst = r;
   *out = r;
   return PHOS_OK;
@@ -1037,17 +1158,23 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
     TRY(start_background_args(c, s, rst_args(r, &s.counters[1]), r->copy));
     r->bg_started = true;
   }
+  if (r->dma_thread.joinable()) r->dma_thread.join();
+  if (r->dma) HIP_TRY(hipStreamSynchronize(r->dma));
+  if (r->dma_status != PHOS_OK) return fail(r->dma_status, "restore DMA: %s", r->dma_error.c_str());
   HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, r->copy));
   HIP_TRY(hipStreamSynchronize(r->copy));
   HIP_TRY(hipStreamSynchronize(app));
   if (stats) {
     stats->bg_pages = c->h_pinned[1];
     stats->demand_pages = c->h_pinned[2];
+    stats->dma_pages = c->h_pinned[3];
   }
   bool timeout = false;
   TRY(read_err(c, r->copy, &timeout));
   c->open_rst = nullptr;
   if (r->d_chunks) (void)hipFree(r->d_chunks);
+  if (r->d_pageable) (void)hipFree(r->d_pageable);
+  if (r->dma) (void)hipStreamDestroy(r->dma);
   delete r;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the pool is not valid");
   return PHOS_OK;

@@ -84,7 +84,8 @@ struct Bulk {        // an admitted checkpoint / restore with work left to issue
 
 struct Iter {        // one iteration of the batched copy
   phos_batch *b = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr;     // the iteration's copy finished
+  hipEvent_t up = nullptr;     // its work queue is uploaded
   bool busy = false;
   std::vector<std::pair<uint32_t, uint32_t>> finishing;  // (request, id in the iteration)
 };
@@ -138,7 +139,7 @@ class Server {
   unsigned long long gpu0_ = 0, *h_clock_ = nullptr;  // clock calibration
   double host0_ms_ = 0;
 
-  hipStream_t bulk_ = nullptr, burst_ = nullptr;
+  hipStream_t bulk_ = nullptr, burst_ = nullptr, upload_ = nullptr;
   Iter iters_[2];
   phos_batch *plain_ = nullptr;
   uint32_t *d_identity_ = nullptr, *d_err_ = nullptr;
@@ -177,6 +178,7 @@ phos_status Server::setup() {
   }
   HIP_TRY(hipStreamCreateWithFlags(&bulk_, hipStreamNonBlocking));
   HIP_TRY(hipStreamCreateWithFlags(&burst_, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking));
   std::vector<uint32_t> ident(max_pages);
   std::iota(ident.begin(), ident.end(), 0u);
   HIP_TRY(hipMalloc((void **)&d_identity_, 4 * max_pages));
@@ -190,6 +192,7 @@ phos_status Server::setup() {
     for (Iter &it : iters_) {
       TRY(phos_batch_create(dev_, kIterMaxSegs, kIterMaxReqs, &cfg_.cfg, &it.b));
       HIP_TRY(hipEventCreateWithFlags(&it.ev, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&it.up, hipEventDisableTiming));
     }
   } else {
     TRY(phos_batch_create(dev_, max_segs, 1, &cfg_.cfg, &plain_));
@@ -203,8 +206,9 @@ void Server::cleanup() {
   for (Iter &it : iters_) {
     if (it.b) phos_batch_destroy(it.b);
     if (it.ev) (void)hipEventDestroy(it.ev);
+    if (it.up) (void)hipEventDestroy(it.up);
     it.b = nullptr;
-    it.ev = nullptr;
+    it.ev = it.up = nullptr;
   }
   if (plain_) phos_batch_destroy(plain_);
   plain_ = nullptr;
@@ -219,7 +223,8 @@ void Server::cleanup() {
   d_faulted_ = nullptr;
   if (bulk_) (void)hipStreamDestroy(bulk_);
   if (burst_) (void)hipStreamDestroy(burst_);
-  bulk_ = burst_ = nullptr;
+  if (upload_) (void)hipStreamDestroy(upload_);
+  bulk_ = burst_ = upload_ = nullptr;
 }
 
 // Section 6 machinery on a request's own pages: its records are offsets into
@@ -353,13 +358,18 @@ phos_status Server::run_batched() {
       bursts.pop_back();
       progress = true;
     }
-    // issue iterations into free slots: shortest remaining work first (a
-    // small request never waits behind a large one; the largest takes what
-    // is left of each iteration), at most quantum bytes per request
+    // issue iterations into free slots, at most quantum bytes per request:
+    // small requests (at most small_bytes left) first, shortest first, so
+    // they never wait behind a large one; the large ones in arrival order,
+    // so they are not starved by a stream of medium ones
     for (Iter &it : iters_) {
       if (it.busy || bulk.empty()) continue;
-      std::stable_sort(bulk.begin(), bulk.end(),
-                       [](const Bulk &x, const Bulk &y) { return x.left < y.left; });
+      const uint64_t small = cfg_.small_bytes;
+      std::stable_sort(bulk.begin(), bulk.end(), [small](const Bulk &x, const Bulk &y) {
+        const bool xs = x.left <= small, ys = y.left <= small;
+        if (xs != ys) return xs;
+        return xs ? x.left < y.left : x.idx < y.idx;
+      });
       segbuf_.clear();
       uint64_t budget = cfg_.iter_bytes;
       uint32_t nreq = 0;
@@ -395,7 +405,12 @@ phos_status Server::run_batched() {
       bulk.erase(std::remove_if(bulk.begin(), bulk.end(), [](const Bulk &b) { return !b.left; }),
                  bulk.end());
       if (segbuf_.empty()) continue;
-      TRY(phos_batch_copy(it.b, segbuf_.data(), segbuf_.size(), bulk_));
+      // the work queue goes up on its own stream while the previous
+      // iteration still copies; the copy stream only waits for the upload
+      TRY(phos_batch_load(it.b, segbuf_.data(), segbuf_.size(), upload_));
+      HIP_TRY(hipEventRecord(it.up, upload_));
+      HIP_TRY(hipStreamWaitEvent(bulk_, it.up, 0));
+      TRY(phos_batch_run(it.b, bulk_));
       HIP_TRY(hipEventRecord(it.ev, bulk_));
       it.busy = true;
       ++iterations_;

@@ -55,7 +55,8 @@ class phos_ckpt_stats(ctypes.Structure):
 
 
 class phos_rst_stats(ctypes.Structure):
-    _fields_ = [("bg_pages", ctypes.c_uint64), ("demand_pages", ctypes.c_uint64)]
+    _fields_ = [("bg_pages", ctypes.c_uint64), ("demand_pages", ctypes.c_uint64),
+                ("dma_pages", ctypes.c_uint64)]
 
 
 class phos_batch_cfg(ctypes.Structure):
@@ -389,7 +390,8 @@ class phos_serve_cfg(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("page_bytes", ctypes.c_uint32),
                 ("budget_bytes", ctypes.c_uint64), ("d_arena", ctypes.c_void_p),
                 ("quantum_bytes", ctypes.c_uint64), ("iter_bytes", ctypes.c_uint64),
-                ("cfg", phos_batch_cfg), ("keep", ctypes.c_uint32), ("_pad", ctypes.c_uint32)]
+                ("cfg", phos_batch_cfg), ("keep", ctypes.c_uint32), ("_pad", ctypes.c_uint32),
+                ("small_bytes", ctypes.c_uint64)]
 
 
 class phos_serve_out(ctypes.Structure):

@@ -109,9 +109,13 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(env.pool_host(), host)
 
 
-@pytest.mark.parametrize("drain", [False, True])
-def test_soft_recopy_config1(env, drain):
+@pytest.mark.parametrize("mode", ["plain", "drain", "deferred", "implicit"])
+def test_soft_recopy_config1(env, mode):
+    """deferred: the background copy starts at the recopy, when every page the
+    window wrote is already traced, so it copies exactly the untraced pages;
+    implicit: no recopy call, phos_ckpt_end recopies."""
     phos, w, T = env.phos, env.world, env.T
+    drain = mode == "drain"
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
     host = synth.content_host(w.seed, 0, w.pool_bytes)
@@ -121,7 +125,8 @@ def test_soft_recopy_config1(env, drain):
                             host, snap_before=(T2 - T1,), window=(0, T2 - T1), keep_violations=False)
     image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
     himg = T.empty(env.image_bytes, dtype=T.uint8, pin_memory=True) if drain else None
-    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, himg, env.copy)
+    flags = phos.CKPT_DEFER_BACKGROUND if mode == "deferred" else 0
+    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, flags, image, himg, env.copy)
     out, cnt = env.violations_buffers(N)
     for j in range(T1, T2):
         L = launches[j]
@@ -130,7 +135,12 @@ def test_soft_recopy_config1(env, drain):
         _validate(env, s, r, out, cnt)
         env.mutate(L, r.data_ptr(), N)
         phos.phos_spec_release(env.ctx, s)
-    phos.phos_ckpt_recopy(ck, env.app)
+    if mode != "implicit":
+        phos.phos_ckpt_recopy(ck, env.app)
+    else:
+        with pytest.raises(phos.PhosError) as e:  # its recopy list lives in the maps
+            phos.phos_track_reset(env.ctx, env.app)
+        assert e.value.status == phos.E_STATE
     d = phos.phos_track_read(env.ctx, 0, w.n_pages)
     v = phos.phos_track_read(env.ctx, 1, w.n_pages)
     assert np.array_equal(d, oracle.pages_to_bitmap(res.dirty, w.n_pages))
@@ -142,6 +152,11 @@ def test_soft_recopy_config1(env, drain):
         assert np.array_equal(himg.numpy(), want), "drained host image differs"
     rset = (res.dirty | res.victim) & _buffer_pages(w)
     assert stats.recopy_pages == int(rset.sum())
+    n_img_pages = env.image_bytes // w.page_bytes
+    if mode == "deferred":
+        assert stats.bg_pages + stats.recopy_pages == n_img_pages
+    else:
+        assert n_img_pages - stats.recopy_pages <= stats.bg_pages <= n_img_pages
     # launches after t2 leave the image unchanged
     _run_plain(env, st, host, T2, T2 + 5)
     assert np.array_equal(image.cpu().numpy(), want)
@@ -198,22 +213,33 @@ def test_cow_straight_to_pinned_host(env):
     assert np.array_equal(himg.numpy(), want)
 
 
-@pytest.mark.parametrize("mode", ["background", "deferred", "prefetch", "host_image", "chunked"])
+@pytest.mark.parametrize("mode", ["background", "deferred", "prefetch", "host_image", "chunked",
+                                  "mixed", "pageable"])
 def test_concurrent_restore_config1(env, mode):
+    """chunked: pinned host pieces; mixed: every other piece pageable (moved by
+    DMA, never read by a kernel); pageable: one pageable host image."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)[:20]
     st = Stream(env, launches)
     host = synth.content_host(w.seed, 0, w.pool_bytes)
     image_h = oracle.snapshot(host, env.base, env.table)
     chunks = None
+    dma_want = 0
     if mode == "host_image":
         image = T.from_numpy(image_h.copy()).pin_memory()
-    elif mode == "chunked":
-        # the image in pinned host pieces of 3 MiB (the last one partly used)
+    elif mode == "pageable":
+        image = T.from_numpy(image_h.copy())
+        dma_want = env.image_bytes // w.page_bytes
+    elif mode in ("chunked", "mixed"):
+        # the image in host pieces of 3 MiB (the last one partly used)
         cb = 3 << 20
         chunks = []
-        for o in range(0, image_h.size, cb):
-            piece = T.zeros(cb, dtype=T.uint8).pin_memory()
+        for k, o in enumerate(range(0, image_h.size, cb)):
+            piece = T.zeros(cb, dtype=T.uint8)
+            if mode == "chunked" or k % 2 == 0:
+                piece = piece.pin_memory()
+            else:
+                dma_want += (min(cb, image_h.size - o)) // w.page_bytes
             piece[:min(cb, image_h.size - o)] = T.from_numpy(image_h[o:o + cb].copy())
             chunks.append(piece)
         image = None
@@ -223,7 +249,7 @@ def test_concurrent_restore_config1(env, mode):
     T.cuda.synchronize()
     flags = {"background": 0, "deferred": phos.RST_DEFER_BACKGROUND,
              "prefetch": phos.RST_DEFER_BACKGROUND | phos.RST_PREFETCH_SPEC,
-             "host_image": 0, "chunked": 0}[mode]
+             "host_image": 0, "chunked": 0, "mixed": 0, "pageable": 0}[mode]
     if chunks is not None:
         rs = phos.phos_restore_begin_chunked(env.ctx, flags, chunks, 3 << 20, env.copy)
     else:
@@ -257,7 +283,8 @@ def test_concurrent_restore_config1(env, mode):
         synth.apply_writes_host(host, env.base, w.seed, L.k, rec_h)
         phos.phos_spec_release(env.ctx, s)
     stats = phos.phos_restore_end(rs, env.app)
-    assert stats.bg_pages + stats.demand_pages == env.image_bytes // w.page_bytes
+    assert stats.dma_pages == dma_want
+    assert stats.bg_pages + stats.demand_pages + stats.dma_pages == env.image_bytes // w.page_bytes
     inbuf = np.repeat(_buffer_pages(w).astype(bool), w.page_bytes)
     got = env.pool_host()
     assert np.array_equal(got[inbuf], host[inbuf]), "restored pool + launches != oracle"

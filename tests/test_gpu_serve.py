@@ -56,22 +56,25 @@ def test_serving_alone_equals_mix_equals_oracle():
     reqs, keep, bursts = bench.serving_inputs(torch, phos, synth, trace, PAGE, src.data_ptr(), SEED)
     src_h = src.cpu().numpy()
     results = {}
-    for mode in (phos.SERVE_PLAIN, phos.SERVE_BATCHED):
+    # plain; batched shortest-remaining-first; batched small-first then arrival order
+    runs = ((phos.SERVE_PLAIN, 0), (phos.SERVE_BATCHED, 2**64 - 1), (phos.SERVE_BATCHED, 8 << 20))
+    for mode, small in runs:
         dst.zero_()
         bench.reseed_bursts(torch, synth, bursts, SEED)
         cfg = phos.phos_serve_cfg(mode, PAGE, budget, dst.data_ptr(), 4 << 20, 16 << 20,
-                                  phos.phos_batch_cfg(256 << 10, 2, 512), 1, 0)
+                                  phos.phos_batch_cfg(256 << 10, 2, 512), 1, 0, small)
         outs, st = phos.phos_serve_run(0, cfg, reqs, len(trace))
         assert st.max_active >= 1 and all(o.latency_ms >= 0 for o in outs[:len(trace)])
         host = dst.cpu().numpy()
-        results[mode] = [host[o.dst_off:o.dst_off + q.size].copy()
-                         for o, q in zip(outs[:len(trace)], trace)]
+        results[(mode, small)] = [host[o.dst_off:o.dst_off + q.size].copy()
+                                  for o, q in zip(outs[:len(trace)], trace)]
         if mode == phos.SERVE_BATCHED:
             assert st.iterations >= 1
     for j, q in enumerate(trace):
         want = _expected(q, src_h, PAGE)
-        assert np.array_equal(results[phos.SERVE_PLAIN][j], want), f"request {j} alone"
-        assert np.array_equal(results[phos.SERVE_BATCHED][j], want), f"request {j} in the mix"
+        for key in runs:
+            where = "alone" if key[0] == phos.SERVE_PLAIN else f"in the mix (small_bytes {key[1]})"
+            assert np.array_equal(results[key][j], want), f"request {j} {where}"
     del keep
 
 

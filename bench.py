@@ -636,12 +636,18 @@ def run_cold_start(args):
     wall0 = time.perf_counter()
     e_begin.record(app)
     cpy.wait_event(e_begin)
+    h0 = time.perf_counter()
     rs = phos.phos_restore_begin_chunked(ctx, 0, pieces, cb, cpy)
+    h_begin = time.perf_counter() - h0
     e_bg.record(cpy)
+    h_first = 0.0
     for j, L in enumerate(launches):
         r = recs.data_ptr() + j * n_rec * 8
         ev0[j].record(app)
+        h1 = time.perf_counter()
         phos.phos_restore_on_demand(rs, specs[j], r, n_rec, app, faulted)
+        if j == 0:
+            h_first = time.perf_counter() - h1
         ev1[j].record(app)
         synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, r, n_rec, app)
     e_end.record(app)
@@ -653,6 +659,9 @@ def run_cold_start(args):
     stream_ms = e_begin.elapsed_time(e_end)
     stalls = np.array([ev0[j].elapsed_time(ev1[j]) for j in range(n_launch)])
     h2d = w.image_bytes / (max(full, stream_ms) / 1e3) / 1e9
+    log(f"[bench] host: begin call {h_begin * 1e3:.2f} ms, first on-demand call {h_first * 1e3:.2f} ms; "
+        f"GPU: app stream reaches launch 0 after {e_begin.elapsed_time(ev0[0]):.2f} ms, "
+        f"its fault-in takes {ev0[0].elapsed_time(ev1[0]):.2f} ms")
     log(f"[bench] time to first kernel {ttfk:.2f} ms; fully present {full:.1f} ms; stream "
         f"{stream_ms:.1f} ms; demand pages {st.demand_pages}, background {st.bg_pages}, "
         f"DMA {st.dma_pages}; "

@@ -28,11 +28,26 @@ __device__ __forceinline__ uint32_t ld_relaxed(uint32_t *p) {
 __device__ __forceinline__ void st_release(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+// The claim (free -> claimed) publishes nothing and the claimer reads
+// nothing another block produced under it, so it needs no ordering: a
+// relaxed compare-and-swap (an acquire-release one would write back the
+// whole L2 before every claim).  Data is ordered by the "done" store.
 __device__ __forceinline__ bool cas_u32(uint32_t *p, uint32_t &expected, uint32_t desired) {
-  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Workgroup barrier that orders LDS only: it does not wait for the block's
+// outstanding global stores (a __syncthreads would drain them).  The signal
+// fences keep the compiler from moving any memory access across it.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 // Block-cooperative 16-byte copy, eight loads in flight per thread;
 // NT: non-temporal (streaming) loads and stores.
@@ -691,17 +706,20 @@ __global__ void __launch_bounds__(kBgThreads)
       const uint32_t n = s_n[cur];
       for (uint32_t m = 0; m < n; ++m) copy_page(C, s_p[cur][m], s_ip[cur][m], t, kBgCopyThreads);
       // towards the pool the writes must reach memory before other XCDs
-      // read the page; towards the image the barrier below is enough (the
-      // host reads the image after the kernel, and the barrier's wait for
-      // this block's loads is what a copy-on-write waiter needs)
+      // read the page
       if (!C.to_image && n) __threadfence();
     }
-    __syncthreads();
+    // Towards the image no store needs to land before "done": the host
+    // reads the image after the kernel, and a copy-on-write waiter only
+    // needs this block's reads of the pool to have returned, which every
+    // wave's stores already depended on when it reached the barrier.  So
+    // the barrier orders LDS only and the copy's stores stay in flight.
+    lds_barrier();
     const uint32_t n = s_n[cur];
     for (uint32_t m = t; m < n; m += kBgThreads)
       __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     copied += n;
-    __syncthreads();  // list `cur` is free for the claim after next
+    lds_barrier();  // list `cur` is free for the claim after next
     cur ^= 1;
   }
   if (t == 0 && copied) atomicAdd(C.stat, (unsigned long long)copied);

@@ -124,7 +124,8 @@ struct phos_ctx {
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
   uint32_t tile_max = 8 * kVQuantum;    // largest validation tile (records)
   uint32_t tile_max_track = 16 * kVQuantum;  // ... with dirty tracking (fewer map flushes)
-  uint32_t bg_batch = 16;               // background groups claimed at once per block
+  uint32_t bg_batch = 64;               // background groups claimed at once per block
+  uint32_t bg_batch_pcie = 4;           // ... when the copy reads host memory
 };
 
 struct phos_ckpt {
@@ -155,6 +156,7 @@ struct phos_rst {
   // pages are claimed at begin, moved by DMA on a private stream from a
   // host thread, and published as present when the DMA has landed
   uint8_t *d_pageable = nullptr;           // per piece: 1 = pageable
+  bool host_image = false;                 // the image (or a piece) is in host memory
   hipStream_t dma = nullptr;
   std::thread dma_thread;
   phos_status dma_status = PHOS_OK;
@@ -241,7 +243,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
     c->n_cu = (uint32_t)prop.multiProcessorCount;
   c->bg_grid = env_u32("PHOS_BG_GRID", c->n_cu);
   c->cow_grid = env_u32("PHOS_COW_GRID", 4 * c->n_cu);
-  c->bg_batch = env_u32("PHOS_BG_BATCH", 16);
+  c->bg_batch = env_u32("PHOS_BG_BATCH", 64);
+  c->bg_batch_pcie = env_u32("PHOS_BG_BATCH_PCIE", 4);
   c->copy_nt = env_u32("PHOS_COPY_NT", 1);  // streaming copies: keep the application's L2 lines
   c->finish_tiles = env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles);
   c->tile_max = std::max<uint32_t>(kVQuantum, env_u32("PHOS_VTILE_MAX", 8 * kVQuantum) /
@@ -748,14 +751,16 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
   return a;
 }
 
+// over_pcie: the copy reads host memory, so a claimed-but-not-copied page
+// takes PCIe time to arrive; claim less far ahead for on-demand waiters.
 static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a,
-                                         hipStream_t stream) {
+                                         hipStream_t stream, bool over_pcie = false) {
   (void)s;
   // groups of 64 KiB: one page at 64 KiB pages, 16 at 4 KiB pages
   const uint32_t grab = std::max<uint32_t>(1, (64u << 10) >> c->page_shift);
   const uint32_t groups = (c->n_pages + grab - 1) / grab;
-  HIP_TRY(launch_background(a, grab, std::max<uint32_t>(1, c->bg_batch), std::min(c->bg_grid, groups),
-                            stream));
+  const uint32_t batch = std::max<uint32_t>(1, over_pcie ? c->bg_batch_pcie : c->bg_batch);
+  HIP_TRY(launch_background(a, grab, batch, std::min(c->bg_grid, groups), stream));
   return PHOS_OK;
 }
 
@@ -974,12 +979,14 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
 
 // Can this device's kernels read the memory at p (device memory or pinned
 // host memory)?  Pageable host memory cannot be read without page faults.
-static bool device_readable(const void *p) {
+static bool device_readable(const void *p, bool *in_host = nullptr) {
   hipPointerAttribute_t at;
   if (hipPointerGetAttributes(&at, p) != hipSuccess) {
     (void)hipGetLastError();
+    if (in_host) *in_host = true;
     return false;
   }
+  if (in_host) *in_host = at.type != hipMemoryTypeDevice;
   return at.type != hipMemoryTypeUnregistered;
 }
 
@@ -1033,13 +1040,16 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
   r->image = (const uint8_t *)image;
   r->copy = copy;
   r->slot = &s;
+  if (!chunks) (void)device_readable(image, &r->host_image);
   bool any_pageable = false;
   std::function<void()> start_dma;
   if (chunks) {
     std::vector<unsigned long long> tab(nchunks);
     std::vector<uint8_t> pageable(nchunks, 0);
     for (uint32_t i = 0; i < nchunks; ++i) {
-      pageable[i] = device_readable(chunks[i]) ? 0 : 1;
+      bool in_host = false;
+      pageable[i] = device_readable(chunks[i], &in_host) ? 0 : 1;
+      r->host_image |= in_host;
       any_pageable |= pageable[i] != 0;
       // a pageable piece's address never reaches a kernel
       tab[i] = pageable[i] ? 0 : reinterpret_cast<uintptr_t>(chunks[i]);
@@ -1106,7 +1116,7 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     }
   }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
-    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1]), copy);
+    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1]), copy, r->host_image);
     if (st != PHOS_OK) {
       delete r;
       return st;
@@ -1155,7 +1165,7 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   HIP_TRY(hipStreamWaitEvent(r->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!r->bg_started) {
-    TRY(start_background_args(c, s, rst_args(r, &s.counters[1]), r->copy));
+    TRY(start_background_args(c, s, rst_args(r, &s.counters[1]), r->copy, r->host_image));
     r->bg_started = true;
   }
   if (r->dma_thread.joinable()) r->dma_thread.join();

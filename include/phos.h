@@ -232,9 +232,13 @@ phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nword
  * bytes, layout as written by a checkpoint).  The background copy of every
  * page into the pool starts on copy_stream unless PHOS_RST_DEFER_BACKGROUND.
  * Device or pinned host memory is read by the kernels directly; a pageable
- * host image cannot be, so its pages are claimed at begin and moved by DMA
- * from a library thread on a private stream (launches that need them wait
- * until they land).  One restore per context at a time. */
+ * host image cannot be, so its pages are held at begin and moved by DMA from
+ * a library thread on a private stream, the pages a launch asks for first
+ * (the launch waits until they land).  That private stream must not share a
+ * hardware queue with app_stream: HIP maps streams round-robin onto
+ * GPU_MAX_HW_QUEUES queues (4 by default), so raise it when more streams are
+ * in use; a wait that cannot be served ends in E_TIMEOUT.  One restore per
+ * context at a time. */
 phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
                                hipStream_t copy_stream, phos_rst **out);
 

@@ -12,6 +12,9 @@ namespace phos {
 constexpr uint32_t kMaxIv = 64;          // intervals per speculated set
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no buffer / no image page"
 constexpr uint32_t kFree = 0, kClaimed = 1, kDone = 2;  // per-page copy state
+// restore from pageable host memory: the page is held by the host's DMA
+// (kHost), or held and asked for by a waiting launch (kWanted)
+constexpr uint32_t kHost = 3, kWanted = 4;
 
 // Validation tiling: 256 threads = 4 wave64s; each wave owns a contiguous
 // quarter of the tile; each lane reads two records (one 16-byte load) per
@@ -93,6 +96,17 @@ struct CopyArgs {
   // Recopy background only: pages already marked in either page map are left
   // to the recopy (nullptr: copy every page).
   const uint8_t *skip_dirty = nullptr, *skip_victim = nullptr;
+  // Restore with pageable pieces: a waiter that finds a page held by the
+  // host asks for it here (pinned host memory: [0] reservation count, then
+  // want_cap entries, written once per page with system-scope atomics so the
+  // host sees them at once) and waits for the page's state to become done,
+  // which the host publishes with a small kernel after the page's DMA.
+  uint32_t *want = nullptr;
+  uint32_t want_cap = 0;
+  // Restore: blocks copying pages a launch needs now (on demand) count
+  // themselves here while they copy; the background copy claims no new
+  // pages while it is nonzero, so on-demand copies get the link first.
+  unsigned long long *demand = nullptr;
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.
@@ -141,6 +155,8 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
                            phos_violation *out, uint64_t cap, hipStream_t s);
 hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
                       uint32_t max_grid, hipStream_t s);
+hipError_t launch_mark_list(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
+                            unsigned long long *count, hipStream_t s);
 hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
                               uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
                               unsigned long long *count, hipStream_t s);
@@ -151,7 +167,7 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s);
 hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,
-                         unsigned long long *faulted, hipStream_t s);
+                         unsigned long long *faulted, uint32_t max_grid, hipStream_t s);
 hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32_t *bits,
                                  hipStream_t s);
 hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t *bits,

@@ -531,8 +531,18 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
     // until the next quiesce, so "done" is trusted and anything else goes
     // through the compare-and-swap.
     uint32_t st = C.state[cand];
-    if (st == kClaimed) st = ld_relaxed(&C.state[cand]);
-    if (st == kFree) {
+    if (st != kFree && st != kDone) st = ld_relaxed(&C.state[cand]);
+    if (st == kHost || st == kWanted) {
+      // held by the host's DMA: the first waiter asks the host for it
+      uint32_t exp = kHost;
+      if (st == kHost && C.want && cas_u32(&C.state[cand], exp, kWanted)) {
+        const uint32_t i =
+            __hip_atomic_fetch_add(&C.want[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (i < C.want_cap)  // past the cap the bulk DMA brings it
+          __hip_atomic_store(&C.want[1 + i], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      st = kWanted;
+    } else if (st == kFree) {
       uint32_t exp = kFree;
       if (cas_u32(&C.state[cand], exp, kClaimed)) {
         const uint32_t slot = atomicAdd(&s_nwon, 1u);
@@ -543,10 +553,14 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
         st = exp;
       }
     }
-    wait = (st == kClaimed);
+    wait = (st == kClaimed || st == kWanted);
   }
   __syncthreads();
   const uint32_t nwon = s_nwon;
+  // Section 6: a launch is waiting for these pages: hold the background copy
+  // back while they move (this block waits for nobody until it lets go)
+  const bool priority = nwon && C.demand && !C.to_image;
+  if (priority && threadIdx.x == 0) atomicAdd(C.demand, 1ull);
   for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i], s_won_ip[i]);
   // Publishing "done".  Checkpoint direction: a waiter only needs this
   // block's reads of the pool to have returned (the image is read after the
@@ -568,6 +582,7 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   if (threadIdx.x == 0 && nwon) {
     atomicAdd(C.stat, (unsigned long long)nwon);
     if (extra) atomicAdd(extra, (unsigned long long)nwon);
+    if (priority) atomicAdd(C.demand, ~0ull);  // -1
   }
   if (WAIT && wait) {
     uint32_t it = 0;
@@ -701,6 +716,15 @@ __global__ void __launch_bounds__(kBgThreads)
   uint32_t cur = 0, copied = 0;
   for (uint64_t i = 0; bg_live(i, batch, grab, C.n_pages); ++i) {
     if (claimer) {
+      // Section 6: on-demand copies go first: claim nothing new while a
+      // launch's pages are moving (bounded: this is a policy, not a
+      // correctness wait; the pages already claimed are still copied)
+      if (C.demand) {
+        uint32_t it = 0;
+        while (__hip_atomic_load(C.demand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
+               ++it < C.spin_limit)
+          __builtin_amdgcn_s_sleep(16);
+      }
       bg_claim_batch(C, i + 1, batch, grab, s_p[cur ^ 1], s_ip[cur ^ 1], &s_n[cur ^ 1]);
     } else {
       const uint32_t n = s_n[cur];
@@ -723,6 +747,15 @@ __global__ void __launch_bounds__(kBgThreads)
     cur ^= 1;
   }
   if (t == 0 && copied) atomicAdd(C.stat, (unsigned long long)copied);
+}
+
+// Publish pool pages the host has copied by DMA: list[0, n) -> kDone.
+__global__ void __launch_bounds__(256)
+    mark_list_kernel(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
+                     unsigned long long *count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) __hip_atomic_store(&state[list[i]], value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (count && i == 0) atomicAdd(count, (unsigned long long)n);
 }
 
 // Set the state of every pool page whose image page lies in a flagged image
@@ -797,23 +830,30 @@ __global__ void __launch_bounds__(kBgCopyThreads)
 
 // Section 6: bring in every not-yet-present page (inside a buffer) that the
 // launch's records touch, before the launch runs.
+// A persistent grid of at most one block per CU walks the records in chunks:
+// its blocks may wait (for pages another block or the host is bringing in),
+// and waiting blocks must never fill the GPU, or the kernel that publishes
+// those pages could find no room to run.
 constexpr uint32_t kDemandPerThread = 4;
 __global__ void __launch_bounds__(kCThreads)
     demand_kernel(CopyArgs C, const uint64_t *rec, uint64_t n, uint64_t pool_base,
                   unsigned long long *faulted) {
-  const uint64_t base = (uint64_t)blockIdx.x * kCThreads * kDemandPerThread;
+  const uint64_t per = (uint64_t)kCThreads * kDemandPerThread;
+  const uint64_t nchunks = (n + per - 1) / per;
   const uint64_t pool_bytes = (uint64_t)C.n_pages << C.page_shift;
-  for (uint32_t u = 0; u < kDemandPerThread; ++u) {
-    const uint64_t i = base + (uint64_t)u * kCThreads + threadIdx.x;
-    uint32_t cand = kNone;
-    if (i < n) {
-      const uint64_t off = (rec[i] & ~7ull) - pool_base;
-      if (off < pool_bytes) {
-        const uint32_t p = (uint32_t)(off >> C.page_shift);
-        if (C.img_page[p] != kNone && C.state[p] != kDone) cand = p;
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    for (uint32_t u = 0; u < kDemandPerThread; ++u) {
+      const uint64_t i = ch * per + (uint64_t)u * kCThreads + threadIdx.x;
+      uint32_t cand = kNone;
+      if (i < n) {
+        const uint64_t off = (rec[i] & ~7ull) - pool_base;
+        if (off < pool_bytes) {
+          const uint32_t p = (uint32_t)(off >> C.page_shift);
+          if (C.img_page[p] != kNone && C.state[p] != kDone) cand = p;
+        }
       }
+      claim_copy<true>(cand, C, faulted);
     }
-    claim_copy<true>(cand, C, faulted);
   }
 }
 
@@ -1011,6 +1051,15 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
   return hipGetLastError();
 }
 
+hipError_t launch_mark_list(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
+                            unsigned long long *count, hipStream_t s) {
+  if (!n) return hipSuccess;
+  // one-wave blocks: the smallest footprint, so it finds room beside waiters
+  hipLaunchKernelGGL(mark_list_kernel, dim3((n + 63) / 64), dim3(64), 0, s, state, list, n, value,
+                     count);
+  return hipGetLastError();
+}
+
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s) {
   if (!nwords) return hipSuccess;
@@ -1026,11 +1075,12 @@ hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const un
 }
 
 hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,
-                         unsigned long long *faulted, hipStream_t s) {
+                         unsigned long long *faulted, uint32_t max_grid, hipStream_t s) {
   if (!n) return hipSuccess;
   const uint64_t per = (uint64_t)kCThreads * kDemandPerThread;
-  hipLaunchKernelGGL(demand_kernel, dim3((unsigned)((n + per - 1) / per)), dim3(kCThreads), 0, s, c,
-                     rec, n, pool_base, faulted);
+  const uint64_t chunks = (n + per - 1) / per;
+  const uint32_t grid = (uint32_t)(chunks < max_grid ? chunks : (max_grid ? max_grid : 1));
+  hipLaunchKernelGGL(demand_kernel, dim3(grid), dim3(kCThreads), 0, s, c, rec, n, pool_base, faulted);
   return hipGetLastError();
 }
 

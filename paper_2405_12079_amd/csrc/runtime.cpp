@@ -70,6 +70,7 @@ struct phos_ctx {
   uint64_t pool_base = 0, pool_bytes = 0;
   uint32_t page_bytes = 0, page_shift = 0, n_pages = 0, nwords = 0;
   std::vector<phos_buffer> bufs;
+  std::vector<uint32_t> h_img_page, h_img_pool;  // pool page -> image page, and back
   uint64_t image_bytes = 0;
   uint32_t n_cu = 256;
 
@@ -119,8 +120,9 @@ struct phos_ctx {
 
   hipStream_t aux = nullptr;     // private stream for synchronous reads
   unsigned long long *h_pinned = nullptr;  // small pinned readback area
+  uint32_t *h_want = nullptr;  // pageable restore: pages asked for by waiting launches (pinned)
 
-  uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 24, copy_nt = 0;
+  uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 22, copy_nt = 0;
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
   uint32_t tile_max = 8 * kVQuantum;    // largest validation tile (records)
   uint32_t tile_max_track = 16 * kVQuantum;  // ... with dirty tracking (fewer map flushes)
@@ -143,6 +145,10 @@ struct phos_ckpt {
   bool cow_streams_many = false;
 };
 
+constexpr uint32_t kWantCap = 16384;      // asked-for pages the host can see per restore
+constexpr uint32_t kDmaRunPages = 64;     // largest single bulk DMA (4 MiB at 64 KiB)
+constexpr uint32_t kDmaUnitPages = 256;   // pages per bulk DMA unit (16 MiB at 64 KiB)
+
 struct phos_rst {
   phos_ctx *ctx;
   uint32_t flags;
@@ -156,6 +162,8 @@ struct phos_rst {
   // pages are claimed at begin, moved by DMA on a private stream from a
   // host thread, and published as present when the DMA has landed
   uint8_t *d_pageable = nullptr;           // per piece: 1 = pageable
+  bool want = false;                       // waiters ask the host (the context's h_want)
+  uint32_t *d_list = nullptr;              // pages the host publishes as present
   bool host_image = false;                 // the image (or a piece) is in host memory
   hipStream_t dma = nullptr;
   std::thread dma_thread;
@@ -206,6 +214,7 @@ static phos_status ctx_free(phos_ctx *c) {
   }
   if (c->h_vstage) (void)hipHostFree(c->h_vstage);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->h_want) (void)hipHostFree(c->h_want);
   if (c->v_evt) (void)hipEventDestroy(c->v_evt);
   if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -251,7 +260,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
                                                   kVQuantum * kVQuantum);
   c->tile_max_track = std::max<uint32_t>(
       kVQuantum, env_u32("PHOS_VTILE_MAX", 16 * kVQuantum) / kVQuantum * kVQuantum);
-  c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
+  c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 22);
   phos_status st = PHOS_OK;
 #define CK(x)                  \
   do {                         \
@@ -297,6 +306,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       !hipck(hipEventCreateWithFlags(&c->vstage_evt, hipEventDisableTiming), "hipEventCreate") ||
       !hipck(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking), "hipStreamCreate") ||
       !hipck(hipHostMalloc((void **)&c->h_pinned, 4096, hipHostMallocDefault), "hipHostMalloc") ||
+      !hipck(hipHostMalloc((void **)&c->h_want, 4ull * (kWantCap + 1), hipHostMallocDefault),
+             "hipHostMalloc") ||
       !hipck(hipDeviceSynchronize(), "hipDeviceSynchronize")) {
     ctx_free(c);
     return PHOS_E_HIP;
@@ -345,6 +356,10 @@ extern "C" phos_status phos_buffers_register(phos_ctx *c, const phos_buffer *buf
   HIP_TRY(hipMemcpy(c->d_img_page, img_page.data(), c->n_pages * 4ull, hipMemcpyHostToDevice));
   c->bufs.assign(bufs, bufs + n);
   c->image_bytes = img;
+  c->h_img_page.swap(img_page);
+  c->h_img_pool.assign(img >> c->page_shift, kNone);
+  for (uint32_t p = 0; p < c->n_pages; ++p)
+    if (c->h_img_page[p] != kNone) c->h_img_pool[c->h_img_page[p]] = p;
   return PHOS_OK;
 }
 
@@ -970,6 +985,9 @@ static CopyArgs rst_args(phos_rst *r, unsigned long long *stat) {
   CopyArgs a = copy_args(r->ctx, *r->slot, const_cast<uint8_t *>(r->image), false, stat);
   a.image_chunks = r->d_chunks;
   a.chunk_pages = r->chunk_pages;
+  a.want = r->want ? r->ctx->h_want : nullptr;
+  a.want_cap = r->want ? kWantCap : 0;
+  a.demand = &r->slot->counters[4];
   return a;
 }
 
@@ -1018,6 +1036,89 @@ extern "C" phos_status phos_restore_begin_chunked(phos_ctx *c, uint32_t flags,
   return restore_open(c, flags, chunks[0], chunks, nchunks, chunk_bytes, copy, out);
 }
 
+// The host side of a restore from pageable pieces, on its own thread and
+// stream: it moves those pages by DMA in units of kDmaUnitPages image pages,
+// and between units serves the pages waiting launches asked for (a kernel
+// cannot read pageable memory, so the host is their fault handler).  Pages
+// are published by a small kernel on the same stream after their DMA; the
+// waiters poll device memory, so waiting adds no traffic on PCIe.
+static void restore_dma_main(phos_rst *r, std::vector<const uint8_t *> src, std::vector<uint8_t> pg,
+                             uint64_t chunk_bytes) {
+  phos_ctx *c = r->ctx;
+  Slot &s = *r->slot;
+  auto failed = [r](const char *what, hipError_t e) {
+    r->dma_status = PHOS_E_HIP;
+    r->dma_error = std::string(what) + ": " + hipGetErrorString(e);
+  };
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return failed("hipSetDevice", e);
+  const uint64_t pb = c->page_bytes, img_pages = c->image_bytes >> c->page_shift;
+  const uint64_t cp = chunk_bytes >> c->page_shift;
+  std::vector<uint8_t> served(img_pages, 0);
+  std::vector<uint32_t> list;
+  uint32_t scanned = 0;
+  const uint32_t *want = c->h_want;  // pinned: kernels append with system-scope atomics
+  // copy image pages [i0, i1) (pool-contiguous, one piece) and list them
+  auto copy_run = [&](uint64_t i0, uint64_t i1) -> hipError_t {
+    const uint64_t k = i0 / cp;
+    return hipMemcpyAsync(reinterpret_cast<void *>(c->pool_base + ((uint64_t)c->h_img_pool[i0] << c->page_shift)),
+                          src[k] + (i0 - k * cp) * pb, (i1 - i0) * pb, hipMemcpyHostToDevice, r->dma);
+  };
+  // present once the DMA has landed: a small kernel after it, in stream order
+  auto publish = [&]() -> hipError_t {
+    if (list.empty()) return hipSuccess;
+    hipError_t e2 = hipMemcpyAsync(r->d_list, list.data(), 4 * list.size(), hipMemcpyHostToDevice, r->dma);
+    if (e2 == hipSuccess)
+      e2 = launch_mark_list(s.state, r->d_list, (uint32_t)list.size(), kDone, &s.counters[3], r->dma);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(r->dma);  // d_list is reused next round
+    list.clear();
+    return e2;
+  };
+  // the pages waiting launches asked for, each copied alone
+  auto serve = [&]() -> hipError_t {
+    hipError_t e2 = hipSuccess;
+    const uint32_t n = std::min<uint32_t>(__atomic_load_n(&want[0], __ATOMIC_ACQUIRE), kWantCap);
+    if (scanned >= n) return hipSuccess;
+    for (; scanned < n; ++scanned) {
+      const uint32_t p = __atomic_load_n(&want[1 + scanned], __ATOMIC_ACQUIRE);
+      if (p == kNone) break;  // reserved, not written yet: next round
+      if (p >= c->n_pages) continue;
+      const uint32_t ip = c->h_img_page[p];
+      if (ip == kNone || !pg[ip / cp] || served[ip]) continue;
+      served[ip] = 1;
+      if ((e2 = copy_run(ip, ip + 1)) != hipSuccess) return e2;
+      list.push_back(p);
+      if (list.size() == kDmaUnitPages && (e2 = publish()) != hipSuccess) return e2;
+    }
+    return publish();
+  };
+  for (uint64_t u0 = 0; u0 < img_pages; u0 += kDmaUnitPages) {
+    if ((e = serve()) != hipSuccess) return failed("serving asked-for pages", e);
+    const uint64_t u1 = std::min<uint64_t>(img_pages, u0 + kDmaUnitPages);
+    uint64_t run = u0;
+    for (uint64_t ip = u0; ip <= u1; ++ip) {
+      // a run breaks at the unit end, a served page, a piece boundary or a
+      // pool discontinuity (buffer boundary)
+      const bool take = ip < u1 && pg[ip / cp] && !served[ip];
+      const bool joins = take && ip > run && ip - run < kDmaRunPages && ip / cp == run / cp &&
+                         c->h_img_pool[ip] == c->h_img_pool[ip - 1] + 1;
+      if (ip > run && !joins) {
+        if ((e = copy_run(run, ip)) != hipSuccess) return failed("DMA", e);
+        run = ip;
+        // between runs (at most 4 MiB), the pages launches are waiting for
+        if ((e = serve()) != hipSuccess) return failed("serving asked-for pages", e);
+      }
+      if (!take) {
+        run = ip + 1;
+        continue;
+      }
+      served[ip] = 1;
+      list.push_back(c->h_img_pool[ip]);
+    }
+    if ((e = publish()) != hipSuccess) return failed("publishing pages", e);
+  }
+}
+
 static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
                                 const void *const *chunks, uint32_t nchunks, uint64_t chunk_bytes,
                                 hipStream_t copy, phos_rst **out) {
@@ -1061,15 +1162,21 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
       e = hipMalloc((void **)&r->d_pageable, nchunks);
       if (e == hipSuccess) e = hipMemcpy(r->d_pageable, pageable.data(), nchunks, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->dma, hipStreamNonBlocking);
-      // claim the pageable pieces' pages before any kernel can claim them
+      if (e == hipSuccess) e = hipMalloc((void **)&r->d_list, 4ull * kDmaUnitPages);
+      r->want = true;
+      c->h_want[0] = 0;  // no kernel of this context runs now (begin is a quiesce point)
+      for (uint32_t i = 1; i <= kWantCap; ++i) c->h_want[i] = kNone;
+      // hold the pageable pieces' pages for the host before any kernel can
+      // claim them
       if (e == hipSuccess)
         e = launch_mark_pieces(c->d_img_page, s.state, c->n_pages, r->chunk_pages, r->d_pageable,
-                               kClaimed, nullptr, c->aux);
+                               kHost, nullptr, c->aux);
       if (e == hipSuccess) e = hipStreamSynchronize(c->aux);
     }
     if (e != hipSuccess) {
       if (r->d_chunks) (void)hipFree(r->d_chunks);
       if (r->d_pageable) (void)hipFree(r->d_pageable);
+      if (r->d_list) (void)hipFree(r->d_list);
       if (r->dma) (void)hipStreamDestroy(r->dma);
       delete r;
       return fail(PHOS_E_NOMEM, "restore piece table: %s", hipGetErrorString(e));
@@ -1081,38 +1188,7 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
       std::vector<const uint8_t *> src(reinterpret_cast<const uint8_t *const *>(chunks),
                                        reinterpret_cast<const uint8_t *const *>(chunks) + nchunks);
       std::vector<uint8_t> pg(pageable);
-      start_dma = [r, c, src, pg, chunk_bytes, &s]() {
-        if (hipSetDevice(c->device) != hipSuccess) {
-          r->dma_status = PHOS_E_HIP;
-          r->dma_error = "hipSetDevice in the restore DMA thread";
-          return;
-        }
-        uint64_t io = 0;  // image offset of the buffer (buffers back to back)
-        for (const phos_buffer &b : c->bufs) {
-          for (uint64_t off = 0; off < b.bytes;) {
-            const uint64_t x = io + off, k = x / chunk_bytes, in = x - k * chunk_bytes;
-            const uint64_t n = std::min(b.bytes - off, chunk_bytes - in);
-            if (pg[k]) {
-              const hipError_t e2 = hipMemcpyAsync(reinterpret_cast<void *>(b.base + off), src[k] + in,
-                                                   n, hipMemcpyHostToDevice, r->dma);
-              if (e2 != hipSuccess) {
-                r->dma_status = PHOS_E_HIP;
-                r->dma_error = hipGetErrorString(e2);
-                return;
-              }
-            }
-            off += n;
-          }
-          io += b.bytes;
-        }
-        // present once the DMA has landed (stream order)
-        const hipError_t e3 = launch_mark_pieces(c->d_img_page, s.state, c->n_pages, r->chunk_pages,
-                                                 r->d_pageable, kDone, &s.counters[3], r->dma);
-        if (e3 != hipSuccess) {
-          r->dma_status = PHOS_E_HIP;
-          r->dma_error = hipGetErrorString(e3);
-        }
-      };
+      start_dma = [r, src, pg, chunk_bytes]() { restore_dma_main(r, src, pg, chunk_bytes); };
     }
   }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
@@ -1144,7 +1220,7 @@ extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const
     HIP_TRY(launch_cow(rst_args(r, &s.counters[2]), pr, none, true, c->cow_grid, app));
   }
   CopyArgs a = rst_args(r, &s.counters[2]);
-  HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, app));
+  HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, c->n_cu, app));
   return PHOS_OK;
 }
 
@@ -1184,6 +1260,7 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   c->open_rst = nullptr;
   if (r->d_chunks) (void)hipFree(r->d_chunks);
   if (r->d_pageable) (void)hipFree(r->d_pageable);
+  if (r->d_list) (void)hipFree(r->d_list);
   if (r->dma) (void)hipStreamDestroy(r->dma);
   delete r;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the pool is not valid");

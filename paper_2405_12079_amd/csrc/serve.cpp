@@ -136,6 +136,7 @@ class Server {
   uint32_t done_ = 0, active_ = 0, max_active_ = 0;
   uint64_t bulk_bytes_ = 0, iterations_ = 0;
   uint32_t page_shift_ = 16;
+  uint32_t n_cu_ = 256;
   unsigned long long gpu0_ = 0, *h_clock_ = nullptr;  // clock calibration
   double host0_ms_ = 0;
 
@@ -156,6 +157,11 @@ phos_status Server::setup() {
       (cfg_.page_bytes & (cfg_.page_bytes - 1)))
     return fail(PHOS_E_INVAL, "serve: bad configuration");
   page_shift_ = (uint32_t)__builtin_ctz(cfg_.page_bytes);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev_) == hipSuccess && prop.multiProcessorCount > 0)
+      n_cu_ = (uint32_t)prop.multiProcessorCount;
+  }
   uint64_t max_pages = 1, max_segs = 1;
   for (uint32_t i = 0; i < n_; ++i) {
     const phos_serve_req &r = reqs_[i];
@@ -241,11 +247,11 @@ phos_status Server::launch_burst(uint32_t i, uint64_t dst, hipStream_t s) {
   c.page_shift = page_shift_;
   c.n_pages = (uint32_t)(r.bytes >> page_shift_);
   c.to_image = 0;
-  c.spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 24);
+  c.spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 22);
   c.nt = 0;
   c.chunk_pages = 0;
   c.image_chunks = nullptr;  // the request's image is one piece
-  HIP_TRY(launch_demand(c, r.d_records, r.nrec, 0, nullptr, s));
+  HIP_TRY(launch_demand(c, r.d_records, r.nrec, 0, nullptr, n_cu_, s));
   return PHOS_OK;
 }
 

@@ -31,12 +31,6 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# HIP maps streams round-robin onto GPU_MAX_HW_QUEUES hardware queues (4 by
-# default); the application, copy and library streams used here must not
-# share one, or the concurrent copies would serialize behind the application
-# (and a restore's host-side DMA behind a launch waiting for it).  Set before
-# the HIP runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
 KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
@@ -681,7 +675,10 @@ def run_cold_start(args):
         f"its fault-in takes {ev0[0].elapsed_time(ev1[0]):.2f} ms")
     log(f"[bench] time to first kernel {ttfk:.2f} ms; fully present {full:.1f} ms; stream "
         f"{stream_ms:.1f} ms; demand pages {st.demand_pages}, background {st.bg_pages}, "
-        f"DMA {st.dma_pages}; "
+        f"DMA {st.dma_pages} ({st.asked_pages} asked for, first queued after "
+        f"{st.dma_first_issue_ms:.1f} ms, landed after {st.dma_first_copy_ms:.1f} ms, "
+        f"published after {st.dma_first_ms:.1f} ms, "
+        f"done after {st.dma_ms:.1f} ms); "
         f"stall p50 {np.percentile(stalls, 50) * 1e3:.1f} us p99 {np.percentile(stalls, 99) * 1e3:.1f} us")
     res = {
         "metric": "cold-start restore: time-to-first-kernel; PCIe GB/s of the concurrent restore",
@@ -700,7 +697,8 @@ def run_cold_start(args):
         "restore_h2d_GBps": round(h2d, 2),
         "stop_the_world_h2d_GBps": round(w.image_bytes / stw_ms / 1e6, 2),
         "demand_pages": int(st.demand_pages), "background_pages": int(st.bg_pages),
-        "dma_pages": int(st.dma_pages),
+        "dma_pages": int(st.dma_pages), "dma_asked_pages": int(st.asked_pages),
+        "dma_ms": round(st.dma_ms, 1),
         "stall_ms": {"p50": round(float(np.percentile(stalls, 50)), 4),
                      "p99": round(float(np.percentile(stalls, 99)), 4),
                      "max": round(float(stalls.max()), 3)},

@@ -120,6 +120,11 @@ typedef struct {
   uint64_t bg_pages;     /* pages brought in by the background restore */
   uint64_t demand_pages; /* pages brought in before a launch           */
   uint64_t dma_pages;    /* pages of pageable image pieces (DMA)       */
+  uint64_t asked_pages;  /* ... of which launches asked for first        */
+  double dma_ms;         /* host time from begin until the DMA finished */
+  double dma_first_ms;   /* ... until its first batch of pages was published */
+  double dma_first_issue_ms;  /* ... until its first copy was queued        */
+  double dma_first_copy_ms;   /* ... until that batch's copies had landed   */
 } phos_rst_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -127,7 +132,22 @@ typedef struct {
 /* Create a context for the pool [pool_base, pool_base + pool_bytes) on HIP
  * device `device`.  pool_base must be page aligned; pool_bytes a multiple of
  * page_bytes; page_bytes a power of two in [4 KiB, 2 MiB].  The caller owns
- * the pool memory.  E_INVAL on bad sizes, E_NOMEM / E_HIP on allocation. */
+ * the pool memory.  E_INVAL on bad sizes, E_NOMEM / E_HIP on allocation.
+ *
+ * Tuning, read from the environment here (defaults in brackets):
+ *   PHOS_SPIN_LIMIT      polls before a device wait gives up [1 << 22]
+ *   PHOS_BG_GRID         background copy blocks [CUs]; PHOS_COW_GRID [4 x CUs]
+ *   PHOS_BG_BATCH        pages a background block claims per batch [64];
+ *                        PHOS_BG_BATCH_PCIE when the image is in host memory [4]
+ *   PHOS_COPY_NT         streaming (non-temporal) device copies [1]
+ *   PHOS_VTILE_MAX       largest validation tile, records [16384 / 32768 tracked]
+ *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles order in one kernel [4096]
+ *   PHOS_RST_PAUSE       restore: polls (about 0.5 us each) the background
+ *                        holds back per batch while on-demand copies run [64];
+ *                        0 lets them share the link
+ *   PHOS_RST_DEEP_DEMAND / PHOS_RST_DEEP_BG  restore from host memory: 16
+ *                        loads in flight per thread in on-demand [1] /
+ *                        background [0] copies */
 phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes, uint32_t page_bytes,
                         phos_ctx **out);
 /* Synchronizes the device, frees everything the context owns. */
@@ -163,8 +183,9 @@ phos_status phos_spec_release(phos_ctx *ctx, phos_spec spec);
 /* Section 4.1 runtime validation of one launch's access stream.  Each record
  * whose access [a, a+8) is not inside a speculated interval holding the mode
  * it needs is a violation (reads checked iff PHOS_V_READS, writes iff
- * PHOS_V_WRITES).  Violations are written to `out` (device memory, cap
- * entries) in ascending record index, and the count to *n_violations (device
+ * PHOS_V_WRITES).  Violations are written to `out` (device memory, 16-byte
+ * aligned, cap entries; E_INVAL if misaligned) in ascending record index,
+ * and the count to *n_violations (device
  * memory, one uint64_t).  With PHOS_V_TRACK the dirty / victim bitmaps are
  * updated.  d_records: device memory, 8-byte aligned (16-byte alignment is
  * faster).  Asynchronous on `stream`; if *n_violations > cap the contents of
@@ -232,13 +253,11 @@ phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nword
  * bytes, layout as written by a checkpoint).  The background copy of every
  * page into the pool starts on copy_stream unless PHOS_RST_DEFER_BACKGROUND.
  * Device or pinned host memory is read by the kernels directly; a pageable
- * host image cannot be, so its pages are held at begin and moved by DMA from
- * a library thread on a private stream, the pages a launch asks for first
- * (the launch waits until they land).  That private stream must not share a
- * hardware queue with app_stream: HIP maps streams round-robin onto
- * GPU_MAX_HW_QUEUES queues (4 by default), so raise it when more streams are
- * in use; a wait that cannot be served ends in E_TIMEOUT.  One restore per
- * context at a time. */
+ * host image cannot be, so its pages are held at begin and moved by the copy
+ * engines (HSA runtime copies, no HIP stream or kernel) from a library
+ * thread, the pages a launch asks for first (the launch waits until they
+ * land).  E_HIP if that DMA failed (or no HSA agent matches the device);
+ * E_TIMEOUT if a device wait expired.  One restore per context at a time. */
 phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
                                hipStream_t copy_stream, phos_rst **out);
 

@@ -91,6 +91,8 @@ struct CopyArgs {
   uint32_t to_image = 0;                 // 1: pool -> image (checkpoint); 0: image -> pool (restore)
   uint32_t spin_limit = 0;
   uint32_t nt = 0;                       // non-temporal page copies
+  uint32_t deep = 0;                     // copies keep 16 loads in flight per thread
+  uint32_t pause_limit = 0;              // background: longest hold (polls) per batch
   uint32_t chunk_pages = 0;              // pages per image piece (with image_chunks)
   const unsigned long long *image_chunks = nullptr;  // image pieces (device table) or nullptr
   // Recopy background only: pages already marked in either page map are left
@@ -155,8 +157,6 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
                            phos_violation *out, uint64_t cap, hipStream_t s);
 hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
                       uint32_t max_grid, hipStream_t s);
-hipError_t launch_mark_list(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
-                            unsigned long long *count, hipStream_t s);
 hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
                               uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
                               unsigned long long *count, hipStream_t s);

@@ -49,9 +49,10 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Block-cooperative 16-byte copy, eight loads in flight per thread;
+// Block-cooperative 16-byte copy, U loads in flight per thread (8; 16 when
+// the source sits across PCIe, where latency, not HBM, sets the rate);
 // NT: non-temporal (streaming) loads and stores.
-template <bool NT>
+template <bool NT, int U>
 __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
                                                uint4 *__restrict__ dst_, uint64_t n16,
                                                uint32_t tid, uint32_t nthreads) {
@@ -59,13 +60,13 @@ __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
   u32x4 *__restrict__ dst = reinterpret_cast<u32x4 *>(dst_);
   const uint64_t T = nthreads;
   uint64_t i = tid;
-  for (; i + 7 * T < n16; i += 8 * T) {
-    u32x4 v[8];
+  for (; i + (U - 1) * T < n16; i += U * T) {
+    u32x4 v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < U; ++u)
       v[u] = NT ? __builtin_nontemporal_load(src + i + u * T) : src[i + u * T];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < U; ++u) {
       if (NT) __builtin_nontemporal_store(v[u], dst + i + u * T);
       else dst[i + u * T] = v[u];
     }
@@ -73,16 +74,22 @@ __device__ __forceinline__ void block_copy16_t(const uint4 *__restrict__ src_,
   for (; i < n16; i += T) dst[i] = src[i];
 }
 // tid / nthreads: this thread among the threads sharing the copy (default:
-// the whole block)
+// the whole block); deep: 16 loads in flight per thread
 __device__ __forceinline__ void block_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                              uint64_t n16, bool nt = false,
-                                             uint32_t tid = ~0u, uint32_t nthreads = 0) {
+                                             uint32_t tid = ~0u, uint32_t nthreads = 0,
+                                             bool deep = false) {
   if (tid == ~0u) {
     tid = threadIdx.x;
     nthreads = blockDim.x;
   }
-  if (nt) block_copy16_t<true>(src, dst, n16, tid, nthreads);
-  else block_copy16_t<false>(src, dst, n16, tid, nthreads);
+  if (deep) {
+    if (nt) block_copy16_t<true, 16>(src, dst, n16, tid, nthreads);
+    else block_copy16_t<false, 16>(src, dst, n16, tid, nthreads);
+  } else {
+    if (nt) block_copy16_t<true, 8>(src, dst, n16, tid, nthreads);
+    else block_copy16_t<false, 8>(src, dst, n16, tid, nthreads);
+  }
 }
 
 // 32 consecutive bytes of a byte map (one per page) as a 32-bit mask.
@@ -486,16 +493,33 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     s[t] += x;
     __syncthreads();
+  }  // s: inclusive prefix of the segment's tile counts
+  // wave w moves tiles w, w + 16, ... of this segment, one violation per
+  // lane, as two 16-byte loads and stores
+  const uint32_t wave = t >> 6, lane = t & 63u;
+  const unsigned long long base = seg_prefix[blockIdx.x];
+  for (uint32_t k = wave; k < 1024; k += 16) {
+    const uint32_t tk = blockIdx.x * 1024 + k;
+    if (tk >= ntiles) break;
+    const uint32_t ck = s[k] - (k ? s[k - 1] : 0u);
+    if (!ck) continue;
+    const unsigned long long dst = base + s[k] - ck, src = tile_off[tk];
+    for (uint32_t i = lane; i < ck; i += 64) {
+      if (dst + i >= cap || src + i >= scratch_cap) continue;
+      const u32x4 *from = reinterpret_cast<const u32x4 *>(scratch + src + i);
+      u32x4 *to = reinterpret_cast<u32x4 *>(out + dst + i);
+      const u32x4 a0 = from[0], a1 = from[1];
+      to[0] = a0;
+      to[1] = a1;
+    }
   }
-  if (!c) return;
-  const unsigned long long dst = seg_prefix[blockIdx.x] + s[t] - c;
-  const unsigned long long src = tile_off[tile];
-  for (uint32_t i = 0; i < c; ++i)
-    if (dst + i < cap && src + i < scratch_cap) out[dst + i] = scratch[src + i];
 }
 
 // ============================================================ page copies
 // Pool page p <-> image page ip.
+// DEEP: 16 loads in flight per thread (kernel instances for images across
+// PCIe; the others keep the smaller register footprint)
+template <bool DEEP = false>
 __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p, uint32_t ip,
                                           uint32_t tid = ~0u, uint32_t nthreads = 0) {
   const uint64_t pb = 1ull << C.page_shift;
@@ -510,7 +534,7 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p, uint32_
   }
   const uint4 *src = reinterpret_cast<const uint4 *>(C.to_image ? pool_p : img_p);
   uint4 *dst = reinterpret_cast<uint4 *>(C.to_image ? img_p : pool_p);
-  block_copy16(src, dst, pb >> 4, C.nt != 0, tid, nthreads);
+  block_copy16(src, dst, pb >> 4, C.nt != 0, tid, nthreads, DEEP);
 }
 
 // Block-collective: every thread offers at most one candidate page.  Pages
@@ -518,7 +542,7 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p, uint32_
 // by this block, then published as done; with WAIT, a thread whose page is
 // claimed by someone else waits until it is done.  Every claimer publishes
 // before it waits, so no wait can form a cycle.
-template <bool WAIT>
+template <bool WAIT, bool DEEP = false>
 __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long *extra) {
   __shared__ uint32_t s_won[kCThreads], s_won_ip[kCThreads];
   __shared__ uint32_t s_nwon;
@@ -538,8 +562,12 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
       if (st == kHost && C.want && cas_u32(&C.state[cand], exp, kWanted)) {
         const uint32_t i =
             __hip_atomic_fetch_add(&C.want[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        if (i < C.want_cap)  // past the cap the bulk DMA brings it
+        if (i < C.want_cap) {  // past the cap the bulk DMA brings it
           __hip_atomic_store(&C.want[1 + i], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          // push it out now: this wave is about to spin, and a store left
+          // in a write buffer would reach the host only when the kernel ends
+          __threadfence_system();
+        }
       }
       st = kWanted;
     } else if (st == kFree) {
@@ -561,7 +589,7 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   // back while they move (this block waits for nobody until it lets go)
   const bool priority = nwon && C.demand && !C.to_image;
   if (priority && threadIdx.x == 0) atomicAdd(C.demand, 1ull);
-  for (uint32_t i = 0; i < nwon; ++i) copy_page(C, s_won[i], s_won_ip[i]);
+  for (uint32_t i = 0; i < nwon; ++i) copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
   // Publishing "done".  Checkpoint direction: a waiter only needs this
   // block's reads of the pool to have returned (the image is read after the
   // kernel ends), so waiting for every outstanding access is enough.
@@ -706,11 +734,13 @@ __device__ __forceinline__ void bg_claim_batch(const CopyArgs &C, uint64_t i, ui
   }
 }
 
+template <bool DEEP>
 __global__ void __launch_bounds__(kBgThreads)
     background_kernel(CopyArgs C, uint32_t grab, uint32_t batch) {
-  __shared__ uint32_t s_p[2][kBgMaxBatch], s_ip[2][kBgMaxBatch], s_n[2];
+  __shared__ uint32_t s_p[2][kBgMaxBatch], s_ip[2][kBgMaxBatch], s_n[2], s_arrive;
   const uint32_t t = threadIdx.x;
   const bool claimer = t >= kBgCopyThreads;
+  if (t == 0) s_arrive = 0;
   if (claimer) bg_claim_batch(C, 0, batch, grab, s_p[0], s_ip[0], &s_n[0]);
   __syncthreads();
   uint32_t cur = 0, copied = 0;
@@ -718,44 +748,42 @@ __global__ void __launch_bounds__(kBgThreads)
     if (claimer) {
       // Section 6: on-demand copies go first: claim nothing new while a
       // launch's pages are moving (bounded: this is a policy, not a
-      // correctness wait; the pages already claimed are still copied)
+      // correctness wait; the pages already claimed are still copied and
+      // published by the copying waves below, which do not wait for this)
       if (C.demand) {
         uint32_t it = 0;
         while (__hip_atomic_load(C.demand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
-               ++it < C.spin_limit)
+               ++it < C.pause_limit)
           __builtin_amdgcn_s_sleep(16);
       }
       bg_claim_batch(C, i + 1, batch, grab, s_p[cur ^ 1], s_ip[cur ^ 1], &s_n[cur ^ 1]);
     } else {
       const uint32_t n = s_n[cur];
-      for (uint32_t m = 0; m < n; ++m) copy_page(C, s_p[cur][m], s_ip[cur][m], t, kBgCopyThreads);
+      for (uint32_t m = 0; m < n; ++m) copy_page<DEEP>(C, s_p[cur][m], s_ip[cur][m], t, kBgCopyThreads);
       // towards the pool the writes must reach memory before other XCDs
       // read the page
       if (!C.to_image && n) __threadfence();
+      // The last copying wave to get here publishes the batch.  Towards the
+      // image no store needs to land before "done": the host reads the
+      // image after the kernel, and a copy-on-write waiter only needs this
+      // block's reads of the pool to have returned, which every wave's
+      // stores already depended on before its arrival.
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      uint32_t order = 0;
+      if ((t & 63u) == 0) order = atomicAdd(&s_arrive, 1u);
+      order = rfl(order);
+      if (order == kBgCopyThreads / 64 - 1) {
+        for (uint32_t m = t & 63u; m < n; m += 64)
+          __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        if ((t & 63u) == 0) s_arrive = 0;
+      }
+      copied += n;
     }
-    // Towards the image no store needs to land before "done": the host
-    // reads the image after the kernel, and a copy-on-write waiter only
-    // needs this block's reads of the pool to have returned, which every
-    // wave's stores already depended on when it reached the barrier.  So
-    // the barrier orders LDS only and the copy's stores stay in flight.
-    lds_barrier();
-    const uint32_t n = s_n[cur];
-    for (uint32_t m = t; m < n; m += kBgThreads)
-      __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    copied += n;
-    lds_barrier();  // list `cur` is free for the claim after next
+    lds_barrier();  // list `cur` is free for the claim after next; s_arrive is 0
     cur ^= 1;
   }
   if (t == 0 && copied) atomicAdd(C.stat, (unsigned long long)copied);
-}
-
-// Publish pool pages the host has copied by DMA: list[0, n) -> kDone.
-__global__ void __launch_bounds__(256)
-    mark_list_kernel(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
-                     unsigned long long *count) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) __hip_atomic_store(&state[list[i]], value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (count && i == 0) atomicAdd(count, (unsigned long long)n);
 }
 
 // Set the state of every pool page whose image page lies in a flagged image
@@ -835,6 +863,7 @@ __global__ void __launch_bounds__(kBgCopyThreads)
 // and waiting blocks must never fill the GPU, or the kernel that publishes
 // those pages could find no room to run.
 constexpr uint32_t kDemandPerThread = 4;
+template <bool DEEP>
 __global__ void __launch_bounds__(kCThreads)
     demand_kernel(CopyArgs C, const uint64_t *rec, uint64_t n, uint64_t pool_base,
                   unsigned long long *faulted) {
@@ -852,7 +881,7 @@ __global__ void __launch_bounds__(kCThreads)
           if (C.img_page[p] != kNone && C.state[p] != kDone) cand = p;
         }
       }
-      claim_copy<true>(cand, C, faulted);
+      claim_copy<true, DEEP>(cand, C, faulted);
     }
   }
 }
@@ -1038,7 +1067,10 @@ hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, u
   if (grab == 0 || grab > kBgMaxBatch) return hipErrorInvalidValue;
   if (batch == 0) batch = 1;
   if (batch * grab > kBgMaxBatch) batch = kBgMaxBatch / grab;
-  hipLaunchKernelGGL(background_kernel, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
+  if (c.deep)
+    hipLaunchKernelGGL(background_kernel<true>, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
+  else
+    hipLaunchKernelGGL(background_kernel<false>, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
   return hipGetLastError();
 }
 
@@ -1048,15 +1080,6 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
   if (!n_pages) return hipSuccess;
   hipLaunchKernelGGL(mark_pieces_kernel, dim3((n_pages + 255) / 256), dim3(256), 0, s, img_page,
                      state, n_pages, chunk_pages, flag, value, count);
-  return hipGetLastError();
-}
-
-hipError_t launch_mark_list(uint32_t *state, const uint32_t *list, uint32_t n, uint32_t value,
-                            unsigned long long *count, hipStream_t s) {
-  if (!n) return hipSuccess;
-  // one-wave blocks: the smallest footprint, so it finds room beside waiters
-  hipLaunchKernelGGL(mark_list_kernel, dim3((n + 63) / 64), dim3(64), 0, s, state, list, n, value,
-                     count);
   return hipGetLastError();
 }
 
@@ -1080,7 +1103,12 @@ hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uin
   const uint64_t per = (uint64_t)kCThreads * kDemandPerThread;
   const uint64_t chunks = (n + per - 1) / per;
   const uint32_t grid = (uint32_t)(chunks < max_grid ? chunks : (max_grid ? max_grid : 1));
-  hipLaunchKernelGGL(demand_kernel, dim3(grid), dim3(kCThreads), 0, s, c, rec, n, pool_base, faulted);
+  if (c.deep)
+    hipLaunchKernelGGL(demand_kernel<true>, dim3(grid), dim3(kCThreads), 0, s, c, rec, n, pool_base,
+                       faulted);
+  else
+    hipLaunchKernelGGL(demand_kernel<false>, dim3(grid), dim3(kCThreads), 0, s, c, rec, n, pool_base,
+                       faulted);
   return hipGetLastError();
 }
 

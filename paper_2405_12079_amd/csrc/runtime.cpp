@@ -3,12 +3,15 @@
 // concurrent-restore protocols (PhoenixOS, arXiv 2405.12079, Sections 4-6),
 // driving the gfx950 kernels in kernels.hip.
 #include <hip/hip_runtime.h>
+#include <hsa/hsa.h>
+#include <hsa/hsa_ext_amd.h>
 
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <chrono>
 #include <functional>
 #include <string>
 #include <thread>
@@ -121,8 +124,19 @@ struct phos_ctx {
   hipStream_t aux = nullptr;     // private stream for synchronous reads
   unsigned long long *h_pinned = nullptr;  // small pinned readback area
   uint32_t *h_want = nullptr;  // pageable restore: pages asked for by waiting launches (pinned)
+  // pageable restore: the two pinned bounce slots the DMA thread stages
+  // runs through, a pinned run of kDone words (the states it publishes), and
+  // the HSA agents its copy-engine copies name (found at the first such restore)
+  uint8_t *h_bounce = nullptr;
+  uint32_t *h_done = nullptr;
+  bool hsa_inited = false, hsa_ready = false;
+  hsa_agent_t gpu_agent{0}, cpu_agent{0};
 
   uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 22, copy_nt = 0;
+  // restore: how long (polls of ~0.5 us) the background holds back per batch
+  // while on-demand copies run (0: never), and 16 loads in flight per thread
+  // for the on-demand / background copies of an image in host memory
+  uint32_t rst_pause = 64, rst_deep_demand = 1, rst_deep_bg = 0;
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
   uint32_t tile_max = 8 * kVQuantum;    // largest validation tile (records)
   uint32_t tile_max_track = 16 * kVQuantum;  // ... with dirty tracking (fewer map flushes)
@@ -146,8 +160,8 @@ struct phos_ckpt {
 };
 
 constexpr uint32_t kWantCap = 16384;      // asked-for pages the host can see per restore
-constexpr uint32_t kDmaRunPages = 64;     // largest single bulk DMA (4 MiB at 64 KiB)
-constexpr uint32_t kDmaUnitPages = 256;   // pages per bulk DMA unit (16 MiB at 64 KiB)
+constexpr uint64_t kDmaRunBytes = 4u << 20;  // largest single bulk DMA (one bounce slot)
+constexpr uint64_t kBounceBytes = 2 * kDmaRunBytes;  // two staging slots
 
 struct phos_rst {
   phos_ctx *ctx;
@@ -159,16 +173,18 @@ struct phos_rst {
   unsigned long long *d_chunks = nullptr;  // image pieces (device table) or nullptr
   uint32_t chunk_pages = 0;
   // pieces in pageable host memory: the kernels cannot read them, so their
-  // pages are claimed at begin, moved by DMA on a private stream from a
+  // pages are held for the host at begin, moved by the copy engines from a
   // host thread, and published as present when the DMA has landed
   uint8_t *d_pageable = nullptr;           // per piece: 1 = pageable
   bool want = false;                       // waiters ask the host (the context's h_want)
-  uint32_t *d_list = nullptr;              // pages the host publishes as present
   bool host_image = false;                 // the image (or a piece) is in host memory
-  hipStream_t dma = nullptr;
   std::thread dma_thread;
+  uint64_t dma_pages = 0;
   phos_status dma_status = PHOS_OK;
   std::string dma_error;
+  std::chrono::steady_clock::time_point t_begin;
+  double dma_ms = 0, dma_first_ms = -1, dma_first_issue_ms = -1, dma_first_copy_ms = -1;
+  uint64_t asked_pages = 0;
   ~phos_rst() {
     if (dma_thread.joinable()) dma_thread.join();
   }
@@ -215,6 +231,8 @@ static phos_status ctx_free(phos_ctx *c) {
   if (c->h_vstage) (void)hipHostFree(c->h_vstage);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->h_want) (void)hipHostFree(c->h_want);
+  if (c->h_bounce) (void)hipHostFree(c->h_bounce);
+  if (c->hsa_inited) (void)hsa_shut_down();
   if (c->v_evt) (void)hipEventDestroy(c->v_evt);
   if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -261,6 +279,9 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->tile_max_track = std::max<uint32_t>(
       kVQuantum, env_u32("PHOS_VTILE_MAX", 16 * kVQuantum) / kVQuantum * kVQuantum);
   c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 22);
+  c->rst_pause = env_u32("PHOS_RST_PAUSE", 64);
+  c->rst_deep_demand = env_u32("PHOS_RST_DEEP_DEMAND", 1);
+  c->rst_deep_bg = env_u32("PHOS_RST_DEEP_BG", 0);
   phos_status st = PHOS_OK;
 #define CK(x)                  \
   do {                         \
@@ -308,6 +329,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       !hipck(hipHostMalloc((void **)&c->h_pinned, 4096, hipHostMallocDefault), "hipHostMalloc") ||
       !hipck(hipHostMalloc((void **)&c->h_want, 4ull * (kWantCap + 1), hipHostMallocDefault),
              "hipHostMalloc") ||
+      !hipck(hipHostMalloc((void **)&c->h_bounce, kBounceBytes + kDmaRunBytes / 1024,
+                           hipHostMallocDefault), "hipHostMalloc") ||
       !hipck(hipDeviceSynchronize(), "hipDeviceSynchronize")) {
     ctx_free(c);
     return PHOS_E_HIP;
@@ -592,7 +615,8 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
                                      uint64_t cap, uint64_t *n_violations, hipStream_t stream) {
   HostSpec *h = get_spec(c, spec);
   if (!h) return fail(PHOS_E_INVAL, "phos_validate: unknown spec %u", spec);
-  if ((n && !d_records) || (cap && !out) || !n_violations || (flags & ~kFlagMask))
+  if ((n && !d_records) || (cap && !out) || (((uintptr_t)out) & 15) || !n_violations ||
+      (flags & ~kFlagMask))
     return fail(PHOS_E_INVAL, "phos_validate: bad argument");
   if (((uintptr_t)d_records) & 7) return fail(PHOS_E_INVAL, "records must be 8-byte aligned");
   const uint32_t tile = pick_tile(c, n, flags);
@@ -618,7 +642,8 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
                                            uint32_t nlaunch, uint32_t flags, phos_violation *out,
                                            uint64_t cap, uint64_t *n_violations,
                                            hipStream_t stream) {
-  if (!c || (nlaunch && (!specs || !d_records || !n)) || (cap && !out) || !n_violations ||
+  if (!c || (nlaunch && (!specs || !d_records || !n)) || (cap && !out) || (((uintptr_t)out) & 15) ||
+      !n_violations ||
       (flags & ~kFlagMask))
     return fail(PHOS_E_INVAL, "phos_validate_batch: bad argument");
   uint64_t total = 0, total_iv = 0;
@@ -981,13 +1006,15 @@ extern "C" phos_status phos_ckpt_copied(phos_ckpt *k, uint32_t *host, uint64_t n
 }
 
 // ------------------------------------------------------------------ restore
-static CopyArgs rst_args(phos_rst *r, unsigned long long *stat) {
+static CopyArgs rst_args(phos_rst *r, unsigned long long *stat, bool deep = false) {
   CopyArgs a = copy_args(r->ctx, *r->slot, const_cast<uint8_t *>(r->image), false, stat);
   a.image_chunks = r->d_chunks;
   a.chunk_pages = r->chunk_pages;
   a.want = r->want ? r->ctx->h_want : nullptr;
   a.want_cap = r->want ? kWantCap : 0;
-  a.demand = &r->slot->counters[4];
+  a.demand = r->ctx->rst_pause ? &r->slot->counters[4] : nullptr;
+  a.pause_limit = std::min(r->ctx->rst_pause, r->ctx->spin_limit);
+  a.deep = deep && r->host_image ? 1u : 0u;
   return a;
 }
 
@@ -1036,49 +1063,152 @@ extern "C" phos_status phos_restore_begin_chunked(phos_ctx *c, uint32_t flags,
   return restore_open(c, flags, chunks[0], chunks, nchunks, chunk_bytes, copy, out);
 }
 
-// The host side of a restore from pageable pieces, on its own thread and
-// stream: it moves those pages by DMA in units of kDmaUnitPages image pages,
-// and between units serves the pages waiting launches asked for (a kernel
-// cannot read pageable memory, so the host is their fault handler).  Pages
-// are published by a small kernel on the same stream after their DMA; the
+// The host side of a restore from pageable pieces, on its own thread: it
+// moves those pages with the copy engines in runs of up to kDmaRunBytes and,
+// between runs, serves the pages waiting launches asked for (a kernel cannot
+// read pageable memory, so the host is their fault handler).  Each run is
+// staged in a pinned bounce slot and issued as two engine copies: the data,
+// then the run's page states (a copy of kDone words that starts only when the
+// data copy's completion signal reaches zero).  No compute queue or kernel
+// takes part, so the DMA cannot queue behind the kernels it serves; the
 // waiters poll device memory, so waiting adds no traffic on PCIe.
+namespace {
+struct DmaSignals {
+  hsa_signal_t data{0}, state{0};
+  bool used = false;
+};
+
+// Wait (bounded) for a copy-engine completion signal to reach zero.
+bool wait_copy(hsa_signal_t sig, std::string *why) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hsa_signal_value_t v = hsa_signal_wait_scacquire(sig, HSA_SIGNAL_CONDITION_LT, 1,
+                                                           100000000ull, HSA_WAIT_STATE_BLOCKED);
+    if (v == 0) return true;
+    if (v < 0) {
+      *why = "the copy engine reported an error";
+      return false;
+    }
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) {
+      *why = "a copy did not complete within 60 s";
+      return false;
+    }
+  }
+}
+}  // namespace
+
+struct AgentSearch {
+  uint32_t domain, bus_dev;  // the HIP device's PCI domain and (bus << 5 | device)
+  hsa_agent_t gpu{0}, cpu{0};
+};
+
+static hsa_status_t match_agent(hsa_agent_t a, void *data) {
+  AgentSearch *f = static_cast<AgentSearch *>(data);
+  hsa_device_type_t t;
+  if (hsa_agent_get_info(a, HSA_AGENT_INFO_DEVICE, &t) != HSA_STATUS_SUCCESS) return HSA_STATUS_SUCCESS;
+  if (t == HSA_DEVICE_TYPE_CPU && !f->cpu.handle) f->cpu = a;
+  uint32_t bdf = 0, dom = 0;
+  if (t == HSA_DEVICE_TYPE_GPU && !f->gpu.handle &&
+      hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_BDFID, &bdf) == HSA_STATUS_SUCCESS &&
+      hsa_agent_get_info(a, (hsa_agent_info_t)HSA_AMD_AGENT_INFO_DOMAIN, &dom) == HSA_STATUS_SUCCESS &&
+      dom == f->domain && (bdf >> 3) == f->bus_dev)  // BDF id: bus << 8 | device << 3 | function
+    f->gpu = a;
+  return HSA_STATUS_SUCCESS;
+}
+
+// The HSA agents of this context's GPU and of the host, and the pinned run
+// of kDone words, for the copy-engine DMA of pageable pieces.
+static phos_status dma_engines_ready(phos_ctx *c) {
+  if (c->hsa_ready) return PHOS_OK;
+  if (!c->hsa_inited) {
+    if (hsa_init() != HSA_STATUS_SUCCESS) return fail(PHOS_E_HIP, "hsa_init failed");
+    c->hsa_inited = true;
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, c->device));
+  AgentSearch f;
+  f.domain = (uint32_t)prop.pciDomainID;
+  f.bus_dev = ((uint32_t)prop.pciBusID << 5) | (uint32_t)prop.pciDeviceID;
+  if (hsa_iterate_agents(match_agent, &f) != HSA_STATUS_SUCCESS || !f.gpu.handle || !f.cpu.handle)
+    return fail(PHOS_E_HIP, "no HSA agent for HIP device %d (PCI %x:%x.%x)", c->device,
+                prop.pciDomainID, prop.pciBusID, prop.pciDeviceID);
+  c->gpu_agent = f.gpu;
+  c->cpu_agent = f.cpu;
+  c->h_done = reinterpret_cast<uint32_t *>(c->h_bounce + kBounceBytes);
+  for (uint64_t i = 0; i < kDmaRunBytes / 4096; ++i) c->h_done[i] = kDone;
+  c->hsa_ready = true;
+  return PHOS_OK;
+}
+
 static void restore_dma_main(phos_rst *r, std::vector<const uint8_t *> src, std::vector<uint8_t> pg,
                              uint64_t chunk_bytes) {
   phos_ctx *c = r->ctx;
   Slot &s = *r->slot;
-  auto failed = [r](const char *what, hipError_t e) {
+  std::string why;
+  auto failed = [r](const std::string &what) {
     r->dma_status = PHOS_E_HIP;
-    r->dma_error = std::string(what) + ": " + hipGetErrorString(e);
+    r->dma_error = what;
   };
-  hipError_t e = hipSetDevice(c->device);
-  if (e != hipSuccess) return failed("hipSetDevice", e);
+  auto since_begin = [r]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r->t_begin)
+        .count();
+  };
   const uint64_t pb = c->page_bytes, img_pages = c->image_bytes >> c->page_shift;
   const uint64_t cp = chunk_bytes >> c->page_shift;
+  const uint64_t run_pages = std::max<uint64_t>(1, kDmaRunBytes / pb);
   std::vector<uint8_t> served(img_pages, 0);
-  std::vector<uint32_t> list;
   uint32_t scanned = 0;
   const uint32_t *want = c->h_want;  // pinned: kernels append with system-scope atomics
-  // copy image pages [i0, i1) (pool-contiguous, one piece) and list them
-  auto copy_run = [&](uint64_t i0, uint64_t i1) -> hipError_t {
-    const uint64_t k = i0 / cp;
-    return hipMemcpyAsync(reinterpret_cast<void *>(c->pool_base + ((uint64_t)c->h_img_pool[i0] << c->page_shift)),
-                          src[k] + (i0 - k * cp) * pb, (i1 - i0) * pb, hipMemcpyHostToDevice, r->dma);
+  DmaSignals sig[2];
+  for (DmaSignals &d : sig)
+    if (hsa_signal_create(0, 0, nullptr, &d.data) != HSA_STATUS_SUCCESS ||
+        hsa_signal_create(0, 0, nullptr, &d.state) != HSA_STATUS_SUCCESS)
+      return failed("hsa_signal_create failed");
+  uint32_t slot = 0;
+  hsa_signal_t first_data{0}, first_state{0};  // the first run's, for the timings
+  auto note_first = [&]() {
+    if (r->dma_first_copy_ms < 0 && first_data.handle && hsa_signal_load_scacquire(first_data) == 0)
+      r->dma_first_copy_ms = since_begin();
+    if (r->dma_first_ms < 0 && first_state.handle && hsa_signal_load_scacquire(first_state) == 0)
+      r->dma_first_ms = since_begin();
   };
-  // present once the DMA has landed: a small kernel after it, in stream order
-  auto publish = [&]() -> hipError_t {
-    if (list.empty()) return hipSuccess;
-    hipError_t e2 = hipMemcpyAsync(r->d_list, list.data(), 4 * list.size(), hipMemcpyHostToDevice, r->dma);
-    if (e2 == hipSuccess)
-      e2 = launch_mark_list(s.state, r->d_list, (uint32_t)list.size(), kDone, &s.counters[3], r->dma);
-    if (e2 == hipSuccess) e2 = hipStreamSynchronize(r->dma);  // d_list is reused next round
-    list.clear();
-    return e2;
+  // image pages [i0, i1): one piece, pool-contiguous
+  auto copy_run = [&](uint64_t i0, uint64_t i1) -> bool {
+    const uint64_t k = i0 / cp, n = i1 - i0, bytes = n * pb;
+    if (bytes > kDmaRunBytes) {  // runs are cut at run_pages
+      why = "DMA run too long";
+      return false;
+    }
+    DmaSignals &d = sig[slot];
+    note_first();
+    if (d.used && !(wait_copy(d.data, &why) && wait_copy(d.state, &why))) return false;
+    note_first();
+    uint8_t *stage = c->h_bounce + slot * kDmaRunBytes;
+    memcpy(stage, src[k] + (i0 - k * cp) * pb, bytes);
+    const uint32_t p0 = c->h_img_pool[i0];
+    hsa_signal_store_relaxed(d.data, 1);
+    hsa_signal_store_relaxed(d.state, 1);
+    if (hsa_amd_memory_async_copy(reinterpret_cast<void *>(c->pool_base + ((uint64_t)p0 << c->page_shift)),
+                                  c->gpu_agent, stage, c->cpu_agent, bytes, 0, nullptr,
+                                  d.data) != HSA_STATUS_SUCCESS ||
+        hsa_amd_memory_async_copy(s.state + p0, c->gpu_agent, c->h_done, c->cpu_agent, 4 * n, 1,
+                                  &d.data, d.state) != HSA_STATUS_SUCCESS) {
+      why = "hsa_amd_memory_async_copy failed";
+      return false;
+    }
+    if (!first_data.handle) {
+      first_data = d.data;
+      first_state = d.state;
+      r->dma_first_issue_ms = since_begin();
+    }
+    d.used = true;
+    slot ^= 1u;
+    r->dma_pages += n;
+    return true;
   };
   // the pages waiting launches asked for, each copied alone
-  auto serve = [&]() -> hipError_t {
-    hipError_t e2 = hipSuccess;
+  auto serve = [&]() -> bool {
     const uint32_t n = std::min<uint32_t>(__atomic_load_n(&want[0], __ATOMIC_ACQUIRE), kWantCap);
-    if (scanned >= n) return hipSuccess;
     for (; scanned < n; ++scanned) {
       const uint32_t p = __atomic_load_n(&want[1 + scanned], __ATOMIC_ACQUIRE);
       if (p == kNone) break;  // reserved, not written yet: next round
@@ -1086,37 +1216,36 @@ static void restore_dma_main(phos_rst *r, std::vector<const uint8_t *> src, std:
       const uint32_t ip = c->h_img_page[p];
       if (ip == kNone || !pg[ip / cp] || served[ip]) continue;
       served[ip] = 1;
-      if ((e2 = copy_run(ip, ip + 1)) != hipSuccess) return e2;
-      list.push_back(p);
-      if (list.size() == kDmaUnitPages && (e2 = publish()) != hipSuccess) return e2;
+      ++r->asked_pages;
+      if (!copy_run(ip, ip + 1)) return false;
     }
-    return publish();
+    return true;
   };
-  for (uint64_t u0 = 0; u0 < img_pages; u0 += kDmaUnitPages) {
-    if ((e = serve()) != hipSuccess) return failed("serving asked-for pages", e);
-    const uint64_t u1 = std::min<uint64_t>(img_pages, u0 + kDmaUnitPages);
-    uint64_t run = u0;
-    for (uint64_t ip = u0; ip <= u1; ++ip) {
-      // a run breaks at the unit end, a served page, a piece boundary or a
-      // pool discontinuity (buffer boundary)
-      const bool take = ip < u1 && pg[ip / cp] && !served[ip];
-      const bool joins = take && ip > run && ip - run < kDmaRunPages && ip / cp == run / cp &&
-                         c->h_img_pool[ip] == c->h_img_pool[ip - 1] + 1;
-      if (ip > run && !joins) {
-        if ((e = copy_run(run, ip)) != hipSuccess) return failed("DMA", e);
-        run = ip;
-        // between runs (at most 4 MiB), the pages launches are waiting for
-        if ((e = serve()) != hipSuccess) return failed("serving asked-for pages", e);
-      }
-      if (!take) {
-        run = ip + 1;
-        continue;
-      }
-      served[ip] = 1;
-      list.push_back(c->h_img_pool[ip]);
+  bool ok = serve();
+  uint64_t run = 0;
+  for (uint64_t ip = 0; ok && ip <= img_pages; ++ip) {
+    // a run breaks at the end, a served page, a piece boundary, a pool
+    // discontinuity (buffer boundary) or run_pages
+    bool take = ip < img_pages && pg[ip / cp] && !served[ip];
+    const bool joins = take && ip > run && ip - run < run_pages && ip / cp == run / cp &&
+                       c->h_img_pool[ip] == c->h_img_pool[ip - 1] + 1;
+    if (ip > run && !joins) {
+      for (uint64_t q = run; q < ip; ++q) served[q] = 1;
+      ok = copy_run(run, ip) && serve();  // between runs, what launches wait for
+      run = ip;
+      take = take && !served[ip];  // it may have been one of them
     }
-    if ((e = publish()) != hipSuccess) return failed("publishing pages", e);
+    if (!take) run = ip + 1;
   }
+  for (DmaSignals &d : sig)
+    if (ok && d.used) ok = wait_copy(d.data, &why) && wait_copy(d.state, &why);
+  note_first();
+  for (DmaSignals &d : sig) {
+    if (d.data.handle) (void)hsa_signal_destroy(d.data);
+    if (d.state.handle) (void)hsa_signal_destroy(d.state);
+  }
+  if (!ok) return failed(why);
+  r->dma_ms = since_begin();
 }
 
 static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
@@ -1159,10 +1288,14 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     hipError_t e = hipMalloc((void **)&r->d_chunks, 8ull * nchunks);
     if (e == hipSuccess) e = hipMemcpy(r->d_chunks, tab.data(), 8ull * nchunks, hipMemcpyHostToDevice);
     if (e == hipSuccess && any_pageable) {
+      const phos_status st = dma_engines_ready(c);
+      if (st != PHOS_OK) {
+        if (r->d_chunks) (void)hipFree(r->d_chunks);
+        delete r;
+        return st;
+      }
       e = hipMalloc((void **)&r->d_pageable, nchunks);
       if (e == hipSuccess) e = hipMemcpy(r->d_pageable, pageable.data(), nchunks, hipMemcpyHostToDevice);
-      if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->dma, hipStreamNonBlocking);
-      if (e == hipSuccess) e = hipMalloc((void **)&r->d_list, 4ull * kDmaUnitPages);
       r->want = true;
       c->h_want[0] = 0;  // no kernel of this context runs now (begin is a quiesce point)
       for (uint32_t i = 1; i <= kWantCap; ++i) c->h_want[i] = kNone;
@@ -1176,8 +1309,6 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     if (e != hipSuccess) {
       if (r->d_chunks) (void)hipFree(r->d_chunks);
       if (r->d_pageable) (void)hipFree(r->d_pageable);
-      if (r->d_list) (void)hipFree(r->d_list);
-      if (r->dma) (void)hipStreamDestroy(r->dma);
       delete r;
       return fail(PHOS_E_NOMEM, "restore piece table: %s", hipGetErrorString(e));
     }
@@ -1192,13 +1323,14 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     }
   }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
-    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1]), copy, r->host_image);
+    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), copy, r->host_image);
     if (st != PHOS_OK) {
       delete r;
       return st;
     }
     r->bg_started = true;
   }
+  r->t_begin = std::chrono::steady_clock::now();
   if (start_dma) r->dma_thread = std::thread(start_dma);
   c->open_rst = r;
   *out = r;
@@ -1219,7 +1351,7 @@ extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const
     const VictimList none{nullptr, nullptr, 0, nullptr, 0};
     HIP_TRY(launch_cow(rst_args(r, &s.counters[2]), pr, none, true, c->cow_grid, app));
   }
-  CopyArgs a = rst_args(r, &s.counters[2]);
+  CopyArgs a = rst_args(r, &s.counters[2], c->rst_deep_demand);
   HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, c->n_cu, app));
   return PHOS_OK;
 }
@@ -1241,28 +1373,32 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   HIP_TRY(hipStreamWaitEvent(r->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!r->bg_started) {
-    TRY(start_background_args(c, s, rst_args(r, &s.counters[1]), r->copy, r->host_image));
+    TRY(start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), r->copy, r->host_image));
     r->bg_started = true;
   }
   if (r->dma_thread.joinable()) r->dma_thread.join();
-  if (r->dma) HIP_TRY(hipStreamSynchronize(r->dma));
-  if (r->dma_status != PHOS_OK) return fail(r->dma_status, "restore DMA: %s", r->dma_error.c_str());
   HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, r->copy));
   HIP_TRY(hipStreamSynchronize(r->copy));
   HIP_TRY(hipStreamSynchronize(app));
   if (stats) {
     stats->bg_pages = c->h_pinned[1];
     stats->demand_pages = c->h_pinned[2];
-    stats->dma_pages = c->h_pinned[3];
+    stats->dma_pages = r->dma_pages;
+    stats->asked_pages = r->asked_pages;
+    stats->dma_ms = r->dma_ms;
+    stats->dma_first_ms = r->dma_first_ms;
+    stats->dma_first_issue_ms = r->dma_first_issue_ms;
+    stats->dma_first_copy_ms = r->dma_first_copy_ms;
   }
   bool timeout = false;
   TRY(read_err(c, r->copy, &timeout));
   c->open_rst = nullptr;
   if (r->d_chunks) (void)hipFree(r->d_chunks);
   if (r->d_pageable) (void)hipFree(r->d_pageable);
-  if (r->d_list) (void)hipFree(r->d_list);
-  if (r->dma) (void)hipStreamDestroy(r->dma);
+  const phos_status dma_status = r->dma_status;
+  const std::string dma_error = r->dma_error;
   delete r;
+  if (dma_status != PHOS_OK) return fail(dma_status, "restore DMA: %s", dma_error.c_str());
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the pool is not valid");
   return PHOS_OK;
 }

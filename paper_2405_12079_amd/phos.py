@@ -56,7 +56,9 @@ class phos_ckpt_stats(ctypes.Structure):
 
 class phos_rst_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("demand_pages", ctypes.c_uint64),
-                ("dma_pages", ctypes.c_uint64)]
+                ("dma_pages", ctypes.c_uint64), ("asked_pages", ctypes.c_uint64),
+                ("dma_ms", ctypes.c_double), ("dma_first_ms", ctypes.c_double),
+                ("dma_first_issue_ms", ctypes.c_double), ("dma_first_copy_ms", ctypes.c_double)]
 
 
 class phos_batch_cfg(ctypes.Structure):

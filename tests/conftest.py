@@ -6,10 +6,6 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
-# one hardware queue per stream (HIP's default of 4 makes streams share
-# queues): a restore's host-side DMA must not queue behind a launch that
-# waits for it
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 # device-side waits give up after about a second here (the library default
 # allows several): a lost wake-up then fails its test at once
 os.environ.setdefault("PHOS_SPIN_LIMIT", str(1 << 20))

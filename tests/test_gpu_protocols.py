@@ -334,6 +334,12 @@ def test_protocol_errors(env):
     with pytest.raises(phos.PhosError) as e:
         phos.phos_validate(env.ctx, 12345, 0, 0, 3, 0, 0, 0, env.app)
     assert e.value.status == phos.E_INVAL
+    out, cnt = env.violations_buffers(16)
+    s2 = env.spec(L)
+    with pytest.raises(phos.PhosError) as e:  # violation output not 16-byte aligned
+        phos.phos_validate(env.ctx, s2, 0, 0, 3, out.data_ptr() + 8, 8, cnt, env.app)
+    assert e.value.status == phos.E_INVAL
+    phos.phos_spec_release(env.ctx, s2)
     with pytest.raises(phos.PhosError) as e:
         phos.phos_spec_register(env.ctx, 0, [(4, 0, env.base, 64)])  # range without mode
     assert e.value.status == phos.E_INVAL

@@ -19,6 +19,9 @@ actually copied into them (a page may be copied twice) are reported beside.
 The roofline object covers the dominant kernel (the background copy);
 `cpu_baseline` times the CPU oracle on a bounded sample of the same step.
 
+Other workloads: --config 3 batched uneven checkpoints, 4 serving loop,
+5 cold-start restore, 6 twin-kernel validator overhead.
+
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--config 2]
 """
 import argparse
@@ -270,9 +273,12 @@ def run_training_step(args):
         log(f"[bench] warmup step {i} done")
     torch.cuda.synchronize()
     rows = []
+    step_s = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        sa, sb = step()
+        ts0 = time.perf_counter()
+        sa, sb = step()  # ends with both checkpoints finished (synchronous)
+        step_s.append(time.perf_counter() - ts0)
         rows.append(dict(bg_a=t_bg_a.ms(), bg_b=t_bg_b.ms(), app=t_app.ms(),
                          rec=t_rec.ms(), bg_a_pages=sa.bg_pages, cow_pages=sa.cow_pages,
                          bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages))
@@ -358,6 +364,8 @@ def run_training_step(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
+        "step_ms": {q: round(float(np.percentile(step_s, p)) * 1e3, 3)
+                    for q, p in (("p10", 10), ("median", 50), ("p90", 90))},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -885,6 +893,119 @@ def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
             "cpu": cpu_model()}
 
 
+def run_twin(args):
+    """Section 4.1 twin kernel: the validator fused into an application kernel
+    (y[j] = 3 y[j] + x[i], uint64, 2^28 elements of 8 bytes per array),
+    timed against the same kernel uninstrumented; contiguous (j = i) and
+    indirect (j = idx[i], a fixed permutation inside each 64-element block)."""
+    import torch
+
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    n = args.twin_n
+    page = 64 << 10
+    nb = (n * 8 + page - 1) // page * page
+    back = torch.empty(3 * nb + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    pool = back[base - back.data_ptr(): base - back.data_ptr() + 3 * nb]
+    xo, yo, io = 0, nb, 2 * nb
+    p64 = pool.view(torch.int64)
+    x, y, idx = p64[:n], p64[nb // 8: nb // 8 + n], p64[2 * nb // 8: 2 * nb // 8 + n]
+    g = torch.Generator(device="cuda").manual_seed(0x5457494E)
+    x.random_(generator=g)
+    y.random_(generator=g)
+    perm = torch.randperm(64, generator=torch.Generator().manual_seed(7)).to("cuda")
+    ar = torch.arange(n, device="cuda", dtype=torch.int64)
+    idx.copy_((ar & ~63) + perm[ar & 63])
+    del ar
+    torch.cuda.synchronize()
+    ctx = phos.phos_create(0, base, 3 * nb, page)
+    phos.phos_buffers_register(ctx, [(base + xo, nb), (base + yo, nb), (base + io, nb)])
+    spec = phos.phos_spec_register(ctx, 1, [(phos.ARG_PTR_CONST, 0, base + xo, 0),
+                                            (phos.ARG_PTR_MUT, 0, base + yo, 0),
+                                            (phos.ARG_PTR_CONST, 0, base + io, 0)])
+    s = torch.cuda.Stream()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.zeros(1024 * 32, dtype=torch.uint8, device="cuda")
+    log(f"[bench] twin kernel: 3 x {n * 8 / 2**30:.1f} GiB arrays, spec of 3 intervals")
+
+    def launch(flags, indirect):
+        phos.phos_twin_scale_add(ctx, spec, base + xo, base + yo, base + io if indirect else 0, n,
+                                 flags, out.data_ptr(), 1024, cnt.data_ptr(), s)
+
+    # parity on sampled elements: one instrumented then one plain launch
+    samp = torch.randint(0, n, (4096,), generator=g, device="cuda")
+    parity = []
+    for indirect in (False, True):
+        t = idx[samp] if indirect else samp
+        y0, xs = y[t].clone(), x[samp].clone()
+        torch.cuda.synchronize()
+        phos.phos_track_reset(ctx, s)
+        launch(phos.V_READS | phos.V_WRITES | phos.V_TRACK, indirect)
+        s.synchronize()
+        y1 = y[t].clone()
+        nviol = int(cnt.item())
+        dirty = phos.phos_track_read(ctx, 0, 3 * nb // page)
+        pages = np.unpackbits(dirty.view(np.uint8), bitorder="little")[:3 * nb // page]
+        launch(0, indirect)
+        s.synchronize()
+        y2 = y[t].clone()
+        e1 = y0 * 3 + xs  # int64 arithmetic wraps like uint64
+        ok = (bool(torch.equal(y1, e1)) and bool(torch.equal(y2, e1 * 3 + xs)) and nviol == 0
+              and pages.sum() == (n * 8 + page - 1) // page and pages[nb // page] == 1
+              and pages[:nb // page].sum() == 0)
+        parity.append(ok)
+        assert ok, f"twin kernel parity failed (indirect={indirect})"
+    variants = [("plain", 0), ("writes", phos.V_WRITES), ("reads_writes", phos.V_READS | phos.V_WRITES),
+                ("reads_writes_track", phos.V_READS | phos.V_WRITES | phos.V_TRACK)]
+    res_ms = {}
+    for indirect in (False, True):
+        for name, fl in variants:
+            e0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + args.warmup)]
+            e1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + args.warmup)]
+            for r in range(args.steps + args.warmup):
+                e0[r].record(s)
+                launch(fl, indirect)
+                e1[r].record(s)
+            s.synchronize()
+            ts = np.array([e0[r].elapsed_time(e1[r]) for r in range(args.warmup, args.steps + args.warmup)])
+            key = ("indirect_" if indirect else "contiguous_") + name
+            res_ms[key] = {"median": round(float(np.median(ts)), 4),
+                           "p10": round(float(np.percentile(ts, 10)), 4),
+                           "p90": round(float(np.percentile(ts, 90)), 4)}
+            log(f"[bench] {key}: {res_ms[key]['median']:.3f} ms")
+    ov = {k: round(100.0 * (res_ms[k]["median"] / res_ms[("indirect_" if k.startswith("indirect")
+                                                          else "contiguous_") + "plain"]["median"] - 1), 2)
+          for k in res_ms if not k.endswith("plain")}
+    plain_ms = res_ms["contiguous_plain"]["median"]
+    twin_ms = res_ms["contiguous_reads_writes_track"]["median"]
+    alg = 24 * n  # read x[i], read y[i], write y[i]
+    log(f"[bench] twin overhead (%): {ov}")
+    phos.phos_spec_release(ctx, spec)
+    phos.phos_destroy(ctx)
+    return {
+        "metric": "twin-kernel validator overhead vs the uninstrumented kernel (reads + writes "
+                  "checked, dirty pages tracked)",
+        "value": ov["contiguous_reads_writes_track"], "unit": "%", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": twin_ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (seeded array contents, fixed in-block permutation)",
+        "config": {"workload": f"twin kernel: y[j] = 3 y[j] + x[i] over {n} uint64 elements, "
+                               "spec of 3 intervals (x R, y RW, idx R)", "elements": n},
+        "ms": res_ms, "overhead_pct": ov,
+        "roofline": {"bound": "hbm", "kernel": "twin_kernel (uninstrumented, contiguous)",
+                     "achieved": round(alg / (plain_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(alg / (plain_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": alg},
+        "roofline_twin": {"bound": "hbm", "kernel": "twin_kernel (reads + writes + tracking)",
+                          "achieved": round(alg / (twin_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                          "unit": "GB/s", "frac": round(alg / (twin_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)},
+        "parity": f"sampled elements equal 3 y + x after the twin and again after the plain kernel; "
+                  f"no violations; dirty pages exactly y's: {parity}",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -901,6 +1022,7 @@ def main():
     ap.add_argument("--iter-mib", type=int, default=2048, help="MiB per batched iteration")
     ap.add_argument("--small-mib", type=int, default=1024,
                     help="batched order: requests with at most this many MiB left go first")
+    ap.add_argument("--twin-n", type=int, default=1 << 28, help="elements per array (config 6)")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
     ap.add_argument("--app-graph", action="store_true",
                     help="replay the per-launch copy-on-write + application loop as one HIP "
@@ -919,6 +1041,8 @@ def main():
         res = run_serving(args)
     elif args.config == 5:
         res = run_cold_start(args)
+    elif args.config == 6:
+        res = run_twin(args)
     else:
         sys.exit(f"unknown config {args.config}")
     print(json.dumps(res), flush=True)

@@ -147,7 +147,8 @@ typedef struct {
  *                        0 lets them share the link
  *   PHOS_RST_DEEP_DEMAND / PHOS_RST_DEEP_BG  restore from host memory: 16
  *                        loads in flight per thread in on-demand [1] /
- *                        background [0] copies */
+ *                        background [0] copies
+ *   PHOS_TWIN_BLOCKS_PER_CU  twin kernel blocks per CU [4; 5 with PHOS_V_TRACK] */
 phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes, uint32_t page_bytes,
                         phos_ctx **out);
 /* Synchronizes the device, frees everything the context owns. */
@@ -202,6 +203,26 @@ phos_status phos_validate_batch(phos_ctx *ctx, const phos_spec *specs,
                                 const uint64_t *const *d_records, const uint64_t *n,
                                 uint32_t nlaunch, uint32_t flags, phos_violation *out,
                                 uint64_t cap, uint64_t *n_violations, hipStream_t stream);
+
+/* Section 4.1 twin kernel: an application kernel with the validator fused
+ * into it.  The kernel computes y[j] = 3 * y[j] + x[i] (uint64, wrapping) for
+ * i < n, with j = idx[i] (an element offset from y, may be negative) or j = i
+ * when idx is NULL.  flags = 0 runs it uninstrumented (spec, out, cap and
+ * n_violations unused).  Otherwise it is the instrumented twin: every global
+ * access it makes is checked against `spec` as phos_validate checks a
+ * record -- per element i the reads of x[i], idx[i] and y[j] (PHOS_V_READS)
+ * and the write of y[j] (PHOS_V_WRITES) -- and PHOS_V_TRACK updates the
+ * dirty / victim bitmaps as phos_validate does.  Every access is made either
+ * way, as in the paper; acting on a reported failure is the caller's
+ * protocol.  Violations (index = i) go to `out` in no particular order, the
+ * count to *n_violations (device memory, zeroed by the call; E_INVAL if
+ * flags != 0 and it is NULL).  x, y, idx: device memory, 8-byte aligned; the
+ * caller guarantees every y + j lies in memory it may write.  Asynchronous
+ * on `stream`. */
+phos_status phos_twin_scale_add(phos_ctx *ctx, phos_spec spec, const uint64_t *x, uint64_t *y,
+                                const int64_t *idx, uint64_t n, uint32_t flags,
+                                phos_violation *out, uint64_t cap, uint64_t *n_violations,
+                                hipStream_t stream);
 
 /* Clear the dirty and victim bitmaps (asynchronous on stream).  E_STATE while
  * a recopy checkpoint is open: its recopy list is read from these maps. */

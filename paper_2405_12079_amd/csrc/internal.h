@@ -141,6 +141,25 @@ struct BatchQ {
   uint64_t chunk_bytes;
 };
 
+// A twin kernel (Section 4.1): an application kernel, y[j] <- 3 * y[j] + x[i]
+// with j = idx[i] (or i), whose instrumented twin checks every global access
+// against the speculated intervals before making it.
+struct TwinArgs {
+  const uint64_t *x;
+  uint64_t *y;
+  const int64_t *idx;  // element offsets from y, or nullptr (j = i)
+  uint64_t n;
+  uint32_t flags, launch_id;  // PHOS_V_* (0: the uninstrumented kernel)
+  uint64_t pool_base, pool_bytes;
+  uint32_t page_shift, vlist_cap;
+  const uint32_t *page_buf;
+  uint8_t *dirty, *victim;
+  uint32_t *vlist, *vmeta;
+  phos_violation *out;  // unordered
+  uint64_t cap;
+  unsigned long long *count;
+};
+
 // ---------------------------------------------------------------- launchers
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
@@ -174,6 +193,8 @@ hipError_t launch_bytes_to_bits(const uint8_t *bytes, uint32_t nwords, uint32_t 
                                 hipStream_t s);
 hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s);
 hipError_t launch_read_clock(unsigned long long *out, hipStream_t s);  // GPU wall clock
+hipError_t launch_twin(const TwinArgs &a, const DevSpec &spec, uint64_t blocks, uint32_t n_cu,
+                       hipStream_t s);
 hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s);
 hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);
 

@@ -9,9 +9,11 @@
 //   pagelist/gather   Section 4.3 recopy of dirty and victim pages
 //   demand_kernel     Section 6 on-demand restore of the pages a launch touches
 //   batch_copy        persistent copy of many requests' segments (no paper analog)
+//   twin_kernel       Section 4.1 instrumented twin of an application kernel
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "util.h"
 
 #define GLOBAL_AS __attribute__((address_space(1)))
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -913,6 +915,127 @@ __global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long
     p[i] = v;
 }
 
+// ============================================================ twin kernel
+// Section 4.1, the instrumented twin of an application kernel: the kernel's
+// own global accesses are checked in place against the launch's speculated
+// intervals (wave-uniform; in registers for up to 8 intervals).  A failed
+// check is reported (unordered: one reservation per wave and check); with
+// tracking, a validated write marks its page dirty and a failing write
+// inside a buffer marks its page a victim (Section 4.3).  The access itself
+// is made either way, as the paper's instrumented kernel does: what to do
+// about a failure is the caller's protocol.
+template <int NIV>
+__device__ __forceinline__ uint32_t twin_classify(const IvRegs &R, const DevSpec &S, uint64_t a,
+                                                  uint32_t w) {
+  if constexpr (NIV >= 0) return classify_n<NIV>(R, a, w);
+  else return classify_lds(S, S.niv, a, w);
+}
+
+__device__ __forceinline__ void twin_report(const TwinArgs &A, bool bad, uint64_t i, uint64_t a,
+                                            uint32_t w, uint32_t reason) {
+  const uint64_t m = __ballot(bad);
+  if (!m) return;
+  const uint32_t lane = threadIdx.x & 63u, lead = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+  unsigned long long base = 0;
+  if (lane == lead) base = atomicAdd(A.count, (unsigned long long)__popcll(m));
+  base = __shfl(base, (int)lead, 64);
+  if (!bad) return;
+  const unsigned long long pos = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+  if (pos >= A.cap) return;
+  const uint64_t off = a - A.pool_base;
+  phos_violation v;
+  v.index = i;
+  v.addr = a;
+  v.launch_id = A.launch_id;
+  v.is_write = (uint8_t)w;
+  v.reason = (uint8_t)reason;
+  v._p = 0;
+  v.victim = (int32_t)(off < A.pool_bytes ? A.page_buf[off >> A.page_shift] : kNone);
+  v._q = 0;
+  A.out[pos] = v;
+}
+
+// Every lane of the wave calls this (act: the lane has an element).
+__device__ __forceinline__ void twin_track(const TwinArgs &A, bool act, uint64_t a, uint32_t reason) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t off = a - A.pool_base;
+  const bool in = act && off < A.pool_bytes;
+  const uint32_t page = in ? (uint32_t)(off >> A.page_shift) : kNone;
+  // validated writes: one store per run of lanes on the same page
+  const uint32_t dp = reason == 0 ? page : kNone;
+  const uint32_t prev = __shfl_up(dp, 1, 64);
+  if (dp != kNone && (lane == 0 || prev != dp)) A.dirty[dp] = 1;
+  if (reason != 0 && in && A.page_buf[page] != kNone && A.victim[page] == 0) {
+    A.victim[page] = 1;  // newly marked (a stale read only adds a duplicate)
+    const uint32_t k = atomicAdd(&A.vmeta[0], 1u);
+    if (k < A.vlist_cap) A.vlist[k] = page;
+    else A.vmeta[3] = 1;
+  }
+}
+
+// Each thread takes kTwinU elements per pass (stride: the grid): all their
+// loads are issued first, then the stores, then the checks, so a wave keeps
+// kTwinU elements' loads in flight and the checks' ALU work overlaps the
+// memory traffic of other waves instead of adding to it.
+constexpr int kTwinU = 4;
+
+template <bool CHECK, int NIV>
+__global__ void __launch_bounds__(256) twin_kernel(TwinArgs A, DevSpec S) {
+  IvRegs R;
+#pragma unroll
+  for (int j = 0; j < (NIV > 0 ? NIV : 0); ++j) {
+    R.lo[j] = S.iv[j].lo;
+    R.hi8[j] = S.iv[j].lo == ~0ull ? 0ull : S.iv[j].lo + S.iv[j].span;
+    R.mode[j] = S.iv[j].mode;
+  }
+  const bool rd = CHECK && (A.flags & PHOS_V_READS), wr = CHECK && (A.flags & PHOS_V_WRITES);
+  const bool tr = CHECK && (A.flags & PHOS_V_TRACK);
+  const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+  // lanes leave the loop in lane order (i0 grows with the lane), so the
+  // lanes still in it are a prefix of the wave
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < A.n; i0 += kTwinU * T) {
+    bool act[kTwinU];
+    int64_t j[kTwinU];
+    uint64_t xv[kTwinU], yv[kTwinU];
+#pragma unroll
+    for (int k = 0; k < kTwinU; ++k) {
+      act[k] = i0 + k * T < A.n;
+      j[k] = act[k] ? (A.idx ? A.idx[i0 + k * T] : (int64_t)(i0 + k * T)) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kTwinU; ++k) {
+      xv[k] = act[k] ? A.x[i0 + k * T] : 0;
+      yv[k] = act[k] ? A.y[j[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kTwinU; ++k)
+      if (act[k]) A.y[j[k]] = 3 * yv[k] + xv[k];
+    if (CHECK) {
+#pragma unroll
+      for (int k = 0; k < kTwinU; ++k) {
+        const uint64_t i = i0 + k * T;
+        const uint64_t xa = (uint64_t)(A.x + i), ya = (uint64_t)(A.y + j[k]);
+        if (rd) {
+          const uint32_t r0 = twin_classify<NIV>(R, S, xa, 0);
+          twin_report(A, act[k] && r0 != 0, i, xa, 0, r0);
+          if (A.idx) {
+            const uint64_t ia = (uint64_t)(A.idx + i);
+            const uint32_t r1 = twin_classify<NIV>(R, S, ia, 0);
+            twin_report(A, act[k] && r1 != 0, i, ia, 0, r1);
+          }
+          const uint32_t r2 = twin_classify<NIV>(R, S, ya, 0);
+          twin_report(A, act[k] && r2 != 0, i, ya, 0, r2);
+        }
+        if (wr || tr) {
+          const uint32_t r3 = twin_classify<NIV>(R, S, ya, 1);
+          if (wr) twin_report(A, act[k] && r3 != 0, i, ya, 1, r3);
+          if (tr) twin_track(A, act[k], ya, r3);
+        }
+      }
+    }
+  }
+}
+
 // ============================================================ batched copy
 // Copy bytes [b0, b1) of the concatenated segment stream.
 __device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, uint64_t b1) {
@@ -1149,6 +1272,47 @@ hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads
   if (!nchunks) return hipSuccess;
   hipLaunchKernelGGL(plain_copy_kernel, dim3((unsigned)nchunks), dim3(threads), 0, s, q);
   return hipGetLastError();
+}
+
+// One resident round of blocks: each block's share of the elements is fixed
+// (grid stride), so blocks beyond what fits at once would run as a second,
+// partial round.  Measured on 3 x 2 GiB arrays: 4 blocks (16 waves) per CU
+// keep enough loads in flight without crowding HBM; the tracking twin does
+// more work per element between its loads and is fastest with 5.
+template <bool C, int N>
+static hipError_t launch_twin_t(const TwinArgs &a, const DevSpec &spec, uint64_t blocks,
+                                uint32_t n_cu, hipStream_t s) {
+  static int per_cu = 0;  // per kernel instance; a racing first call computes the same value
+  if (!per_cu) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, twin_kernel<C, N>, 256, 0) != hipSuccess ||
+        v < 1)
+      v = 1;
+    per_cu = v;
+  }
+  const uint32_t want = env_u32("PHOS_TWIN_BLOCKS_PER_CU", (a.flags & PHOS_V_TRACK) ? 5 : 4);
+  const uint64_t cap = (uint64_t)(want && (int)want < per_cu ? (int)want : per_cu) * (n_cu ? n_cu : 1);
+  const uint32_t grid = (uint32_t)(blocks < cap ? (blocks ? blocks : 1) : cap);
+  hipLaunchKernelGGL((twin_kernel<C, N>), dim3(grid), dim3(256), 0, s, a, spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_twin(const TwinArgs &a, const DevSpec &spec, uint64_t blocks, uint32_t n_cu,
+                       hipStream_t s) {
+  if (!a.n) return hipSuccess;
+  if (!a.flags) return launch_twin_t<false, 0>(a, spec, blocks, n_cu, s);
+  switch (spec.niv) {
+    case 0: return launch_twin_t<true, 0>(a, spec, blocks, n_cu, s);
+    case 1: return launch_twin_t<true, 1>(a, spec, blocks, n_cu, s);
+    case 2: return launch_twin_t<true, 2>(a, spec, blocks, n_cu, s);
+    case 3: return launch_twin_t<true, 3>(a, spec, blocks, n_cu, s);
+    case 4: return launch_twin_t<true, 4>(a, spec, blocks, n_cu, s);
+    case 5: return launch_twin_t<true, 5>(a, spec, blocks, n_cu, s);
+    case 6: return launch_twin_t<true, 6>(a, spec, blocks, n_cu, s);
+    case 7: return launch_twin_t<true, 7>(a, spec, blocks, n_cu, s);
+    case 8: return launch_twin_t<true, 8>(a, spec, blocks, n_cu, s);
+    default: return launch_twin_t<true, -1>(a, spec, blocks, n_cu, s);
+  }
 }
 
 }  // namespace phos

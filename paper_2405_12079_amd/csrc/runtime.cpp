@@ -610,6 +610,51 @@ static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *si
 
 static const uint32_t kFlagMask = PHOS_V_READS | PHOS_V_WRITES | PHOS_V_TRACK;
 
+extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const uint64_t *x,
+                                           uint64_t *y, const int64_t *idx, uint64_t n,
+                                           uint32_t flags, phos_violation *out, uint64_t cap,
+                                           uint64_t *n_violations, hipStream_t stream) {
+  if (!c) return fail(PHOS_E_INVAL, "phos_twin_scale_add: NULL context");
+  if ((flags & ~kFlagMask) || (n && (!x || !y)) ||
+      (flags && (!n_violations || (cap && !out) || (((uintptr_t)out) & 15))))
+    return fail(PHOS_E_INVAL, "phos_twin_scale_add: bad argument");
+  if (((uintptr_t)x | (uintptr_t)y | (uintptr_t)idx) & 7)
+    return fail(PHOS_E_INVAL, "x, y and idx must be 8-byte aligned");
+  DevSpec ds;
+  ds.niv = 0;
+  ds.pad = 0;
+  TwinArgs a;
+  memset(&a, 0, sizeof a);
+  if (flags) {
+    HostSpec *h = get_spec(c, spec);
+    if (!h) return fail(PHOS_E_INVAL, "phos_twin_scale_add: unknown spec %u", spec);
+    fill_devspec(*h, &ds);
+    a.launch_id = h->launch_id;
+  }
+  a.x = x;
+  a.y = y;
+  a.idx = idx;
+  a.n = n;
+  a.flags = flags;
+  a.pool_base = c->pool_base;
+  a.pool_bytes = c->pool_bytes;
+  a.page_shift = c->page_shift;
+  a.page_buf = c->d_page_buf;
+  a.dirty = c->d_dirty;
+  a.victim = c->d_victim;
+  a.vlist = c->d_vlist;
+  a.vmeta = c->d_vmeta;
+  a.vlist_cap = c->vlist_cap;
+  a.out = out;
+  a.cap = out ? cap : 0;
+  a.count = reinterpret_cast<unsigned long long *>(n_violations);
+  DeviceGuard g(c->device);
+  if (flags) HIP_TRY(launch_fill_u64(a.count, 1, 0, stream));
+  const uint64_t blocks = (n + 4 * 256 - 1) / (4 * 256);  // four elements per thread
+  HIP_TRY(launch_twin(a, ds, blocks, c->n_cu, stream));
+  return PHOS_OK;
+}
+
 extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t *d_records,
                                      uint64_t n, uint32_t flags, phos_violation *out,
                                      uint64_t cap, uint64_t *n_violations, hipStream_t stream) {

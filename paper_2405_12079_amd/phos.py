@@ -79,6 +79,7 @@ SIGNATURES = [
     ("phos_spec_intervals", [P, U32, P, U32, ctypes.POINTER(U32)]),
     ("phos_spec_release", [P, U32]),
     ("phos_validate", [P, U32, P, U64, U32, P, U64, P, P]),
+    ("phos_twin_scale_add", [P, U32, P, P, P, U64, U32, P, U64, P, P]),
     ("phos_validate_batch", [P, P, P, P, U32, U32, P, U64, P, P]),
     ("phos_track_reset", [P, P]),
     ("phos_track_read", [P, U32, P, U64]),
@@ -223,6 +224,12 @@ def phos_validate_batch(ctx, specs, d_records, n, flags, out, cap, n_violations,
     nn = (U64 * max(1, k))(*n)
     _call("phos_validate_batch", ctx, sp, rp, nn, k, flags, _ptr(out), cap, _ptr(n_violations),
           _stream(stream))
+
+
+def phos_twin_scale_add(ctx, spec, x, y, idx, n, flags, out=None, cap=0, n_violations=None,
+                        stream=None) -> None:
+    _call("phos_twin_scale_add", ctx, spec, _ptr(x), _ptr(y), _ptr(idx), n, flags, _ptr(out), cap,
+          _ptr(n_violations), _stream(stream))
 
 
 def phos_track_reset(ctx, stream=None) -> None:

@@ -20,7 +20,7 @@ The roofline object covers the dominant kernel (the background copy);
 `cpu_baseline` times the CPU oracle on a bounded sample of the same step.
 
 Other workloads: --config 3 batched uneven checkpoints, 4 serving loop,
-5 cold-start restore, 6 twin-kernel validator overhead.
+5 cold-start restore, 6 twin-kernel validator overhead, 7 preemptible drain.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--config 2]
 """
@@ -1006,6 +1006,92 @@ def run_twin(args):
     }
 
 
+def run_drain(args):
+    """Section 5 preemptible drain: a 16 GiB image drained to pinned host
+    memory by phos_ckpt_end, once as one copy and once in chunks (the
+    default), while the application issues 64 MiB device-to-host copies;
+    reports the application copies' latency and the drain rate."""
+    import threading
+
+    import torch
+
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    page, pool_bytes = 64 << 10, 16 << 30
+    back = torch.empty(pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    img = torch.empty(pool_bytes, dtype=torch.uint8, device="cuda")
+    host_img = pinned_tensor(torch, pool_bytes)
+    app_dev = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    app_host = pinned_tensor(torch, 64 << 20)
+    app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
+    back.random_(0, 256)
+    torch.cuda.synchronize()
+
+    def app_copies(k):
+        ts = []
+        for _ in range(k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(app)
+            with torch.cuda.stream(app):
+                app_host.copy_(app_dev, non_blocking=True)
+            e1.record(app)
+            app.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return ts
+
+    out = {"app_copy_alone_ms": round(float(np.median(app_copies(20))), 3)}
+    for label, chunk_kb in (("one_copy", "0"), ("chunked", None)):
+        saved = os.environ.get("PHOS_DRAIN_CHUNK_KB")
+        if chunk_kb is not None:
+            os.environ["PHOS_DRAIN_CHUNK_KB"] = chunk_kb
+        try:
+            ctx = phos.phos_create(0, base, pool_bytes, page)
+        finally:
+            if chunk_kb is not None:
+                if saved is None:
+                    del os.environ["PHOS_DRAIN_CHUNK_KB"]
+                else:
+                    os.environ["PHOS_DRAIN_CHUNK_KB"] = saved
+        phos.phos_buffers_register(ctx, [(base, pool_bytes)])
+        rates, lat = [], []
+        for rep in range(max(2, args.steps)):
+            ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img.data_ptr(), host_img.data_ptr(), cpy)
+            cpy.synchronize()  # the background copy has finished: time the drain alone
+            box = {}
+
+            def end():
+                t0 = time.perf_counter()
+                phos.phos_ckpt_end(ck, cpy)
+                box["s"] = time.perf_counter() - t0
+
+            th = threading.Thread(target=end)
+            th.start()
+            time.sleep(0.02)
+            lat += app_copies(8)
+            th.join()
+            rates.append(pool_bytes / box["s"] / 1e9)
+        same = bool(torch.equal(host_img[:1 << 20], img[:1 << 20].cpu()))
+        phos.phos_destroy(ctx)
+        out[label] = {"drain_GBps": round(float(np.median(rates)), 2),
+                      "app_copy_ms_during_drain": {"median": round(float(np.median(lat)), 3),
+                                                   "p90": round(float(np.percentile(lat, 90)), 3),
+                                                   "max": round(float(np.max(lat)), 3)},
+                      "image_prefix_equal": same}
+        log(f"[bench] drain {label}: {out[label]}")
+    return {
+        "metric": "app device-to-host copy latency during the image drain (p90, ms); drain GB/s",
+        "value": out["chunked"]["app_copy_ms_during_drain"]["p90"], "unit": "ms", "n_gpus": 1,
+        "steps": max(2, args.steps), "warmup": 0, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (random image bytes)",
+        "config": {"workload": "preemptible drain: 16 GiB image to pinned host memory, "
+                               "64 MiB application copies to host meanwhile"},
+        **out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1043,6 +1129,8 @@ def main():
         res = run_cold_start(args)
     elif args.config == 6:
         res = run_twin(args)
+    elif args.config == 7:
+        res = run_drain(args)
     else:
         sys.exit(f"unknown config {args.config}")
     print(json.dumps(res), flush=True)

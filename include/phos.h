@@ -148,7 +148,9 @@ typedef struct {
  *   PHOS_RST_DEEP_DEMAND / PHOS_RST_DEEP_BG  restore from host memory: 16
  *                        loads in flight per thread in on-demand [1] /
  *                        background [0] copies
- *   PHOS_TWIN_BLOCKS_PER_CU  twin kernel blocks per CU [4; 5 with PHOS_V_TRACK] */
+ *   PHOS_TWIN_BLOCKS_PER_CU  twin kernel blocks per CU [4; 5 with PHOS_V_TRACK]
+ *   PHOS_DRAIN_CHUNK_KB  image drain to a host image: chunk size [16384; 0 =
+ *                        one copy]; PHOS_DRAIN_WINDOW chunks in flight [2] */
 phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes, uint32_t page_bytes,
                         phos_ctx **out);
 /* Synchronizes the device, frees everything the context owns. */
@@ -261,7 +263,10 @@ phos_status phos_ckpt_recopy(phos_ckpt *ck, hipStream_t app_stream);
 
 /* Finish: wait for every copy (and app_stream), drain image to host_image if
  * given, free the handle.  A recopy checkpoint not yet recopied is recopied
- * first (ending is a quiesce point).  E_TIMEOUT if a device wait expired. */
+ * first (ending is a quiesce point).  The drain (Section 5) is issued in
+ * chunks from the calling thread with a few in flight, so device-to-host
+ * copies the application issues meanwhile wait for a few chunks, not for
+ * the whole image.  E_TIMEOUT if a device wait expired. */
 phos_status phos_ckpt_end(phos_ckpt *ck, hipStream_t app_stream, phos_ckpt_stats *stats);
 
 /* Synchronous: copied-page bitmap of an open checkpoint (bit p = pool page p);

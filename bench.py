@@ -231,10 +231,12 @@ def run_training_step(args):
     t_rec = Timer(torch, cpy)
     graph = None
 
-    def app_loop(ca):
+    def app_loop(ca, cb):
         for j, L in enumerate(launches):
             if j % chunk == 0:  # validate the next `chunk` launches' access streams
                 c = j // chunk
+                if args.precopy and j:  # every launch validated so far has been enqueued
+                    phos.phos_ckpt_precopy(cb, app)
                 sl = slice(j, min(j + chunk, n_launch))
                 phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], [n_rec] * len(specs[sl]),
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
@@ -255,10 +257,10 @@ def run_training_step(args):
         if args.app_graph and warm:
             if graph is None:
                 graph = HipGraph()
-                graph.capture(app, lambda: app_loop(ca))
+                graph.capture(app, lambda: app_loop(ca, cb))
             graph.launch(app)
         else:
-            app_loop(ca)
+            app_loop(ca, cb)
         t_app.stop()
         t_rec.e0.record(app)  # from the application's last launch to the recopy's end
         phos.phos_ckpt_recopy(cb, app)
@@ -281,7 +283,8 @@ def run_training_step(args):
         step_s.append(time.perf_counter() - ts0)
         rows.append(dict(bg_a=t_bg_a.ms(), bg_b=t_bg_b.ms(), app=t_app.ms(),
                          rec=t_rec.ms(), bg_a_pages=sa.bg_pages, cow_pages=sa.cow_pages,
-                         bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages))
+                         bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages,
+                         precopy_pages=sb.precopy_pages))
         log(f"[bench] step {i}: " + ", ".join(f"{k}={v:.3f}" if isinstance(v, float) else f"{k}={v}"
                                              for k, v in rows[-1].items()))
     torch.cuda.synchronize()
@@ -338,8 +341,8 @@ def run_training_step(args):
     # checkpoint image bytes finished per step (two images), and the bytes
     # actually copied into them
     img_bytes = 2 * nimg
-    copied_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"])
-                            * page for r in rows])
+    copied_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"]
+                             + r["precopy_pages"]) * page for r in rows])
     snap_gbps = img_bytes / (ms_step / 1e3) / 1e9
     # dominant kernel: the background copy of the copy-on-write image (every
     # page not taken by copy-on-write; 2 bytes of HBM traffic per byte), timed
@@ -378,6 +381,9 @@ def run_training_step(args):
         "validation_ms_alone": {k: round(v, 4) for k, v in alone.items()},
         "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
         "recopy_ms": round(float(np.mean([r["rec"] for r in rows])), 3),
+        "recopy_pages": int(np.mean([r["recopy_pages"] for r in rows])),
+        "precopy": {"rounds": (nchunk - 1) if args.precopy else 0,
+                    "pages": int(np.mean([r["precopy_pages"] for r in rows]))},
         "app_loop_graph": bool(args.app_graph),
         "launches_per_validation_call": chunk,
         "copy_roofs": roofs,
@@ -1109,6 +1115,9 @@ def main():
     ap.add_argument("--small-mib", type=int, default=1024,
                     help="batched order: requests with at most this many MiB left go first")
     ap.add_argument("--twin-n", type=int, default=1 << 28, help="elements per array (config 6)")
+    ap.add_argument("--precopy", action="store_true",
+                    help="config 2: a pre-copy round of the recopy image before each validation "
+                         "chunk after the first (iterative recopy; use with --val-chunk)")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
     ap.add_argument("--app-graph", action="store_true",
                     help="replay the per-launch copy-on-write + application loop as one HIP "

@@ -114,6 +114,7 @@ typedef struct {
   uint64_t cow_pages;    /* pages copied before a launch (copy-on-write)       */
   uint64_t recopy_pages; /* pages recopied after the re-quiesce                */
   uint64_t image_bytes;  /* bytes of the image                                 */
+  uint64_t precopy_pages; /* pages copied by pre-copy rounds                   */
 } phos_ckpt_stats;
 
 typedef struct {
@@ -260,6 +261,18 @@ phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream)
  * reaches them: the recopy copies those pages anyway, so the image is the
  * same and the concurrent copy moves fewer bytes. */
 phos_status phos_ckpt_recopy(phos_ckpt *ck, hipStream_t app_stream);
+
+/* Sections 4.3 and 7, iterative recopy: a pre-copy round.  In app_stream
+ * order, every page marked dirty so far is unmarked and copied into the
+ * image now, while the application keeps running; a page written again
+ * later is marked again by validation and copied at the re-quiesce, which
+ * then moves fewer pages.  Victim marks are kept for the re-quiesce.  Call
+ * between launches: every launch validated so far must be enqueued on
+ * app_stream before this call, and later validations issued after it in
+ * app_stream order (a mark made concurrently could be lost).  Asynchronous
+ * on app_stream.  E_STATE unless an open recopy checkpoint not yet
+ * recopied. */
+phos_status phos_ckpt_precopy(phos_ckpt *ck, hipStream_t app_stream);
 
 /* Finish: wait for every copy (and app_stream), drain image to host_image if
  * given, free the handle.  A recopy checkpoint not yet recopied is recopied

@@ -185,6 +185,8 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
                            uint32_t *list, unsigned int *count, hipStream_t s);
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s);
+hipError_t launch_precopy(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
+                          uint8_t *dirty, uint32_t grid, hipStream_t s);
 hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,
                          unsigned long long *faulted, uint32_t max_grid, hipStream_t s);
 hipError_t launch_states_to_bits(const uint32_t *state, uint32_t n_pages, uint32_t *bits,

@@ -7,6 +7,7 @@
 //   cow_kernel        Section 4.2 pre-launch copy of pages about to be written
 //   background_kernel Section 4.2/4.3/6 concurrent bulk copy under per-page claims
 //   pagelist/gather   Section 4.3 recopy of dirty and victim pages
+//   precopy_kernel    Sections 4.3/7 pre-copy round of a recopy checkpoint
 //   demand_kernel     Section 6 on-demand restore of the pages a launch touches
 //   batch_copy        persistent copy of many requests' segments (no paper analog)
 //   twin_kernel       Section 4.1 instrumented twin of an application kernel
@@ -807,6 +808,53 @@ __global__ void __launch_bounds__(256)
   if (count && (threadIdx.x & 63u) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
 }
 
+// Pre-copy round of a recopy checkpoint (iterative recopy, Sections 4.3 and
+// 7): every listed page (marked dirty so far; its writers have all run) is
+// unmarked and copied into the image now; a page written again later is
+// marked again and copied at the re-quiesce.  The claims keep the concurrent
+// background copy of the same image from landing a stale copy afterwards: a
+// free page is claimed and published, a page the background holds is waited
+// for and then overwritten, a done page is overwritten.
+__global__ void __launch_bounds__(kBgCopyThreads)
+    precopy_kernel(CopyArgs C, const uint32_t *list, const unsigned int *count, uint8_t *dirty) {
+  __shared__ uint32_t s_own;
+  const uint32_t cnt = *count;
+  uint32_t nw = 0;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const uint32_t p = list[i];
+    const uint32_t ip = p < C.n_pages ? C.img_page[p] : kNone;
+    if (ip == kNone) continue;  // the same page for the whole block
+    if (threadIdx.x == 0) {
+      dirty[p] = 0;
+      uint32_t own = 0, st = ld_relaxed(&C.state[p]);
+      if (st == kFree) {
+        uint32_t exp = kFree;
+        if (cas_u32(&C.state[p], exp, kClaimed)) own = 1;
+        else st = exp;
+      }
+      if (!own && st == kClaimed) {
+        uint32_t it = 0;
+        while (ld_acquire(&C.state[p]) != kDone) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++it > C.spin_limit) {
+            atomicOr(C.err, 1u);
+            break;
+          }
+        }
+      }
+      s_own = own;
+    }
+    __syncthreads();
+    copy_page(C, p, ip);
+    __syncthreads();  // every wave's copy issued (its loads returned)
+    if (threadIdx.x == 0 && s_own)
+      __hip_atomic_store(&C.state[p], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ++nw;
+    __syncthreads();  // s_own is rewritten for the next page
+  }
+  if (threadIdx.x == 0 && nw) atomicAdd(C.stat, (unsigned long long)nw);
+}
+
 // Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
 __global__ void __launch_bounds__(256)
     pagelist_kernel(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
@@ -1211,6 +1259,12 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
   if (!nwords) return hipSuccess;
   hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, nwords,
                      n_pages, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_precopy(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
+                          uint8_t *dirty, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(precopy_kernel, dim3(grid), dim3(kBgCopyThreads), 0, s, c, list, count, dirty);
   return hipGetLastError();
 }
 

@@ -978,6 +978,7 @@ extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
     TRY(start_background(c, s, k->image, true, k->copy, true));
     k->bg_started = true;
   }
+  HIP_TRY(launch_fill_u32(s.list_count, 1, 0, k->copy));
   HIP_TRY(launch_pagelist(c->d_dirty, c->d_victim, c->nwords, c->n_pages, s.list, s.list_count,
                           k->copy));
   CopyArgs a = copy_args(c, s, k->image, true, &s.counters[3]);
@@ -987,6 +988,22 @@ extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
   HIP_TRY(hipStreamWaitEvent(app, e, 0));
   HIP_TRY(hipEventDestroy(e));
   k->recopied = true;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_precopy(phos_ckpt *k, hipStream_t app) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_precopy: NULL checkpoint");
+  if (k->protocol != PHOS_RECOPY) return fail(PHOS_E_STATE, "pre-copy needs a recopy checkpoint");
+  if (k->recopied) return fail(PHOS_E_STATE, "recopy already done");
+  phos_ctx *c = k->ctx;
+  DeviceGuard g(c->device);
+  Slot &s = *k->slot;
+  // in the application's stream order: after the launches whose marks it
+  // copies, before those validated later
+  HIP_TRY(launch_fill_u32(s.list_count, 1, 0, app));
+  HIP_TRY(launch_pagelist(c->d_dirty, nullptr, c->nwords, c->n_pages, s.list, s.list_count, app));
+  CopyArgs a = copy_args(c, s, k->image, true, &s.counters[5]);
+  HIP_TRY(launch_precopy(a, s.list, s.list_count, c->d_dirty, c->bg_grid, app));
   return PHOS_OK;
 }
 
@@ -1050,13 +1067,14 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     k->bg_started = true;
   }
   if (k->host_image && c->image_bytes) TRY(drain_image(c, k));
-  HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, k->copy));
+  HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 6 * 8, hipMemcpyDeviceToHost, k->copy));
   HIP_TRY(hipStreamSynchronize(k->copy));
   HIP_TRY(hipStreamSynchronize(app));
   if (stats) {
     stats->bg_pages = c->h_pinned[1];
     stats->cow_pages = c->h_pinned[2];
     stats->recopy_pages = c->h_pinned[3];
+    stats->precopy_pages = c->h_pinned[5];
     stats->image_bytes = c->image_bytes;
   }
   bool timeout = false;

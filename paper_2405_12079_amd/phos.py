@@ -51,7 +51,8 @@ class phos_arg(ctypes.Structure):
 
 class phos_ckpt_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("cow_pages", ctypes.c_uint64),
-                ("recopy_pages", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64)]
+                ("recopy_pages", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
+                ("precopy_pages", ctypes.c_uint64)]
 
 
 class phos_rst_stats(ctypes.Structure):
@@ -86,6 +87,7 @@ SIGNATURES = [
     ("phos_ckpt_begin", [P, U32, U32, P, P, P, PP]),
     ("phos_ckpt_cow", [P, U32, P]),
     ("phos_ckpt_recopy", [P, P]),
+    ("phos_ckpt_precopy", [P, P]),
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
@@ -257,6 +259,10 @@ def phos_ckpt_cow(ck, spec, app_stream) -> None:
 
 def phos_ckpt_recopy(ck, app_stream) -> None:
     _call("phos_ckpt_recopy", ck, _stream(app_stream))
+
+
+def phos_ckpt_precopy(ck, app_stream) -> None:
+    _call("phos_ckpt_precopy", ck, _stream(app_stream))
 
 
 def phos_ckpt_end(ck, app_stream) -> phos_ckpt_stats:

@@ -109,11 +109,24 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(env.pool_host(), host)
 
 
-@pytest.mark.parametrize("mode", ["plain", "drain", "deferred", "implicit"])
+def _tracked(env, launches, j0, j1):
+    """The oracle's dirty and victim pages of launches j0..j1-1."""
+    w = env.world
+    d = np.zeros(w.n_pages, np.uint8)
+    v = np.zeros(w.n_pages, np.uint8)
+    for L in launches[j0:j1]:
+        iv = oracle.spec_build(env.table, L.arg_values(env.base))
+        oracle.track(iv, synth.records_host(env.hw, L), env.table, env.base, w.page_bytes,
+                     w.n_pages, d, v)
+    return d, v
+
+
+@pytest.mark.parametrize("mode", ["plain", "drain", "deferred", "implicit", "precopy"])
 def test_soft_recopy_config1(env, mode):
     """deferred: the background copy starts at the recopy, when every page the
     window wrote is already traced, so it copies exactly the untraced pages;
-    implicit: no recopy call, phos_ckpt_end recopies."""
+    implicit: no recopy call, phos_ckpt_end recopies; precopy: two pre-copy
+    rounds inside the window (iterative recopy)."""
     phos, w, T = env.phos, env.world, env.T
     drain = mode == "drain"
     launches = synth.config1_launches(w)
@@ -128,7 +141,10 @@ def test_soft_recopy_config1(env, mode):
     flags = phos.CKPT_DEFER_BACKGROUND if mode == "deferred" else 0
     ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, flags, image, himg, env.copy)
     out, cnt = env.violations_buffers(N)
+    rounds = [T1 + (T2 - T1) // 3, T1 + 2 * (T2 - T1) // 3] if mode == "precopy" else []
     for j in range(T1, T2):
+        if j in rounds:
+            phos.phos_ckpt_precopy(ck, env.app)
         L = launches[j]
         s = env.spec(L)
         r = st.records(j)
@@ -143,20 +159,26 @@ def test_soft_recopy_config1(env, mode):
         assert e.value.status == phos.E_STATE
     d = phos.phos_track_read(env.ctx, 0, w.n_pages)
     v = phos.phos_track_read(env.ctx, 1, w.n_pages)
-    assert np.array_equal(d, oracle.pages_to_bitmap(res.dirty, w.n_pages))
+    dirty_left = res.dirty
+    if rounds:  # the final recopy sees only the marks made after the last round
+        dirty_left = _tracked(env, launches, rounds[-1], T2)[0]
+    assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left, w.n_pages))
     assert np.array_equal(v, oracle.pages_to_bitmap(res.victim, w.n_pages))
     stats = phos.phos_ckpt_end(ck, env.app)
     want = res.snapshots[T2 - T1]
     assert np.array_equal(image.cpu().numpy(), want), "recopy image != snapshot at t2"
     if drain:
         assert np.array_equal(himg.numpy(), want), "drained host image differs"
-    rset = (res.dirty | res.victim) & _buffer_pages(w)
+    rset = (dirty_left | res.victim) & _buffer_pages(w)
     assert stats.recopy_pages == int(rset.sum())
+    pre = sum(int((_tracked(env, launches, a, b)[0] & _buffer_pages(w)).sum())
+              for a, b in zip([T1] + rounds[:-1], rounds))
+    assert stats.precopy_pages == pre
     n_img_pages = env.image_bytes // w.page_bytes
     if mode == "deferred":
         assert stats.bg_pages + stats.recopy_pages == n_img_pages
     else:
-        assert n_img_pages - stats.recopy_pages <= stats.bg_pages <= n_img_pages
+        assert n_img_pages - stats.recopy_pages - stats.precopy_pages <= stats.bg_pages <= n_img_pages
     # launches after t2 leave the image unchanged
     _run_plain(env, st, host, T2, T2 + 5)
     assert np.array_equal(image.cpu().numpy(), want)

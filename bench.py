@@ -20,7 +20,8 @@ The roofline object covers the dominant kernel (the background copy);
 `cpu_baseline` times the CPU oracle on a bounded sample of the same step.
 
 Other workloads: --config 3 batched uneven checkpoints, 4 serving loop,
-5 cold-start restore, 6 twin-kernel validator overhead, 7 preemptible drain.
+5 cold-start restore, 6 twin-kernel validator overhead, 7 preemptible drain,
+8 copy-on-write staging budget.
 
   python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--config 2]
 """
@@ -1098,6 +1099,115 @@ def run_drain(args):
     }
 
 
+def run_staging(args):
+    """Section 4.2 copy-on-write staging budget: the training-step layout and
+    launches with one copy-on-write checkpoint into a 16 GiB pinned host
+    image.  The background copy crosses PCIe (~0.3 s), so the pages the
+    launches write first are copied on demand; with a device staging area of
+    B bytes the first B bytes of them are copied at HBM speed, the rest over
+    PCIe.  Reports the launches' stall (loop time minus the same loop without
+    a checkpoint) against B."""
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    w = synth.config2_world()
+    n_launch, n_rec = args.launches, 1_000_000
+    launches = synth.config2_launches(w, n_launch, n_rec)
+    page = w.page_bytes
+    back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    pool = back[base - back.data_ptr(): base - back.data_ptr() + w.pool_bytes]
+    dw = synth.DeviceWorld(w, base)
+    recs = torch.empty(n_launch * n_rec, dtype=torch.int64, device="cuda")
+    for g in range(0, n_launch, 100):
+        synth.records_device(dw, launches[g:g + 100], n_rec, out=recs[g * n_rec:(g + 100) * n_rec])
+    ctx = phos.phos_create(0, base, w.pool_bytes, page)
+    phos.phos_buffers_register(ctx, w.buffers(base))
+    nimg = phos.phos_image_bytes(ctx)
+    himg = pinned_tensor(torch, nimg)
+    staging = torch.empty(nimg, dtype=torch.uint8, device="cuda")
+    snap = torch.empty(w.pool_bytes, dtype=torch.uint8, device="cuda")
+    specs = [phos.phos_spec_register(ctx, L.k, L.arg_values(base)) for L in launches]
+    rec_ptrs = [recs.data_ptr() + j * n_rec * 8 for j in range(n_launch)]
+    lcap = 2_000_000
+    vout = torch.empty(lcap * 32, dtype=torch.uint8, device="cuda")
+    vcnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
+    flags = phos.V_READS | phos.V_WRITES | phos.V_TRACK
+    log(f"[bench] CoW staging: {w.n_alloc} buffers, {nimg / 2**30:.2f} GiB host image, "
+        f"{n_launch} launches x {n_rec} accesses")
+
+    def loop(ck):
+        phos.phos_validate_batch(ctx, specs, rec_ptrs, [n_rec] * n_launch, flags, vout, lcap,
+                                 vcnt.data_ptr(), app)
+        for j, L in enumerate(launches):
+            if ck is not None:
+                phos.phos_ckpt_cow(ck, specs[j], app)
+            synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
+
+    def fresh():
+        synth.content_device(pool, w.seed)
+        torch.cuda.synchronize()
+
+    t = Timer(torch, app)
+    alone = []
+    for _ in range(2):
+        fresh()
+        t.start()
+        loop(None)
+        t.stop()
+        app.synchronize()
+        alone.append(t.ms())
+    alone_ms = float(np.median(alone))
+    log(f"[bench] launches without a checkpoint: {alone_ms:.2f} ms")
+    # sampled image pages checked against the pool at t1
+    rng = np.random.default_rng(8)
+    img_off = np.concatenate([[0], np.cumsum(w.alloc_bytes.astype(np.int64))])
+    samples = rng.integers(0, nimg // page, 2048)
+    rows = {}
+    for mib in [int(x) for x in args.budgets.split(",")]:
+        fresh()
+        snap.copy_(pool)
+        torch.cuda.synchronize()
+        ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, himg.data_ptr(), None, cpy)
+        phos.phos_ckpt_staging(ck, staging, min(mib << 20, nimg))
+        t.start()
+        loop(ck)
+        t.stop()
+        t0 = time.perf_counter()
+        st = phos.phos_ckpt_end(ck, app)
+        end_s = time.perf_counter() - t0
+        loop_ms = t.ms()
+        ok = True
+        for p in samples.tolist():
+            b = int(np.searchsorted(img_off, p * page, side="right") - 1)
+            src = int(w.alloc_off[b]) + p * page - int(img_off[b])
+            ok &= bool(torch.equal(himg[p * page:(p + 1) * page],
+                                   snap[src:src + page].cpu()))
+        assert ok, f"host image differs from the pool at t1 (budget {mib} MiB)"
+        rows[mib] = {"loop_ms": round(loop_ms, 2), "stall_ms": round(loop_ms - alone_ms, 2),
+                     "cow_pages": int(st.cow_pages), "staged_pages": int(st.staged_pages),
+                     "background_pages": int(st.bg_pages), "end_s": round(end_s, 3)}
+        log(f"[bench] budget {mib} MiB: {rows[mib]}")
+    phos.phos_destroy(ctx)
+    first = rows[min(rows)]
+    return {
+        "metric": "copy-on-write stall of the launches (ms per step) vs the device staging budget",
+        "value": rows[max(rows)]["stall_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": rows[max(rows)]["loop_ms"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded layout, access streams and contents)",
+        "config": {"workload": "CoW staging: training-step layout, 1000 launches x 1e6 accesses, "
+                               "16 GiB pinned host image, budgets " + args.budgets + " MiB"},
+        "launches_without_checkpoint_ms": round(alone_ms, 2),
+        "by_budget_mib": rows, "stall_ms_without_staging": first["stall_ms"],
+        "parity": "2048 sampled image pages equal the pool at t1 for every budget",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1118,6 +1228,8 @@ def main():
     ap.add_argument("--precopy", action="store_true",
                     help="config 2: a pre-copy round of the recopy image before each validation "
                          "chunk after the first (iterative recopy; use with --val-chunk)")
+    ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",
+                    help="config 8: staging budgets in MiB")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
     ap.add_argument("--app-graph", action="store_true",
                     help="replay the per-launch copy-on-write + application loop as one HIP "
@@ -1140,6 +1252,8 @@ def main():
         res = run_twin(args)
     elif args.config == 7:
         res = run_drain(args)
+    elif args.config == 8:
+        res = run_staging(args)
     else:
         sys.exit(f"unknown config {args.config}")
     print(json.dumps(res), flush=True)

@@ -115,6 +115,7 @@ typedef struct {
   uint64_t recopy_pages; /* pages recopied after the re-quiesce                */
   uint64_t image_bytes;  /* bytes of the image                                 */
   uint64_t precopy_pages; /* pages copied by pre-copy rounds                   */
+  uint64_t staged_pages;  /* copy-on-write pages that went through staging      */
 } phos_ckpt_stats;
 
 typedef struct {
@@ -137,7 +138,8 @@ typedef struct {
  *
  * Tuning, read from the environment here (defaults in brackets):
  *   PHOS_SPIN_LIMIT      polls before a device wait gives up [1 << 22]
- *   PHOS_BG_GRID         background copy blocks [CUs]; PHOS_COW_GRID [4 x CUs]
+ *   PHOS_BG_GRID         background copy blocks [CUs]; PHOS_COW_GRID [4 x CUs];
+ *                        PHOS_BG_GRID_HOST when copying into a host image [8]
  *   PHOS_BG_BATCH        pages a background block claims per batch [64];
  *                        PHOS_BG_BATCH_PCIE when the image is in host memory [4]
  *   PHOS_COPY_NT         streaming (non-temporal) device copies [1]
@@ -239,13 +241,24 @@ phos_status phos_track_read(phos_ctx *ctx, uint32_t which, uint32_t *host_words,
 /* Section 4.2 / 4.3: open a concurrent checkpoint.  The caller has quiesced
  * the application (its streams are idle).  image: device memory of
  * phos_image_bytes() bytes that receives the image (pinned host memory means
- * copying straight to the host).  host_image: optional pinned host memory
+ * copying straight to the host; E_INVAL for pageable memory).  host_image: optional pinned host memory
  * filled from image by phos_ckpt_end (NULL: none).  The background copy of
  * every page starts on copy_stream unless PHOS_CKPT_DEFER_BACKGROUND.
  * Opening resets the dirty / victim bitmaps when no other checkpoint is
  * open.  At most one checkpoint per protocol may be open (E_STATE). */
 phos_status phos_ckpt_begin(phos_ctx *ctx, uint32_t protocol, uint32_t flags, void *image,
                             void *host_image, hipStream_t copy_stream, phos_ckpt **out);
+
+/* Section 4.2, CoW staging for a checkpoint into a host image (pinned): the
+ * copy-on-write copies, which a launch waits for, go first into `staging`
+ * (device memory, the caller's, `bytes` rounded down to whole pages) at HBM
+ * speed instead of over PCIe; once it is full they go straight to the host
+ * image.  phos_ckpt_end moves the staged pages into the image.  Call after
+ * phos_ckpt_begin and before the first phos_ckpt_cow (E_STATE otherwise, or
+ * for a recopy checkpoint); bytes below one page: no staging.  E_INVAL for
+ * a device image or staging that is not 16-byte aligned device memory.
+ * The staging memory must stay allocated until phos_ckpt_end returns. */
+phos_status phos_ckpt_staging(phos_ckpt *ck, void *staging, uint64_t bytes);
 
 /* Section 4.2: before the launch described by `spec` runs on app_stream,
  * copy every page it may write that the checkpoint has not copied yet: the

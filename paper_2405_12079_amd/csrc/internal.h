@@ -105,6 +105,13 @@ struct CopyArgs {
   // which the host publishes with a small kernel after the page's DMA.
   uint32_t *want = nullptr;
   uint32_t want_cap = 0;
+  // Checkpoint into a host image: copy-on-write pages go first to a device
+  // staging area of stage_cap pages (slots taken in order from *stage_head;
+  // stage_page[slot] = the pool page), straight to the host image after.
+  uint8_t *stage = nullptr;
+  uint32_t *stage_page = nullptr;
+  unsigned long long *stage_head = nullptr;
+  uint32_t stage_cap = 0;
   // Restore: blocks copying pages a launch needs now (on demand) count
   // themselves here while they copy; the background copy claims no new
   // pages while it is nonzero, so on-demand copies get the link first.
@@ -185,6 +192,7 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
                            uint32_t *list, unsigned int *count, hipStream_t s);
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s);
+hipError_t launch_unstage(const CopyArgs &c, uint32_t grid, hipStream_t s);
 hipError_t launch_precopy(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                           uint8_t *dirty, uint32_t grid, hipStream_t s);
 hipError_t launch_demand(const CopyArgs &c, const uint64_t *rec, uint64_t n, uint64_t pool_base,

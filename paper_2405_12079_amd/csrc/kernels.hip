@@ -592,7 +592,28 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   // back while they move (this block waits for nobody until it lets go)
   const bool priority = nwon && C.demand && !C.to_image;
   if (priority && threadIdx.x == 0) atomicAdd(C.demand, 1ull);
-  for (uint32_t i = 0; i < nwon; ++i) copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
+  if (C.stage && C.to_image) {
+    // copy-on-write into a host image: the first pages go to the device
+    // staging area at HBM speed (moved to the image when the checkpoint
+    // ends), the rest straight to the host once the area is full
+    __shared__ unsigned long long s_slot0;
+    if (threadIdx.x == 0) s_slot0 = nwon ? atomicAdd(C.stage_head, (unsigned long long)nwon) : 0;
+    __syncthreads();
+    const unsigned long long slot0 = s_slot0;
+    const uint64_t pb = 1ull << C.page_shift;
+    for (uint32_t i = 0; i < nwon; ++i) {
+      const unsigned long long slot = slot0 + i;
+      if (slot < C.stage_cap) {
+        block_copy16(reinterpret_cast<const uint4 *>(C.pool + ((uint64_t)s_won[i] << C.page_shift)),
+                     reinterpret_cast<uint4 *>(C.stage + slot * pb), pb >> 4, C.nt != 0);
+        if (threadIdx.x == 0) C.stage_page[slot] = s_won[i];
+      } else {
+        copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
+      }
+    }
+  } else {
+    for (uint32_t i = 0; i < nwon; ++i) copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
+  }
   // Publishing "done".  Checkpoint direction: a waiter only needs this
   // block's reads of the pool to have returned (the image is read after the
   // kernel ends), so waiting for every outstanding access is enough.
@@ -853,6 +874,22 @@ __global__ void __launch_bounds__(kBgCopyThreads)
     __syncthreads();  // s_own is rewritten for the next page
   }
   if (threadIdx.x == 0 && nw) atomicAdd(C.stat, (unsigned long long)nw);
+}
+
+// Staged copy-on-write pages -> their places in the host image (at the end
+// of the checkpoint, after every copy that could stage one).
+__global__ void __launch_bounds__(kBgCopyThreads) unstage_kernel(CopyArgs C) {
+  const unsigned long long head = *C.stage_head;
+  const uint64_t n = head < C.stage_cap ? head : C.stage_cap;
+  const uint64_t pb = 1ull << C.page_shift;
+  for (uint64_t slot = blockIdx.x; slot < n; slot += gridDim.x) {
+    const uint32_t p = C.stage_page[slot];
+    const uint32_t ip = p < C.n_pages ? C.img_page[p] : kNone;
+    if (ip == kNone) continue;
+    block_copy16(reinterpret_cast<const uint4 *>(C.stage + slot * pb),
+                 reinterpret_cast<uint4 *>(C.image + ((uint64_t)ip << C.page_shift)), pb >> 4,
+                 false);
+  }
 }
 
 // Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
@@ -1259,6 +1296,11 @@ hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, 
   if (!nwords) return hipSuccess;
   hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, nwords,
                      n_pages, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_unstage(const CopyArgs &c, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(unstage_kernel, dim3(grid), dim3(kBgCopyThreads), 0, s, c);
   return hipGetLastError();
 }
 

@@ -133,6 +133,7 @@ struct phos_ctx {
   hsa_agent_t gpu_agent{0}, cpu_agent{0};
 
   uint32_t bg_grid = 1024, cow_grid = 1024, spin_limit = 1u << 22, copy_nt = 0;
+  uint32_t bg_grid_host = 8;  // background blocks copying into a host image
   // restore: how long (polls of ~0.5 us) the background holds back per batch
   // while on-demand copies run (0: never), and 16 loads in flight per thread
   // for the on-demand / background copies of an image in host memory
@@ -159,6 +160,12 @@ struct phos_ckpt {
   bool bg_known_done = false;
   hipStream_t cow_stream = nullptr;  // the one stream CoW calls came from
   bool cow_streams_many = false;
+  bool host = false;  // the image is in host memory (copies cross PCIe)
+  // copy-on-write staging area (device memory, the caller's) for a host image
+  uint8_t *stage = nullptr;
+  uint32_t *d_stage_page = nullptr;
+  unsigned long long *d_stage_head = nullptr;
+  uint32_t stage_cap = 0;
 };
 
 constexpr uint32_t kWantCap = 16384;      // asked-for pages the host can see per restore
@@ -271,6 +278,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->n_cu = (uint32_t)prop.multiProcessorCount;
   c->bg_grid = env_u32("PHOS_BG_GRID", c->n_cu);
+  c->bg_grid_host = std::max<uint32_t>(1, env_u32("PHOS_BG_GRID_HOST", 8));
   c->cow_grid = env_u32("PHOS_COW_GRID", 4 * c->n_cu);
   c->bg_batch = env_u32("PHOS_BG_BATCH", 64);
   c->bg_batch_pcie = env_u32("PHOS_BG_BATCH_PCIE", 4);
@@ -821,6 +829,19 @@ static phos_status ensure_slot(phos_ctx *c, Slot &s, bool with_list) {
   return PHOS_OK;
 }
 
+// Can this device's kernels read the memory at p (device memory or pinned
+// host memory)?  Pageable host memory cannot be read without page faults.
+static bool device_readable(const void *p, bool *in_host = nullptr) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    if (in_host) *in_host = true;
+    return false;
+  }
+  if (in_host) *in_host = at.type != hipMemoryTypeDevice;
+  return at.type != hipMemoryTypeUnregistered;
+}
+
 static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
                           unsigned long long *stat) {
   CopyArgs a;
@@ -849,18 +870,24 @@ static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a
   const uint32_t grab = std::max<uint32_t>(1, (64u << 10) >> c->page_shift);
   const uint32_t groups = (c->n_pages + grab - 1) / grab;
   const uint32_t batch = std::max<uint32_t>(1, over_pcie ? c->bg_batch_pcie : c->bg_batch);
-  HIP_TRY(launch_background(a, grab, batch, std::min(c->bg_grid, groups), stream));
+  // Stores to host memory are posted: a full grid keeps megabytes of them
+  // queued for a 50 GB/s link, and the application's own memory traffic
+  // waits behind them (measured: launches ran only once the whole copy had
+  // ended).  A few blocks fill the link.
+  const uint32_t grid = over_pcie && a.to_image ? std::min(c->bg_grid, c->bg_grid_host) : c->bg_grid;
+  HIP_TRY(launch_background(a, grab, batch, std::min(grid, groups), stream));
   return PHOS_OK;
 }
 
 static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
-                                    hipStream_t stream, bool skip_traced = false) {
+                                    hipStream_t stream, bool skip_traced = false,
+                                    bool over_pcie = false) {
   CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
   if (skip_traced) {  // recopy: pages traced as written are left to the recopy
     a.skip_dirty = c->d_dirty;
     a.skip_victim = c->d_victim;
   }
-  return start_background_args(c, s, a, stream);
+  return start_background_args(c, s, a, stream, over_pcie);
 }
 
 // Pages of the intervals with any of `modes`, clamped to the pool.
@@ -915,8 +942,12 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   k->host_image = host_image;
   k->copy = copy;
   k->slot = &s;
+  if (!device_readable(image, &k->host)) {
+    delete k;
+    return fail(PHOS_E_INVAL, "the image must be device or pinned host memory");
+  }
   if (!(flags & PHOS_CKPT_DEFER_BACKGROUND)) {
-    phos_status st = start_background(c, s, k->image, true, copy, protocol == PHOS_RECOPY);
+    phos_status st = start_background(c, s, k->image, true, copy, protocol == PHOS_RECOPY, k->host);
     if (st == PHOS_OK && (hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming) != hipSuccess ||
                           hipEventRecord(k->bg_done, copy) != hipSuccess))
       st = fail(PHOS_E_HIP, "background completion event");
@@ -929,6 +960,35 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   }
   c->open_ckpt[protocol] = k;
   *out = k;
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_staging(phos_ckpt *k, void *staging, uint64_t bytes) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_staging: NULL checkpoint");
+  if (k->protocol != PHOS_COW) return fail(PHOS_E_STATE, "staging needs a CoW checkpoint");
+  if (k->stage || k->cow_stream) return fail(PHOS_E_STATE, "staging set twice or after a CoW call");
+  phos_ctx *c = k->ctx;
+  if (!k->host) return fail(PHOS_E_INVAL, "staging is for a checkpoint into a host image");
+  const uint64_t cap = std::min<uint64_t>(bytes >> c->page_shift, c->n_pages);
+  if (!cap) return PHOS_OK;  // no staging: every copy goes straight to the image
+  bool in_host = true;
+  if (!staging || ((uintptr_t)staging & 15) || !device_readable(staging, &in_host) || in_host)
+    return fail(PHOS_E_INVAL, "staging must be 16-byte aligned device memory");
+  DeviceGuard g(c->device);
+  TRY(dalloc(&k->d_stage_page, cap));
+  phos_status st = dalloc(&k->d_stage_head, 1);
+  if (st == PHOS_OK && (launch_fill_u64(k->d_stage_head, 1, 0, c->aux) != hipSuccess ||
+                        hipStreamSynchronize(c->aux) != hipSuccess))
+    st = fail(PHOS_E_HIP, "staging set-up");
+  if (st != PHOS_OK) {
+    (void)hipFree(k->d_stage_page);
+    if (k->d_stage_head) (void)hipFree(k->d_stage_head);
+    k->d_stage_page = nullptr;
+    k->d_stage_head = nullptr;
+    return st;
+  }
+  k->stage = static_cast<uint8_t *>(staging);
+  k->stage_cap = (uint32_t)cap;
   return PHOS_OK;
 }
 
@@ -957,6 +1017,12 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   }
   const PageRanges r = page_ranges(c, *h, PHOS_W);
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
+  if (k->stage) {
+    a.stage = k->stage;
+    a.stage_page = k->d_stage_page;
+    a.stage_head = k->d_stage_head;
+    a.stage_cap = k->stage_cap;
+  }
   const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords};
   HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, app));
   return PHOS_OK;
@@ -975,7 +1041,7 @@ extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
   HIP_TRY(hipEventRecord(e, app));
   HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
   if (!k->bg_started) {
-    TRY(start_background(c, s, k->image, true, k->copy, true));
+    TRY(start_background(c, s, k->image, true, k->copy, true, k->host));
     k->bg_started = true;
   }
   HIP_TRY(launch_fill_u32(s.list_count, 1, 0, k->copy));
@@ -1063,8 +1129,17 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
   HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!k->bg_started) {
-    TRY(start_background(c, s, k->image, true, k->copy));
+    TRY(start_background(c, s, k->image, true, k->copy, false, k->host));
     k->bg_started = true;
+  }
+  if (k->stage) {  // staged copy-on-write pages to their places in the host image
+    CopyArgs a = copy_args(c, s, k->image, true, nullptr);
+    a.stage = k->stage;
+    a.stage_page = k->d_stage_page;
+    a.stage_head = k->d_stage_head;
+    a.stage_cap = k->stage_cap;
+    HIP_TRY(launch_unstage(a, c->bg_grid, k->copy));
+    HIP_TRY(hipMemcpyAsync(c->h_pinned + 6, k->d_stage_head, 8, hipMemcpyDeviceToHost, k->copy));
   }
   if (k->host_image && c->image_bytes) TRY(drain_image(c, k));
   HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 6 * 8, hipMemcpyDeviceToHost, k->copy));
@@ -1075,12 +1150,15 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     stats->cow_pages = c->h_pinned[2];
     stats->recopy_pages = c->h_pinned[3];
     stats->precopy_pages = c->h_pinned[5];
+    stats->staged_pages = k->stage ? std::min<uint64_t>(c->h_pinned[6], k->stage_cap) : 0;
     stats->image_bytes = c->image_bytes;
   }
   bool timeout = false;
   TRY(read_err(c, k->copy, &timeout));
   c->open_ckpt[k->protocol] = nullptr;
   if (k->bg_done) (void)hipEventDestroy(k->bg_done);
+  if (k->d_stage_page) (void)hipFree(k->d_stage_page);
+  if (k->d_stage_head) (void)hipFree(k->d_stage_head);
   delete k;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the image is not valid");
   return PHOS_OK;
@@ -1121,18 +1199,6 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
                                 const void *const *chunks, uint32_t nchunks, uint64_t chunk_bytes,
                                 hipStream_t copy, phos_rst **out);
 
-// Can this device's kernels read the memory at p (device memory or pinned
-// host memory)?  Pageable host memory cannot be read without page faults.
-static bool device_readable(const void *p, bool *in_host = nullptr) {
-  hipPointerAttribute_t at;
-  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-    (void)hipGetLastError();
-    if (in_host) *in_host = true;
-    return false;
-  }
-  if (in_host) *in_host = at.type != hipMemoryTypeDevice;
-  return at.type != hipMemoryTypeUnregistered;
-}
 
 extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const void *image,
                                           hipStream_t copy, phos_rst **out) {

@@ -52,7 +52,7 @@ class phos_arg(ctypes.Structure):
 class phos_ckpt_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("cow_pages", ctypes.c_uint64),
                 ("recopy_pages", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
-                ("precopy_pages", ctypes.c_uint64)]
+                ("precopy_pages", ctypes.c_uint64), ("staged_pages", ctypes.c_uint64)]
 
 
 class phos_rst_stats(ctypes.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = [
     ("phos_ckpt_cow", [P, U32, P]),
     ("phos_ckpt_recopy", [P, P]),
     ("phos_ckpt_precopy", [P, P]),
+    ("phos_ckpt_staging", [P, P, U64]),
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
@@ -259,6 +260,10 @@ def phos_ckpt_cow(ck, spec, app_stream) -> None:
 
 def phos_ckpt_recopy(ck, app_stream) -> None:
     _call("phos_ckpt_recopy", ck, _stream(app_stream))
+
+
+def phos_ckpt_staging(ck, staging, nbytes) -> None:
+    _call("phos_ckpt_staging", ck, _ptr(staging), nbytes)
 
 
 def phos_ckpt_precopy(ck, app_stream) -> None:

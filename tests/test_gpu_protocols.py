@@ -109,6 +109,67 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(env.pool_host(), host)
 
 
+@pytest.mark.parametrize("defer,budget", [(True, 0), (True, 10), (True, None), (False, 64)])
+def test_cow_staging_host_image(env, defer, budget):
+    """Copy-on-write into a pinned host image through a device staging area of
+    `budget` pages (None: room for every page): staged pages reach the image
+    at the end, the overflow goes straight to the host; the image is the t1
+    snapshot either way."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(0,), cow_window=(0, T2 - T1), keep_violations=False)
+    himg = T.zeros(env.image_bytes, dtype=T.uint8, pin_memory=True)
+    pages = w.n_pages if budget is None else budget
+    staging = T.empty(max(1, pages) * w.page_bytes, dtype=T.uint8, device="cuda")
+    T.cuda.synchronize()
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND if defer else 0,
+                              himg, None, env.copy)
+    phos.phos_ckpt_staging(ck, staging, pages * w.page_bytes)
+    out, cnt = env.violations_buffers(N)
+    for j in range(T1, T2):
+        L = launches[j]
+        s = env.spec(L)
+        r = st.records(j)
+        _validate(env, s, r, out, cnt)
+        phos.phos_ckpt_cow(ck, s, env.app)
+        env.mutate(L, r.data_ptr(), N)
+        phos.phos_spec_release(env.ctx, s)
+    stats = phos.phos_ckpt_end(ck, env.app)
+    assert np.array_equal(himg.numpy(), res.snapshots[0]), "CoW host image != snapshot at t1"
+    n_img_pages = env.image_bytes // w.page_bytes
+    assert stats.bg_pages + stats.cow_pages == n_img_pages
+    assert stats.staged_pages == min(stats.cow_pages, pages)
+    if defer:
+        assert stats.cow_pages == sum(len(c) for c in res.cow_sets)
+    assert np.array_equal(env.pool_host(), host)
+
+
+def test_staging_rejects_bad_use(env):
+    phos, T = env.phos, env.T
+    dimg = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    staging = T.empty(1 << 20, dtype=T.uint8, device="cuda")
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, dimg, None, env.copy)
+    with pytest.raises(phos.PhosError) as e:  # a device image needs no staging
+        phos.phos_ckpt_staging(ck, staging, 1 << 20)
+    assert e.value.status == phos.E_INVAL
+    phos.phos_ckpt_end(ck, env.app)
+    himg = T.empty(env.image_bytes, dtype=T.uint8, pin_memory=True)
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, himg, None, env.copy)
+    with pytest.raises(phos.PhosError) as e:  # staging in host memory
+        phos.phos_ckpt_staging(ck, himg, 1 << 20)
+    assert e.value.status == phos.E_INVAL
+    phos.phos_ckpt_end(ck, env.app)
+    pageable = T.empty(env.image_bytes, dtype=T.uint8)
+    with pytest.raises(phos.PhosError) as e:  # no kernel may write pageable memory
+        phos.phos_ckpt_begin(env.ctx, phos.COW, 0, pageable, None, env.copy)
+    assert e.value.status == phos.E_INVAL
+
+
 def _tracked(env, launches, j0, j1):
     """The oracle's dirty and victim pages of launches j0..j1-1."""
     w = env.world

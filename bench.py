@@ -232,7 +232,39 @@ def run_training_step(args):
     t_rec = Timer(torch, cpy)
     graph = None
 
+    def start_copies(ca, cb):
+        # the background copies start once the first validation pass is done:
+        # they then share HBM with the latency-bound launches, not with it
+        cpy.wait_stream(app)
+        t_bg_a.start()
+        phos.phos_ckpt_start(ca, None)
+        t_bg_a.stop()
+        t_bg_b.start()
+        phos.phos_ckpt_start(cb, None)
+        t_bg_b.stop()
+
+    vstream = torch.cuda.Stream() if args.pipelined_validation else None
+    vdone = [torch.cuda.Event() for _ in range(nchunk)] if vstream is not None else []
+
+    def app_loop_pipelined(ca, cb):
+        # every chunk's validation is issued on its own stream up front; the
+        # launches of chunk c wait only for chunk c's pass, so the passes run
+        # beside the (latency-bound) launches of earlier chunks
+        vstream.wait_stream(app)
+        for c in range(nchunk):
+            sl = slice(c * chunk, min((c + 1) * chunk, n_launch))
+            phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], [n_rec] * len(specs[sl]),
+                                     VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, vstream)
+            vdone[c].record(vstream)
+        for j, L in enumerate(launches):
+            if j % chunk == 0:
+                app.wait_event(vdone[j // chunk])
+            phos.phos_ckpt_cow(ca, specs[j], app)
+            synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
+
     def app_loop(ca, cb):
+        if vstream is not None:
+            return app_loop_pipelined(ca, cb)
         for j, L in enumerate(launches):
             if j % chunk == 0:  # validate the next `chunk` launches' access streams
                 c = j // chunk
@@ -241,6 +273,8 @@ def run_training_step(args):
                 sl = slice(j, min(j + chunk, n_launch))
                 phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], [n_rec] * len(specs[sl]),
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
+                if j == 0 and args.copy_after_validation:
+                    start_copies(ca, cb)
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 
@@ -248,12 +282,16 @@ def run_training_step(args):
 
     def step():
         nonlocal graph, warm
-        t_bg_a.start()
-        ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
-        t_bg_a.stop()
-        t_bg_b.start()
-        cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, 0, img_b, None, cpy)
-        t_bg_b.stop()
+        if args.copy_after_validation:
+            ca = phos.phos_ckpt_begin(ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, img_a, None, cpy)
+            cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, phos.CKPT_DEFER_BACKGROUND, img_b, None, cpy)
+        else:
+            t_bg_a.start()
+            ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
+            t_bg_a.stop()
+            t_bg_b.start()
+            cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, 0, img_b, None, cpy)
+            t_bg_b.stop()
         t_app.start()
         if args.app_graph and warm:
             if graph is None:
@@ -1225,6 +1263,12 @@ def main():
     ap.add_argument("--small-mib", type=int, default=1024,
                     help="batched order: requests with at most this many MiB left go first")
     ap.add_argument("--twin-n", type=int, default=1 << 28, help="elements per array (config 6)")
+    ap.add_argument("--copy-after-validation", dest="copy_after_validation", action="store_true",
+                    help="config 2: open the checkpoints with deferred background copies and "
+                         "start them after the first validation pass")
+    ap.add_argument("--pipelined-validation", dest="pipelined_validation", action="store_true",
+                    help="config 2: validate the launch chunks on their own stream ahead of the "
+                         "launches (use with --val-chunk)")
     ap.add_argument("--precopy", action="store_true",
                     help="config 2: a pre-copy round of the recopy image before each validation "
                          "chunk after the first (iterative recopy; use with --val-chunk)")
@@ -1236,6 +1280,11 @@ def main():
                          "graph (eager is faster: it skips copy-on-write once the background "
                          "copy is known done)")
     args = ap.parse_args()
+    if args.pipelined_validation and (args.app_graph or args.precopy or args.copy_after_validation):
+        sys.exit("--pipelined-validation runs alone (no --app-graph, --precopy, "
+                 "--copy-after-validation)")
+    if args.copy_after_validation and args.app_graph:
+        sys.exit("--copy-after-validation starts the copies on another stream: not with --app-graph")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the hot path is per GPU and shards by process "
               f"(one pool per GPU), so --gpus {args.gpus} is not run.", file=sys.stderr)

@@ -260,6 +260,14 @@ phos_status phos_ckpt_begin(phos_ctx *ctx, uint32_t protocol, uint32_t flags, vo
  * The staging memory must stay allocated until phos_ckpt_end returns. */
 phos_status phos_ckpt_staging(phos_ckpt *ck, void *staging, uint64_t bytes);
 
+/* Start the background copy of a checkpoint opened with
+ * PHOS_CKPT_DEFER_BACKGROUND now, on its copy_stream, after the work already
+ * enqueued on `after` (NULL: no wait).  Lets a caller keep the bandwidth-bound
+ * copy away from bandwidth-bound work it must finish first (e.g. the
+ * validation of the launches) and beside latency-bound launches instead.
+ * E_STATE if the background copy has started or the recopy is done. */
+phos_status phos_ckpt_start(phos_ckpt *ck, hipStream_t after);
+
 /* Section 4.2: before the launch described by `spec` runs on app_stream,
  * copy every page it may write that the checkpoint has not copied yet: the
  * pages of its write intervals and the victim pages marked by validation.

@@ -963,6 +963,27 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   return PHOS_OK;
 }
 
+extern "C" phos_status phos_ckpt_start(phos_ckpt *k, hipStream_t after) {
+  if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_start: NULL checkpoint");
+  if (k->bg_started) return fail(PHOS_E_STATE, "the background copy has started");
+  if (k->recopied) return fail(PHOS_E_STATE, "recopy already done");
+  phos_ctx *c = k->ctx;
+  DeviceGuard g(c->device);
+  if (after) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t he = hipEventRecord(e, after);
+    if (he == hipSuccess) he = hipStreamWaitEvent(k->copy, e, 0);
+    (void)hipEventDestroy(e);
+    if (he != hipSuccess) return fail(PHOS_E_HIP, "phos_ckpt_start: %s", hipGetErrorString(he));
+  }
+  TRY(start_background(c, *k->slot, k->image, true, k->copy, k->protocol == PHOS_RECOPY, k->host));
+  k->bg_started = true;
+  if (!k->bg_done) HIP_TRY(hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(k->bg_done, k->copy));
+  return PHOS_OK;
+}
+
 extern "C" phos_status phos_ckpt_staging(phos_ckpt *k, void *staging, uint64_t bytes) {
   if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_staging: NULL checkpoint");
   if (k->protocol != PHOS_COW) return fail(PHOS_E_STATE, "staging needs a CoW checkpoint");

@@ -89,6 +89,7 @@ SIGNATURES = [
     ("phos_ckpt_recopy", [P, P]),
     ("phos_ckpt_precopy", [P, P]),
     ("phos_ckpt_staging", [P, P, U64]),
+    ("phos_ckpt_start", [P, P]),
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
@@ -260,6 +261,10 @@ def phos_ckpt_cow(ck, spec, app_stream) -> None:
 
 def phos_ckpt_recopy(ck, app_stream) -> None:
     _call("phos_ckpt_recopy", ck, _stream(app_stream))
+
+
+def phos_ckpt_start(ck, after=None) -> None:
+    _call("phos_ckpt_start", ck, _stream(after))
 
 
 def phos_ckpt_staging(ck, staging, nbytes) -> None:

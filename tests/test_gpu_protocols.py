@@ -70,8 +70,10 @@ def _validate(env, spec, r, out, cnt, flags=V):
     env.phos.phos_validate(env.ctx, spec, r, N, flags, out, N, cnt, env.app)
 
 
-@pytest.mark.parametrize("defer", [True, False])
+@pytest.mark.parametrize("defer", [True, False, "start"])
 def test_soft_cow_config1(env, defer):
+    """defer: background copy at the end; "start": deferred, then started by
+    phos_ckpt_start after the fifth launch of the window."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -93,7 +95,12 @@ def test_soft_cow_config1(env, defer):
         phos.phos_ckpt_cow(ck, s, env.app)
         env.mutate(L, r.data_ptr(), N)
         cum[res.cow_sets[j - T1].astype(np.int64)] = 1
-        if defer and (j - T1) % 7 == 0:
+        if defer == "start" and j == T1 + 4:
+            phos.phos_ckpt_start(ck, env.app)
+            with pytest.raises(phos.PhosError) as e:  # started once
+                phos.phos_ckpt_start(ck, env.app)
+            assert e.value.status == phos.E_STATE
+        if defer is True and (j - T1) % 7 == 0:
             env.app.synchronize()
             got = bits_to_pages(phos.phos_ckpt_copied(ck, w.n_pages), w.n_pages)
             assert np.array_equal(got, cum), f"copy set after launch {j}"
@@ -102,7 +109,7 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(image.cpu().numpy(), res.snapshots[0]), "CoW image != snapshot at t1"
     n_img_pages = env.image_bytes // w.page_bytes
     assert stats.bg_pages + stats.cow_pages == n_img_pages
-    if defer:
+    if defer is True:
         assert stats.cow_pages == int(cum.sum())
     assert stats.recopy_pages == 0
     # the application's own writes went to the pool, unaffected by the checkpoint

@@ -480,33 +480,47 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-// Move each tile's violations from scratch to their ordered place.
-__global__ void __launch_bounds__(1024)
+// Move each tile's violations from scratch to their ordered place.  One
+// block per kScatTiles tiles (a call of 30,000 tiles fills the GPU instead of
+// 30 CUs): the block adds up the counts of its segment's tiles before its
+// own, scans its own counts in one wave, and its four waves move the tiles,
+// one violation per lane as two 16-byte loads and stores.
+constexpr uint32_t kScatTiles = 64;
+static_assert(kSeg % kScatTiles == 0, "a scatter block's tiles lie in one segment");
+
+__global__ void __launch_bounds__(256)
     vscatter_kernel(const uint32_t *tile_count, const unsigned long long *tile_off, uint32_t ntiles,
                     const unsigned long long *seg_prefix, const phos_violation *scratch,
                     uint64_t scratch_cap, phos_violation *out, uint64_t cap) {
-  __shared__ uint32_t s[1024];
-  const uint32_t t = threadIdx.x;
-  const uint32_t tile = blockIdx.x * 1024 + t;
-  const uint32_t c = tile < ntiles ? tile_count[tile] : 0;
-  s[t] = c;
+  __shared__ unsigned long long s_red[4];
+  __shared__ uint32_t s_cnt[kScatTiles];
+  __shared__ unsigned long long s_dst[kScatTiles];
+  const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+  const uint32_t tile0 = blockIdx.x * kScatTiles;
+  const uint32_t seg0 = tile0 / kSeg * kSeg;
+  unsigned long long before = 0;  // this segment's violations before tile0
+  for (uint32_t k = seg0 + t; k < tile0; k += 256) before += tile_count[k];
+  for (uint32_t d = 32; d; d >>= 1) before += __shfl_xor(before, (int)d, 64);
+  if (lane == 0) s_red[wave] = before;
   __syncthreads();
-  for (uint32_t d = 1; d < 1024; d <<= 1) {
-    const uint32_t x = t >= d ? s[t - d] : 0;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }  // s: inclusive prefix of the segment's tile counts
-  // wave w moves tiles w, w + 16, ... of this segment, one violation per
-  // lane, as two 16-byte loads and stores
-  const uint32_t wave = t >> 6, lane = t & 63u;
-  const unsigned long long base = seg_prefix[blockIdx.x];
-  for (uint32_t k = wave; k < 1024; k += 16) {
-    const uint32_t tk = blockIdx.x * 1024 + k;
+  if (wave == 0) {
+    const uint32_t tk = tile0 + lane;
+    const uint32_t c = tk < ntiles ? tile_count[tk] : 0u;
+    uint32_t incl = c;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t x = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += x;
+    }
+    s_cnt[lane] = c;
+    s_dst[lane] = seg_prefix[tile0 / kSeg] + s_red[0] + s_red[1] + s_red[2] + s_red[3] + (incl - c);
+  }
+  __syncthreads();
+  for (uint32_t k = wave; k < kScatTiles; k += 4) {
+    const uint32_t tk = tile0 + k;
     if (tk >= ntiles) break;
-    const uint32_t ck = s[k] - (k ? s[k - 1] : 0u);
+    const uint32_t ck = s_cnt[k];
     if (!ck) continue;
-    const unsigned long long dst = base + s[k] - ck, src = tile_off[tk];
+    const unsigned long long dst = s_dst[k], src = tile_off[tk];
     for (uint32_t i = lane; i < ck; i += 64) {
       if (dst + i >= cap || src + i >= scratch_cap) continue;
       const u32x4 *from = reinterpret_cast<const u32x4 *>(scratch + src + i);
@@ -1253,7 +1267,7 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
                            const phos_violation *scratch, uint64_t scratch_cap,
                            phos_violation *out, uint64_t cap, hipStream_t s) {
   if (!ntiles) return hipSuccess;
-  hipLaunchKernelGGL(vscatter_kernel, dim3((ntiles + kSeg - 1) / kSeg), dim3(1024), 0, s,
+  hipLaunchKernelGGL(vscatter_kernel, dim3((ntiles + kScatTiles - 1) / kScatTiles), dim3(256), 0, s,
                      tile_count, tile_off, ntiles, seg_prefix, scratch, scratch_cap, out, cap);
   return hipGetLastError();
 }

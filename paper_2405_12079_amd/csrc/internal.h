@@ -116,6 +116,11 @@ struct CopyArgs {
   // themselves here while they copy; the background copy claims no new
   // pages while it is nonzero, so on-demand copies get the link first.
   unsigned long long *demand = nullptr;
+  // Background copy completion: [0] blocks finished, [1] set to 1 by the last
+  // (a checkpoint's background copy; nullptr: not kept).  Copy-on-write
+  // skips its page scan once [1] is set (skip_when_finished).
+  unsigned long long *bg_exit = nullptr;
+  uint32_t skip_when_finished = 0;
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.

@@ -682,7 +682,17 @@ __global__ void __launch_bounds__(kCThreads)
     if (V.meta[3]) map_units = (V.map_words + kCThreads / 4 - 1) / (kCThreads / 4);  // overflowed
   }
   const uint32_t list_units = end > start ? (end - start + kCThreads - 1) / kCThreads : 0;
-  const uint32_t units = range_units + list_units + map_units;
+  uint32_t units = range_units + list_units + map_units;
+  // The background copy has finished, and the copy-on-write calls come from
+  // one stream (the earlier ones are complete): every page is done already,
+  // so there is nothing to scan.  The block still takes part in the victim
+  // cursor update below.
+  __shared__ uint32_t s_skip;  // one decision for the whole block
+  if (t == 0)
+    s_skip = C.skip_when_finished && C.bg_exit &&
+             __hip_atomic_load(&C.bg_exit[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  __syncthreads();
+  if (s_skip) units = 0;
   for (uint32_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
     if (unit < range_units) {
       uint32_t j = 0;
@@ -822,6 +832,13 @@ __global__ void __launch_bounds__(kBgThreads)
     cur ^= 1;
   }
   if (t == 0 && copied) atomicAdd(C.stat, (unsigned long long)copied);
+  if (C.bg_exit && t == 0) {
+    // every block's pages are claimed and published by now (its own, or by
+    // a copy-on-write that claimed them first): the last block out says so
+    __threadfence();
+    if (atomicAdd(&C.bg_exit[0], 1ull) == gridDim.x - 1)
+      __hip_atomic_store(&C.bg_exit[1], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Set the state of every pool page whose image page lies in a flagged image

@@ -883,6 +883,7 @@ static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool t
                                     hipStream_t stream, bool skip_traced = false,
                                     bool over_pcie = false) {
   CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
+  a.bg_exit = to_image ? &s.counters[6] : nullptr;  // [6], [7]: completion (reset at begin)
   if (skip_traced) {  // recopy: pages traced as written are left to the recopy
     a.skip_dirty = c->d_dirty;
     a.skip_victim = c->d_victim;
@@ -1038,6 +1039,10 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   }
   const PageRanges r = page_ranges(c, *h, PHOS_W);
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
+  // once the background copy has finished every page is done, provided the
+  // earlier copy-on-write calls (one stream) have completed
+  a.bg_exit = &k->slot->counters[6];
+  a.skip_when_finished = k->cow_streams_many ? 0u : 1u;
   if (k->stage) {
     a.stage = k->stage;
     a.stage_page = k->d_stage_page;

@@ -138,7 +138,8 @@ typedef struct {
  *
  * Tuning, read from the environment here (defaults in brackets):
  *   PHOS_SPIN_LIMIT      polls before a device wait gives up [1 << 22]
- *   PHOS_BG_GRID         background copy blocks [CUs]; PHOS_COW_GRID [4 x CUs];
+ *   PHOS_BG_GRID         background copy blocks [2 x CUs; at most CUs when
+ *                        reading a host image]; PHOS_COW_GRID [4 x CUs];
  *                        PHOS_BG_GRID_HOST when copying into a host image [8]
  *   PHOS_BG_BATCH        pages a background block claims per batch [64];
  *                        PHOS_BG_BATCH_PCIE when the image is in host memory [4]

@@ -1285,6 +1285,152 @@ def run_staging(args):
     }
 
 
+def run_cow(args):
+    """Section 4.2 soft copy-on-write into a device image, on the training-step
+    layout and launches.  Before each launch the pages of its write intervals,
+    and the pages its violating writes hit inside buffers, are copied into the
+    image unless already copied.  The access streams are validated once the
+    checkpoint is open, before the timed launches.  Two orders: the background
+    copy deferred until the launches are done (every page they write goes
+    through copy-on-write: the worst case for the stall), and the background
+    copy started with the launches, running beside them.
+    Reports each launch's copy-on-write time (HIP events around the call on
+    the application stream), the pages copied, their rate against HBM peak,
+    and the launches' loop time against the same loop with no checkpoint.
+    Parity: the image equals the pool at t1, copied buffer by buffer with
+    torch (a stop-the-world snapshot)."""
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+
+    torch.cuda.set_device(0)
+    w = synth.config2_world()
+    n_launch, n_rec = args.launches, 1_000_000
+    launches = synth.config2_launches(w, n_launch, n_rec)
+    page = w.page_bytes
+    back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    pool = back[base - back.data_ptr(): base - back.data_ptr() + w.pool_bytes]
+    synth.content_device(pool, w.seed)
+    dw = synth.DeviceWorld(w, base)
+    recs = torch.empty(n_launch * n_rec, dtype=torch.int64, device="cuda")
+    for g in range(0, n_launch, 100):
+        synth.records_device(dw, launches[g:g + 100], n_rec, out=recs[g * n_rec:(g + 100) * n_rec])
+    ctx = phos.phos_create(0, base, w.pool_bytes, page)
+    phos.phos_buffers_register(ctx, w.buffers(base))
+    nimg = phos.phos_image_bytes(ctx)
+    img = torch.empty(nimg, dtype=torch.uint8, device="cuda")
+    snap = torch.empty(nimg, dtype=torch.uint8, device="cuda")
+    specs = [phos.phos_spec_register(ctx, L.k, L.arg_values(base)) for L in launches]
+    rec_ptrs = [recs.data_ptr() + j * n_rec * 8 for j in range(n_launch)]
+    lcap = 2_000_000
+    vout = torch.empty(lcap * 32, dtype=torch.uint8, device="cuda")
+    vcnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
+    log(f"[bench] copy-on-write: {w.n_alloc} buffers, {nimg / 2**30:.2f} GiB device image, "
+        f"{n_launch} launches x {n_rec} accesses")
+    # pages of the launches' write intervals inside buffers (the deferred
+    # order copies these and the victim pages of violating writes)
+    inbuf = np.zeros(w.n_pages, bool)
+    for off, nb in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
+        inbuf[off // page:(off + nb) // page] = True
+    wpages = np.zeros(w.n_pages, bool)
+    for sp in specs:
+        for iv in phos.phos_spec_intervals(ctx, sp):
+            lo, hi = max(int(iv["lo"]), base), min(int(iv["hi"]), base + w.pool_bytes)
+            if int(iv["mode"]) & phos.W and hi > lo:
+                wpages[(lo - base) // page:(hi - base + page - 1) // page] = True
+    n_wpages = int((wpages & inbuf).sum())
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_launch)]
+
+    def loop(ck):
+        for j, L in enumerate(launches):
+            if ck is not None:
+                ev[j][0].record(app)
+                phos.phos_ckpt_cow(ck, specs[j], app)
+                ev[j][1].record(app)
+            synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
+
+    def snapshot():
+        o = 0
+        for off, nb in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
+            snap[o:o + nb].copy_(pool[off:off + nb])
+            o += nb
+        torch.cuda.synchronize()
+
+    t = Timer(torch, app)
+    alone = []
+    for _ in range(3):
+        t.start()
+        loop(None)
+        t.stop()
+        app.synchronize()
+        alone.append(t.ms())
+    alone_ms = float(np.median(alone[1:]))
+    log(f"[bench] launches without a checkpoint: {alone_ms:.2f} ms")
+    rows = {}
+    for mode in ("deferred", "concurrent"):
+        runs = []
+        for rep in range(max(1, args.warmup) + max(1, args.steps)):
+            snapshot()
+            # opening resets the victim list, so the streams are validated
+            # after it; the background copy starts once they are
+            ck = phos.phos_ckpt_begin(ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, img, None, cpy)
+            phos.phos_validate_batch(ctx, specs, rec_ptrs, [n_rec] * n_launch,
+                                     phos.V_READS | phos.V_WRITES | phos.V_TRACK, vout, lcap,
+                                     vcnt.data_ptr(), app)
+            if mode == "concurrent":
+                phos.phos_ckpt_start(ck, app)
+            t.start()
+            loop(ck)
+            t.stop()
+            if mode == "deferred":
+                phos.phos_ckpt_start(ck, app)
+            st = phos.phos_ckpt_end(ck, app)
+            torch.cuda.synchronize()
+            assert torch.equal(img, snap), f"image != pool at t1 ({mode})"
+            cow_ms = np.array([a.elapsed_time(b) for a, b in ev])
+            if rep >= max(1, args.warmup):
+                runs.append((t.ms(), cow_ms, int(st.cow_pages), int(st.bg_pages)))
+        loop_ms = float(np.median([r[0] for r in runs]))
+        cow_ms = np.concatenate([r[1] for r in runs])
+        cow_pages = int(np.median([r[2] for r in runs]))
+        total_cow_ms = float(np.median([r[1].sum() for r in runs]))
+        gbps = 2 * cow_pages * page / (total_cow_ms / 1e3) / 1e9 if total_cow_ms else 0.0
+        rows[mode] = {
+            "loop_ms": round(loop_ms, 3), "stall_ms": round(loop_ms - alone_ms, 3),
+            "cow_pages": cow_pages, "background_pages": int(np.median([r[3] for r in runs])),
+            "cow_call_ms": {"p50": round(float(np.percentile(cow_ms, 50)), 4),
+                            "p99": round(float(np.percentile(cow_ms, 99)), 4),
+                            "max": round(float(cow_ms.max()), 4),
+                            "sum": round(total_cow_ms, 3)},
+            "cow_GBps_hbm": round(gbps, 1),
+        }
+        log(f"[bench] {mode}: {rows[mode]}")
+    phos.phos_destroy(ctx)
+    d = rows["deferred"]
+    return {
+        "metric": "copy-on-write copy rate (HBM GB/s over the copy-on-write calls) and the "
+                  "launches' stall",
+        "value": d["cow_GBps_hbm"], "unit": "GB/s", "n_gpus": 1, "steps": max(1, args.steps),
+        "warmup": max(1, args.warmup), "ms_per_step": d["loop_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded layout, access streams and contents)",
+        "config": {"workload": "copy-on-write: training-step layout, 1000 launches x 1e6 accesses, "
+                               "16 GiB device image, background deferred / beside"},
+        "roofline": {"bound": "hbm", "kernel": "cow_kernel (background deferred)",
+                     "achieved": d["cow_GBps_hbm"], "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(d["cow_GBps_hbm"] / 8000.0, 4), "traffic": None,
+                     "algorithmic_bytes": 2 * d["cow_pages"] * page},
+        "launches_without_checkpoint_ms": round(alone_ms, 3),
+        "write_interval_pages": n_wpages,
+        "by_order": rows,
+        "parity": "the image equals the pool at t1 (whole image, every run)",
+    }
+
+
 def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1346,6 +1492,8 @@ def main():
         res = run_drain(args)
     elif args.config == 8:
         res = run_staging(args)
+    elif args.config == 9:
+        res = run_cow(args)
     else:
         sys.exit(f"unknown config {args.config}")
     print(json.dumps(res), flush=True)

@@ -273,7 +273,14 @@ phos_status phos_ckpt_start(phos_ckpt *ck, hipStream_t after);
  * copy every page it may write that the checkpoint has not copied yet: the
  * pages of its write intervals and the victim pages marked by validation.
  * A page already being copied is waited for.  Asynchronous on app_stream;
- * the launch must be enqueued after this call.  PROTOCOL COW only. */
+ * the launch must be enqueued after this call.  PROTOCOL COW only.
+ * The validation that marks a launch's victim pages must be complete in
+ * app_stream order before this call (enqueued on app_stream, or waited for
+ * with an event).  While every call comes from one stream and every tracking
+ * validation went to that same stream, the host skips a call whose write
+ * pages earlier calls already asked for when no validation has run since
+ * (those pages are done before the launch, in stream order); with tracking
+ * validations on other streams each call scans the whole victim map. */
 phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream);
 
 /* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every

@@ -33,7 +33,8 @@ constexpr uint32_t kFuseTiles = 4096;            // calls up to this many tiles 
 constexpr uint32_t kCThreads = 256;
 constexpr uint32_t kBgCopyThreads = 512;            // copying waves of a background block
 constexpr uint32_t kBgThreads = kBgCopyThreads + 64; // plus one claiming wave
-constexpr uint32_t kUnitPages = 64;  // pages per copy-on-write work unit
+constexpr uint32_t kUnitPages = 4;  // pages per copy-on-write work unit
+constexpr uint32_t kVictimUnit = 16;  // victim-list entries per copy-on-write work unit
 
 // Interval in the form the kernel tests: an access at a is inside iff
 // (a - lo) <= span (unsigned), span = hi - lo - 8.  Empty-for-8-byte
@@ -139,6 +140,9 @@ struct VictimList {
   uint32_t cap;
   const uint8_t *map;
   uint32_t map_words;
+  // 1: scan the whole map and leave the list and its cursor alone (the
+  // caller cannot order the list's appends before this launch)
+  uint32_t scan_map;
 };
 
 // Batched-copy work queue: segments, exclusive byte prefix, a chunk cursor.
@@ -186,8 +190,10 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
                            uint32_t ntiles, const unsigned long long *seg_prefix,
                            const phos_violation *scratch, uint64_t scratch_cap,
                            phos_violation *out, uint64_t cap, hipStream_t s);
+// victim_blocks: blocks added for the victim list (its length is only known
+// on the device)
 hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
-                      uint32_t max_grid, hipStream_t s);
+                      uint32_t max_grid, uint32_t victim_blocks, hipStream_t s);
 hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_t n_pages,
                               uint32_t chunk_pages, const uint8_t *flag, uint32_t value,
                               unsigned long long *count, hipStream_t s);

@@ -664,8 +664,9 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
 }
 
 // Section 4.2: work units of kUnitPages pages of the write intervals, then
-// units of 2048 victim pages (pages hit by failing writes inside buffers);
+// units of kVictimUnit victim pages (pages hit by failing writes inside buffers);
 // a persistent grid strides over them and skips units already copied.
+static_assert(kUnitPages <= kCThreads && kVictimUnit <= kCThreads, "one candidate per thread");
 __device__ __forceinline__ bool unit_needed(const CopyArgs &C, uint32_t cand) {
   return __syncthreads_or(cand != kNone && C.img_page[cand] != kNone && C.state[cand] != kDone);
 }
@@ -676,12 +677,15 @@ __global__ void __launch_bounds__(kCThreads)
   const uint32_t range_units = R.units_prefix[R.n];
   // victim pages marked since the previous call: entries [start, end)
   uint32_t start = 0, end = 0, map_units = 0;
-  if (V.meta) {
+  const uint32_t all_map_units = (V.map_words + kCThreads / 4 - 1) / (kCThreads / 4);
+  if (V.meta && V.scan_map) {
+    map_units = all_map_units;
+  } else if (V.meta) {
     start = V.meta[1];
     end = V.meta[0] < V.cap ? V.meta[0] : V.cap;
-    if (V.meta[3]) map_units = (V.map_words + kCThreads / 4 - 1) / (kCThreads / 4);  // overflowed
+    if (V.meta[3]) map_units = all_map_units;  // the list overflowed
   }
-  const uint32_t list_units = end > start ? (end - start + kCThreads - 1) / kCThreads : 0;
+  const uint32_t list_units = end > start ? (end - start + kVictimUnit - 1) / kVictimUnit : 0;
   uint32_t units = range_units + list_units + map_units;
   // The background copy has finished, and the copy-on-write calls come from
   // one stream (the earlier ones are complete): every page is done already,
@@ -705,8 +709,9 @@ __global__ void __launch_bounds__(kCThreads)
       continue;
     }
     if (unit < range_units + list_units) {
-      const uint32_t e = start + (unit - range_units) * kCThreads + t;
-      const uint32_t cand = e < end ? V.list[e] : kNone;
+      const uint32_t e = start + (unit - range_units) * kVictimUnit + t;
+      uint32_t cand = (t < kVictimUnit && e < end) ? V.list[e] : kNone;
+      if (cand >= C.n_pages) cand = kNone;
       if (!unit_needed(C, cand)) continue;
       if (wait) claim_copy<true>(cand, C, nullptr);
       else claim_copy<false>(cand, C, nullptr);
@@ -730,7 +735,7 @@ __global__ void __launch_bounds__(kCThreads)
     }
   }
   // the last block out moves the list cursor past the entries handled here
-  if (V.meta) {
+  if (V.meta && !V.scan_map) {
     __syncthreads();
     if (t == 0 && atomicAdd(&V.meta[2], 1u) == gridDim.x - 1) {
       V.meta[1] = end;
@@ -1290,10 +1295,10 @@ hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long 
 }
 
 hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &v, bool wait,
-                      uint32_t max_grid, hipStream_t s) {
-  // the victim entries are only known on the device: a few extra blocks
-  // stride over them
-  uint32_t units = r.units_prefix[r.n] + (v.meta ? 8 : 0);
+                      uint32_t max_grid, uint32_t victim_blocks, hipStream_t s) {
+  // the victim entries are only known on the device: extra blocks stride
+  // over them (the whole grid when the caller knows some may be new)
+  uint32_t units = r.units_prefix[r.n] + (v.meta ? victim_blocks : 0);
   if (!units) return hipSuccess;
   hipLaunchKernelGGL(cow_kernel, dim3(units < max_grid ? units : max_grid), dim3(kCThreads), 0, s,
                      c, r, v, wait ? 1u : 0u);

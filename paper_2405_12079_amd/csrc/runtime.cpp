@@ -141,6 +141,13 @@ struct phos_ctx {
   uint64_t drain_chunk = 16u << 20;  // image drain to host: chunk bytes (0: one copy)
   uint32_t drain_window = 2;        // ... and chunks in flight
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
+  // Victim pages: a tracking validation (or twin) may have appended to the
+  // list since the last copy-on-write call, which then strides over it with
+  // its whole grid.  The host knows this in device order only while every
+  // such call went to one stream (victim_stream).
+  bool victims_pending = false;
+  bool victim_stream_set = false, victim_streams_many = false;
+  hipStream_t victim_stream = nullptr;
   uint32_t tile_max = 8 * kVQuantum;    // largest validation tile (records)
   uint32_t tile_max_track = 16 * kVQuantum;  // ... with dirty tracking (fewer map flushes)
   uint32_t bg_batch = 64;               // background groups claimed at once per block
@@ -160,6 +167,9 @@ struct phos_ckpt {
   bool bg_known_done = false;
   hipStream_t cow_stream = nullptr;  // the one stream CoW calls came from
   bool cow_streams_many = false;
+  // pages of the write intervals earlier CoW calls on cow_stream asked for
+  // (one bit per pool page; empty until the first call)
+  std::vector<uint64_t> requested;
   bool host = false;  // the image is in host memory (copies cross PCIe)
   // copy-on-write staging area (device memory, the caller's) for a host image
   uint8_t *stage = nullptr;
@@ -592,6 +602,16 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   return a;
 }
 
+static void note_victims(phos_ctx *c, hipStream_t s) {
+  c->victims_pending = true;
+  if (!c->victim_stream_set) {
+    c->victim_stream_set = true;
+    c->victim_stream = s;
+  } else if (c->victim_stream != s) {
+    c->victim_streams_many = true;
+  }
+}
+
 // Validations share the context's workspace, so they are serialized: a call
 // on another stream than the previous one waits for it.  Under stream
 // capture no event is used (captured validations must share one stream).
@@ -603,6 +623,7 @@ static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *si
   const bool capturing = cs != hipStreamCaptureStatusNone;
   if (!capturing && c->v_evt_used && s != c->v_stream) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
   HIP_TRY(launch_validate(a, single, (a.flags & PHOS_V_TRACK) != 0, s));
+  if (a.flags & PHOS_V_TRACK) note_victims(c, s);
   if (a.ntiles <= c->finish_tiles) {
     HIP_TRY(launch_vfinish(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_scratch, c->scratch_cap,
                            out, cap, n_out, c->d_cursor, c->d_seg_sum, s));
@@ -664,6 +685,7 @@ extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const ui
   if (flags) HIP_TRY(launch_fill_u64(a.count, 1, 0, stream));
   const uint64_t blocks = (n + 4 * 256 - 1) / (4 * 256);  // four elements per thread
   HIP_TRY(launch_twin(a, ds, blocks, c->n_cu, stream));
+  if (flags & PHOS_V_TRACK) note_victims(c, stream);
   return PHOS_OK;
 }
 
@@ -914,6 +936,27 @@ static PageRanges page_ranges(phos_ctx *c, const HostSpec &h, uint32_t modes) {
   return r;
 }
 
+// Bit p of `bits` for every page p of the ranges: all set? / set them.
+static bool ranges_all_set(const std::vector<uint64_t> &bits, const PageRanges &r) {
+  for (uint32_t i = 0; i < r.n; ++i)
+    for (uint64_t p = r.p0[i], e = (uint64_t)r.p0[i] + r.np[i]; p < e;) {
+      const uint64_t w = p >> 6, lo = p & 63, hi = std::min<uint64_t>(64, lo + (e - p));
+      const uint64_t m = (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+      if ((bits[w] & m) != m) return false;
+      p += hi - lo;
+    }
+  return true;
+}
+
+static void ranges_set(std::vector<uint64_t> &bits, const PageRanges &r) {
+  for (uint32_t i = 0; i < r.n; ++i)
+    for (uint64_t p = r.p0[i], e = (uint64_t)r.p0[i] + r.np[i]; p < e;) {
+      const uint64_t w = p >> 6, lo = p & 63, hi = std::min<uint64_t>(64, lo + (e - p));
+      bits[w] |= (hi == 64 ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+      p += hi - lo;
+    }
+}
+
 extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t flags, void *image,
                                        void *host_image, hipStream_t copy, phos_ckpt **out) {
   if (!c || !image || !out) return fail(PHOS_E_INVAL, "phos_ckpt_begin: NULL argument");
@@ -937,6 +980,8 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, c->aux));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, c->aux));
     HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, c->aux));
+    c->victims_pending = false;
+    c->victim_stream_set = c->victim_streams_many = false;
   }
   HIP_TRY(hipStreamSynchronize(c->aux));
   phos_ckpt *k = new phos_ckpt;
@@ -1042,6 +1087,20 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
     if (k->bg_known_done) return PHOS_OK;
   }
   const PageRanges r = page_ranges(c, *h, PHOS_W);
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  // Victim pages may be new since the last call unless the host knows
+  // otherwise in device order (every tracking call on this stream).
+  const bool victims_unsure =
+      c->victim_streams_many || (c->victim_stream_set && c->victim_stream != app);
+  const bool victims_new = c->victims_pending || victims_unsure || capturing;
+  // A page an earlier call on this same stream asked for is done before
+  // this launch runs (stream order): with all of this launch's write pages
+  // asked for and no victim page possibly new, there is nothing to do.
+  const bool exact = !capturing && !k->cow_streams_many && !victims_unsure;
+  if (exact) {
+    if (k->requested.empty()) k->requested.assign((c->n_pages + 63) / 64, 0);
+    if (!victims_new && ranges_all_set(k->requested, r)) return PHOS_OK;
+  }
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
   // once the background copy has finished every page is done, provided the
   // earlier copy-on-write calls (one stream) have completed
@@ -1053,8 +1112,15 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
     a.stage_head = k->d_stage_head;
     a.stage_cap = k->stage_cap;
   }
-  const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords};
-  HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, app));
+  // with tracking calls on other streams the list may be appended to while
+  // this launch reads it: the victim map (marks only ever added, complete
+  // for every call this stream has waited for) is scanned instead
+  const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords,
+                     victims_unsure ? 1u : 0u};
+  // (a captured call may be replayed after any validation)
+  HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, victims_new ? c->cow_grid : 8u, app));
+  if (!capturing) c->victims_pending = false;
+  if (exact) ranges_set(k->requested, r);
   return PHOS_OK;
 }
 
@@ -1543,8 +1609,8 @@ extern "C" phos_status phos_restore_on_demand(phos_rst *r, phos_spec spec, const
   Slot &s = *r->slot;
   if (r->flags & PHOS_RST_PREFETCH_SPEC) {
     const PageRanges pr = page_ranges(c, *h, PHOS_R | PHOS_W);
-    const VictimList none{nullptr, nullptr, 0, nullptr, 0};
-    HIP_TRY(launch_cow(rst_args(r, &s.counters[2]), pr, none, true, c->cow_grid, app));
+    const VictimList none{nullptr, nullptr, 0, nullptr, 0, 0};
+    HIP_TRY(launch_cow(rst_args(r, &s.counters[2]), pr, none, true, c->cow_grid, 0, app));
   }
   CopyArgs a = rst_args(r, &s.counters[2], c->rst_deep_demand);
   HIP_TRY(launch_demand(a, d_records, n, c->pool_base, (unsigned long long *)d_faulted, c->n_cu, app));

@@ -115,11 +115,25 @@ SIGNATURES = [
 _lib = None
 
 
+def _torch_first():
+    """Load torch's HIP runtime before libphos.so when torch is installed.
+    torch ships its own HSA runtime (soname libhsa-runtime64.so.1, asked for
+    as libhsa-runtime64.so); loaded first, it satisfies libphos.so's need for
+    libhsa-runtime64.so.1 and the process has one HSA runtime.  In the other
+    order each library gets its own, and the one initialized second finds no
+    device."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        _torch_first()
         L = ctypes.CDLL(LIB_PATH)
         for name, args in SIGNATURES:
             fn = getattr(L, name)

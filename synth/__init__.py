@@ -485,6 +485,9 @@ def dev_lib():
         path = os.path.join(HERE, "libsynth_dev.so")
         if not os.path.exists(path):
             raise RuntimeError(f"{path} missing: run __graft_entry__.build()")
+        # torch's HSA runtime first, so that the process has only one (it
+        # satisfies this library's libhsa-runtime64.so.1)
+        import torch  # noqa: F401
         lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.synth_dev_records.argtypes = [ctypes.POINTER(SynthWorld), P, ctypes.c_uint32,

@@ -116,6 +116,71 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(env.pool_host(), host)
 
 
+@pytest.mark.parametrize("vstream", ["same", "other"])
+def test_soft_cow_chunked_validation(env, vstream):
+    """The training step's order on the plain-tiny workload: each chunk of 20
+    launches is validated in one batched call ahead of its launches, on the
+    application's stream ("same": a copy-on-write call whose write pages
+    earlier calls already asked for, with no new victim pages, is skipped on
+    the host) or on a stream of its own that the application waits for chunk
+    by chunk, every chunk issued up front ("other": the host cannot order the
+    victim pages, so every call looks at them).  With the background copy
+    deferred, copy-on-write copies exactly the union of the oracle's copy
+    sets, and the image is the snapshot at t1."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(0,), cow_window=(0, T2 - T1), keep_violations=False)
+    union = np.zeros(w.n_pages, np.uint8)
+    for cs in res.cow_sets:
+        union[cs.astype(np.int64)] = 1
+    T.cuda.synchronize()
+    groups = {g: env.records(launches[g * 20:(g + 1) * 20], N) for g in range(T1 // 20, T2 // 20)}
+    T.cuda.synchronize()
+    specs = {j: env.spec(launches[j]) for j in range(T1, T2)}
+    cap = 100_000
+    bufs = {g: env.violations_buffers(cap) for g in groups}
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, image, None, env.copy)
+    vs = T.cuda.Stream() if vstream == "other" else env.app
+
+    def validate(g):
+        js = range(g * 20, (g + 1) * 20)
+        out, cnt = bufs[g]
+        phos.phos_validate_batch(env.ctx, [specs[j] for j in js],
+                                 [groups[g].data_ptr() + (j % 20) * N * 8 for j in js], [N] * 20,
+                                 V, out, cap, cnt, vs)
+
+    done = {}
+    if vstream == "other":
+        vs.wait_stream(env.app)
+        for g in groups:
+            validate(g)
+            done[g] = T.cuda.Event()
+            done[g].record(vs)
+    for j in range(T1, T2):
+        g = j // 20
+        if j % 20 == 0:
+            if vstream == "other":
+                env.app.wait_event(done[g])
+            else:
+                validate(g)
+        phos.phos_ckpt_cow(ck, specs[j], env.app)
+        env.mutate(launches[j], groups[g].data_ptr() + (j % 20) * N * 8, N)
+    stats = phos.phos_ckpt_end(ck, env.app)
+    T.cuda.synchronize()
+    for j in range(T1, T2):
+        phos.phos_spec_release(env.ctx, specs[j])
+    assert np.array_equal(image.cpu().numpy(), res.snapshots[0]), "CoW image != snapshot at t1"
+    assert stats.cow_pages == int(union.sum())
+    assert stats.bg_pages + stats.cow_pages == env.image_bytes // w.page_bytes
+    assert np.array_equal(env.pool_host(), host)
+
+
 @pytest.mark.parametrize("defer,budget", [(True, 0), (True, 10), (True, None), (False, 64)])
 def test_cow_staging_host_image(env, defer, budget):
     """Copy-on-write into a pinned host image through a device staging area of

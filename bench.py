@@ -390,6 +390,8 @@ def run_training_step(args):
     # checkpoint image bytes finished per step (two images), and the bytes
     # actually copied into them
     img_bytes = 2 * nimg
+    rec_ms = float(np.mean([r["rec"] for r in rows]))
+    rec_bytes = float(np.mean([r["recopy_pages"] for r in rows])) * page
     copied_bytes = np.mean([(r["bg_a_pages"] + r["cow_pages"] + r["bg_b_pages"] + r["recopy_pages"]
                              + r["precopy_pages"]) * page for r in rows])
     snap_gbps = img_bytes / (ms_step / 1e3) / 1e9
@@ -429,7 +431,7 @@ def run_training_step(args):
         "validated_addr_per_s": round(n_addr / (alone["track"] / 1e3), 1),
         "validation_ms_alone": {k: round(v, 4) for k, v in alone.items()},
         "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
-        "recopy_ms": round(float(np.mean([r["rec"] for r in rows])), 3),
+        "recopy_ms": round(rec_ms, 3),
         "recopy_pages": int(np.mean([r["recopy_pages"] for r in rows])),
         "precopy": {"rounds": (nchunk - 1) if args.precopy else 0,
                     "pages": int(np.mean([r["precopy_pages"] for r in rows]))},
@@ -459,7 +461,15 @@ def run_training_step(args):
                               "achieved": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6, 1),
                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                               "frac": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6
-                                            / HBM_PEAK_GBPS, 4)},
+                                            / HBM_PEAK_GBPS, 4),
+                              "traffic": measured_traffic("validate_kernel", "training_step")},
+        # the recopy at the re-quiesce: page list + gather, from the
+        # application's last launch to the recopy's end
+        "roofline_recopy": {"bound": "hbm", "kernel": "gather_pages_kernel (+ page list), recopy",
+                            "achieved": round(2 * rec_bytes / rec_ms / 1e6, 1),
+                            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "frac": round(2 * rec_bytes / rec_ms / 1e6 / HBM_PEAK_GBPS, 4),
+                            "traffic": measured_traffic("gather_pages_kernel", "training_step")},
     }
     if graph is not None:
         graph.close()

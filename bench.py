@@ -253,6 +253,7 @@ def run_training_step(args):
         phos.phos_ckpt_start(cb, None)
         t_bg_b.stop()
 
+    final_at = {int(x) for x in args.final_at.split(",") if x.strip()}
     vstream = torch.cuda.Stream() if args.pipelined_validation else None
     vdone = [torch.cuda.Event() for _ in range(nchunk)] if vstream is not None else []
 
@@ -285,6 +286,8 @@ def run_training_step(args):
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
                 if j == 0 and args.copy_after_validation:
                     start_copies(ca, cb)
+            if j in final_at:  # dirty pages no remaining launch may write
+                phos.phos_ckpt_precopy_final(cb, specs[j:], app)
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 
@@ -433,7 +436,8 @@ def run_training_step(args):
         "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
         "recopy_ms": round(rec_ms, 3),
         "recopy_pages": int(np.mean([r["recopy_pages"] for r in rows])),
-        "precopy": {"rounds": (nchunk - 1) if args.precopy else 0,
+        "precopy": {"rounds": ((nchunk - 1) if args.precopy else 0) + len(final_at),
+                    "final_at": sorted(final_at),
                     "pages": int(np.mean([r["precopy_pages"] for r in rows]))},
         "app_loop_graph": bool(args.app_graph),
         "launches_per_validation_call": chunk,
@@ -1444,8 +1448,8 @@ def run_cow(args):
 def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--launches", type=int, default=1000)
     ap.add_argument("--val-chunk", type=int, default=1000,
@@ -1467,6 +1471,9 @@ def parse_args(argv=None):
     ap.add_argument("--precopy", action="store_true",
                     help="config 2: a pre-copy round of the recopy image before each validation "
                          "chunk after the first (iterative recopy; use with --val-chunk)")
+    ap.add_argument("--final-at", dest="final_at", default="500,750,900,975",
+                    help="config 2: launch positions before which a pre-copy round copies the "
+                         "dirty pages no remaining launch may write ('' for none)")
     ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",
                     help="config 8: staging budgets in MiB")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
@@ -1482,6 +1489,10 @@ def main():
     if args.pipelined_validation and (args.app_graph or args.precopy or args.copy_after_validation):
         sys.exit("--pipelined-validation runs alone (no --app-graph, --precopy, "
                  "--copy-after-validation)")
+    if args.final_at and (args.app_graph or args.pipelined_validation):
+        # a round builds its page mask on the host at the call
+        log("[bench] final-page pre-copy rounds are off with --app-graph / --pipelined-validation")
+        args.final_at = ""
     if args.copy_after_validation and args.app_graph:
         sys.exit("--copy-after-validation starts the copies on another stream: not with --app-graph")
     if args.gpus != 1:

@@ -303,6 +303,23 @@ phos_status phos_ckpt_recopy(phos_ckpt *ck, hipStream_t app_stream);
  * recopied. */
 phos_status phos_ckpt_precopy(phos_ckpt *ck, hipStream_t app_stream);
 
+/* Sections 4.3 and 7, iterative recopy with the window's remaining launches
+ * known (their access streams validated ahead, as the speculation allows):
+ * a pre-copy round that copies only the dirty pages none of the `upcoming`
+ * launches may write, i.e. pages outside every write interval of their
+ * specs.  Such a page has had its last writer in the window issued on
+ * app_stream already, so it is unmarked and copied once, in app_stream
+ * order; a later write to it can only be a violation, which marks the victim
+ * map, and the recopy at the re-quiesce copies victim pages.  Unlike
+ * phos_ckpt_precopy the marks of launches validated ahead of their turn do
+ * no harm: their pages are in the upcoming write intervals.  upcoming: the
+ * specs of every launch of the window still to be issued on app_stream (any
+ * order; n_upcoming 0: none).  E_INVAL for an unknown spec, E_STATE for a
+ * copy-on-write checkpoint, after the recopy, or under stream capture (the
+ * mask is built on the host at the call).  Asynchronous on app_stream. */
+phos_status phos_ckpt_precopy_final(phos_ckpt *ck, const phos_spec *upcoming, uint32_t n_upcoming,
+                                    hipStream_t app_stream);
+
 /* Finish: wait for every copy (and app_stream), drain image to host_image if
  * given, free the handle.  A recopy checkpoint not yet recopied is recopied
  * first (ending is a quiesce point).  The drain (Section 5) is issued in

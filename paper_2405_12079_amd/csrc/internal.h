@@ -199,8 +199,10 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
                              hipStream_t s);
+// exclude: optional word mask (32 pages a word) of pages left out of the list
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
-                           uint32_t *list, unsigned int *count, hipStream_t s);
+                           uint32_t *list, unsigned int *count, hipStream_t s,
+                           const uint32_t *exclude = nullptr);
 hipError_t launch_gather_pages(const CopyArgs &c, const uint32_t *list, const unsigned int *count,
                                uint32_t grid, hipStream_t s);
 hipError_t launch_unstage(const CopyArgs &c, uint32_t grid, hipStream_t s);

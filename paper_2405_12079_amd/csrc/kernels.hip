@@ -930,13 +930,14 @@ __global__ void __launch_bounds__(kBgCopyThreads) unstage_kernel(CopyArgs C) {
 
 // Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
 __global__ void __launch_bounds__(256)
-    pagelist_kernel(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
-                    uint32_t *list, unsigned int *count) {
+    pagelist_kernel(const uint8_t *a, const uint8_t *b, const uint32_t *exclude, uint32_t nwords,
+                    uint32_t n_pages, uint32_t *list, unsigned int *count) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t lane = threadIdx.x & 63u;
   uint32_t bits = 0;
   if (w < nwords) {
     bits = bytes_to_mask(a + 32ull * w) | (b ? bytes_to_mask(b + 32ull * w) : 0u);
+    if (exclude) bits &= ~exclude[w];
     const uint64_t last = (uint64_t)w * 32 + 32;
     if (last > n_pages) bits &= (n_pages - w * 32 >= 32) ? ~0u : ((1u << (n_pages - w * 32)) - 1u);
   }
@@ -1328,10 +1329,11 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
 }
 
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
-                           uint32_t *list, unsigned int *count, hipStream_t s) {
+                           uint32_t *list, unsigned int *count, hipStream_t s,
+                           const uint32_t *exclude) {
   if (!nwords) return hipSuccess;
-  hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, nwords,
-                     n_pages, list, count);
+  hipLaunchKernelGGL(pagelist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, a, b, exclude,
+                     nwords, n_pages, list, count);
   return hipGetLastError();
 }
 

@@ -176,6 +176,17 @@ struct phos_ckpt {
   uint32_t *d_stage_page = nullptr;
   unsigned long long *d_stage_head = nullptr;
   uint32_t stage_cap = 0;
+  // final-page pre-copy rounds: the pages the remaining launches may write,
+  // one bit per pool page (pinned host copy, device copy, upload event)
+  uint32_t *h_mask = nullptr, *d_mask = nullptr;
+  hipEvent_t mask_evt = nullptr;
+  bool mask_used = false;
+  ~phos_ckpt() {
+    if (mask_used) (void)hipEventSynchronize(mask_evt);
+    if (mask_evt) (void)hipEventDestroy(mask_evt);
+    if (h_mask) (void)hipHostFree(h_mask);
+    if (d_mask) (void)hipFree(d_mask);
+  }
 };
 
 constexpr uint32_t kWantCap = 16384;      // asked-for pages the host can see per restore
@@ -1164,6 +1175,55 @@ extern "C" phos_status phos_ckpt_precopy(phos_ckpt *k, hipStream_t app) {
   // copies, before those validated later
   HIP_TRY(launch_fill_u32(s.list_count, 1, 0, app));
   HIP_TRY(launch_pagelist(c->d_dirty, nullptr, c->nwords, c->n_pages, s.list, s.list_count, app));
+  CopyArgs a = copy_args(c, s, k->image, true, &s.counters[5]);
+  HIP_TRY(launch_precopy(a, s.list, s.list_count, c->d_dirty, c->bg_grid, app));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_precopy_final(phos_ckpt *k, const phos_spec *upcoming,
+                                               uint32_t n_upcoming, hipStream_t app) {
+  if (!k || (n_upcoming && !upcoming)) return fail(PHOS_E_INVAL, "phos_ckpt_precopy_final: bad argument");
+  if (k->protocol != PHOS_RECOPY) return fail(PHOS_E_STATE, "pre-copy needs a recopy checkpoint");
+  if (k->recopied) return fail(PHOS_E_STATE, "recopy already done");
+  phos_ctx *c = k->ctx;
+  std::vector<const HostSpec *> hs(n_upcoming);
+  for (uint32_t i = 0; i < n_upcoming; ++i) {
+    hs[i] = get_spec(c, upcoming[i]);
+    if (!hs[i]) return fail(PHOS_E_INVAL, "upcoming launch %u: unknown spec %u", i, upcoming[i]);
+  }
+  DeviceGuard g(c->device);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(app, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(PHOS_E_STATE, "phos_ckpt_precopy_final cannot be captured (its mask is built now)");
+  const size_t bytes = 4ull * c->nwords;
+  if (!k->h_mask && hipHostMalloc(&k->h_mask, bytes, hipHostMallocDefault) != hipSuccess) {
+    k->h_mask = nullptr;
+    return fail(PHOS_E_NOMEM, "hipHostMalloc(%zu)", bytes);
+  }
+  if (!k->d_mask) TRY(dalloc(&k->d_mask, c->nwords));
+  if (!k->mask_evt) HIP_TRY(hipEventCreateWithFlags(&k->mask_evt, hipEventDisableTiming));
+  if (k->mask_used) HIP_TRY(hipEventSynchronize(k->mask_evt));  // the last upload has read it
+  // every page any remaining launch may write (its write intervals)
+  memset(k->h_mask, 0, bytes);
+  for (const HostSpec *h : hs) {
+    const PageRanges r = page_ranges(c, *h, PHOS_W);
+    for (uint32_t i = 0; i < r.n; ++i)
+      for (uint64_t p = r.p0[i], e = (uint64_t)r.p0[i] + r.np[i]; p < e;) {
+        const uint32_t lo = (uint32_t)(p & 31), hi = (uint32_t)std::min<uint64_t>(32, lo + (e - p));
+        k->h_mask[p >> 5] |= (hi == 32 ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        p += hi - lo;
+      }
+  }
+  Slot &s = *k->slot;
+  HIP_TRY(hipMemcpyAsync(k->d_mask, k->h_mask, bytes, hipMemcpyHostToDevice, app));
+  HIP_TRY(hipEventRecord(k->mask_evt, app));
+  k->mask_used = true;
+  // in app_stream order: after the launches issued so far; the dirty pages
+  // outside the mask have had their last writer issued already
+  HIP_TRY(launch_fill_u32(s.list_count, 1, 0, app));
+  HIP_TRY(launch_pagelist(c->d_dirty, nullptr, c->nwords, c->n_pages, s.list, s.list_count, app,
+                          k->d_mask));
   CopyArgs a = copy_args(c, s, k->image, true, &s.counters[5]);
   HIP_TRY(launch_precopy(a, s.list, s.list_count, c->d_dirty, c->bg_grid, app));
   return PHOS_OK;

@@ -88,6 +88,7 @@ SIGNATURES = [
     ("phos_ckpt_cow", [P, U32, P]),
     ("phos_ckpt_recopy", [P, P]),
     ("phos_ckpt_precopy", [P, P]),
+    ("phos_ckpt_precopy_final", [P, P, U32, P]),
     ("phos_ckpt_staging", [P, P, U64]),
     ("phos_ckpt_start", [P, P]),
     ("phos_ckpt_end", [P, P, P]),
@@ -287,6 +288,12 @@ def phos_ckpt_staging(ck, staging, nbytes) -> None:
 
 def phos_ckpt_precopy(ck, app_stream) -> None:
     _call("phos_ckpt_precopy", ck, _stream(app_stream))
+
+
+def phos_ckpt_precopy_final(ck, upcoming, app_stream) -> None:
+    k = len(upcoming)
+    sp = (U32 * max(1, k))(*upcoming)
+    _call("phos_ckpt_precopy_final", ck, sp, k, _stream(app_stream))
 
 
 def phos_ckpt_end(ck, app_stream) -> phos_ckpt_stats:

@@ -317,6 +317,75 @@ def test_soft_recopy_config1(env, mode):
     assert np.array_equal(image.cpu().numpy(), want)
 
 
+def _write_pages(env, launches):
+    """Pool pages overlapping any write interval of the launches' specs, as
+    the oracle builds them (Section 4.1)."""
+    w = env.world
+    m = np.zeros(w.n_pages, np.uint8)
+    for L in launches:
+        for iv in oracle.spec_build(env.table, L.arg_values(env.base)):
+            if not int(iv["mode"]) & 2:
+                continue
+            lo = max(int(iv["lo"]), env.base) - env.base
+            hi = min(int(iv["hi"]), env.base + w.pool_bytes) - env.base
+            if hi > lo:
+                m[lo // w.page_bytes:(hi - 1) // w.page_bytes + 1] = 1
+    return m
+
+
+def test_precopy_final_rounds(env):
+    """Iterative recopy with the window's remaining launches known: every
+    launch of the window is validated up front in one batched call (as the
+    training step does), and two rounds copy the dirty pages none of the
+    launches still to come may write.  The final dirty map is the oracle's
+    dirty map restricted to the last round's upcoming write pages, the
+    rounds copy the rest of it, and the image is the snapshot at t2."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(T2 - T1,), window=(0, T2 - T1), keep_violations=False)
+    T.cuda.synchronize()
+    groups = {g: env.records(launches[g * 20:(g + 1) * 20], N) for g in range(T1 // 20, T2 // 20)}
+    T.cuda.synchronize()
+    specs = {j: env.spec(launches[j]) for j in range(T1, T2)}
+    ptr = {j: groups[j // 20].data_ptr() + (j % 20) * N * 8 for j in range(T1, T2)}
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, None, env.copy)
+    cap = 200_000
+    out, cnt = env.violations_buffers(cap)
+    phos.phos_validate_batch(env.ctx, [specs[j] for j in range(T1, T2)],
+                             [ptr[j] for j in range(T1, T2)], [N] * (T2 - T1), V, out, cap, cnt,
+                             env.app)
+    rounds = [T1 + (T2 - T1) // 2, T2 - 6]
+    for j in range(T1, T2):
+        if j in rounds:
+            phos.phos_ckpt_precopy_final(ck, [specs[i] for i in range(j, T2)], env.app)
+        env.mutate(launches[j], ptr[j], N)
+    phos.phos_ckpt_recopy(ck, env.app)
+    with pytest.raises(phos.PhosError) as e:  # no round after the recopy
+        phos.phos_ckpt_precopy_final(ck, [], env.app)
+    assert e.value.status == phos.E_STATE
+    d = phos.phos_track_read(env.ctx, 0, w.n_pages)
+    v = phos.phos_track_read(env.ctx, 1, w.n_pages)
+    stats = phos.phos_ckpt_end(ck, env.app)
+    T.cuda.synchronize()
+    for j in range(T1, T2):
+        phos.phos_spec_release(env.ctx, specs[j])
+    upcoming = _write_pages(env, launches[rounds[-1]:T2])
+    dirty_left = res.dirty & upcoming
+    assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left, w.n_pages))
+    assert np.array_equal(v, oracle.pages_to_bitmap(res.victim, w.n_pages))
+    inbuf = _buffer_pages(w)
+    assert stats.precopy_pages == int((res.dirty & (1 - upcoming) & inbuf).sum())
+    assert stats.precopy_pages > 0
+    assert stats.recopy_pages == int(((dirty_left | res.victim) & inbuf).sum())
+    assert np.array_equal(image.cpu().numpy(), res.snapshots[T2 - T1]), "image != snapshot at t2"
+
+
 def test_both_protocols_open_together(env):
     """A CoW checkpoint (t1 image) and a recopy checkpoint (t2 image) over one window."""
     phos, w, T = env.phos, env.world, env.T

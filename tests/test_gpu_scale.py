@@ -2,7 +2,8 @@
 step (16 GiB pool of 2,000 buffers, 64 KiB pages, 1,000 launches x 10^6
 accesses validated with tracking in one batched call, copy-on-write before
 every launch, a copy-on-write and a recopy checkpoint open together on one
-copy stream, recopy at the end).
+copy stream, pre-copy rounds of the pages no remaining launch may write
+before launches 500, 750, 900 and 975, recopy at the end).
 
 Compared against what the oracle computes at this size: the dirty and victim
 page maps of all 1,000 launches (Section 4.3), the violation lists of sampled
@@ -20,6 +21,8 @@ import synth
 pytestmark = pytest.mark.gpu
 N_LAUNCH, N_REC = 1000, 1_000_000
 SAMPLED = (0, 1, 357, 998, 999)
+# the final-page pre-copy rounds of the timed step (bench.py's default)
+FINAL_AT = (500, 750, 900, 975)
 
 
 def _snapshot_device(torch, pool, w):
@@ -93,6 +96,8 @@ def test_training_step_full_size():
                                  phos.V_READS | phos.V_WRITES | phos.V_TRACK, vout, cap,
                                  vcnt.data_ptr(), app)
         for j, L in enumerate(launches):
+            if j in FINAL_AT:
+                phos.phos_ckpt_precopy_final(cb, specs[j:], app)
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, ptrs[j], N_REC, app)
         phos.phos_ckpt_recopy(cb, app)
@@ -106,17 +111,29 @@ def test_training_step_full_size():
         assert torch.equal(img_b, want_b), "recopy image != pool at t2"
         n_img_pages = nimg // page
         assert sa.bg_pages + sa.cow_pages == n_img_pages
-        assert n_img_pages - sb.recopy_pages <= sb.bg_pages <= n_img_pages
+        assert n_img_pages - sb.recopy_pages - sb.precopy_pages <= sb.bg_pages <= n_img_pages
         del want_a, want_b, img_a, img_b
 
-        # write-set tracking of all 1,000 launches against the oracle
+        # write-set tracking of all 1,000 launches against the oracle; the
+        # pre-copy rounds took the dirty pages outside the write intervals of
+        # the launches after the last round
         dirty, victim = _oracle_maps(w, launches, base)
-        assert np.array_equal(dirty_gpu, oracle.pages_to_bitmap(dirty, w.n_pages))
+        table = oracle.Table.from_world(w, base)
+        later = np.zeros(w.n_pages, np.uint8)
+        for L in launches[max(FINAL_AT):] if FINAL_AT else []:
+            for iv in oracle.spec_build(table, L.arg_values(base)):
+                lo = max(int(iv["lo"]), base) - base
+                hi = min(int(iv["hi"]), base + w.pool_bytes) - base
+                if int(iv["mode"]) & 2 and hi > lo:
+                    later[lo // page:(hi - 1) // page + 1] = 1
+        dirty_left = dirty & later if FINAL_AT else dirty
+        assert np.array_equal(dirty_gpu, oracle.pages_to_bitmap(dirty_left, w.n_pages))
         assert np.array_equal(victim_gpu, oracle.pages_to_bitmap(victim, w.n_pages))
         inbuf = np.zeros(w.n_pages, np.uint8)
         for off, nb in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
             inbuf[off // page:(off + nb) // page] = 1
-        assert sb.recopy_pages == int(((dirty | victim) & inbuf).sum())
+        assert sb.recopy_pages == int(((dirty_left | victim) & inbuf).sum())
+        assert sb.precopy_pages == int(((dirty & (1 - dirty_left)) & inbuf).sum())
 
         # violation lists of sampled launches against the oracle
         nv = int(vcnt.item())

@@ -286,8 +286,9 @@ def run_training_step(args):
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
                 if j == 0 and args.copy_after_validation:
                     start_copies(ca, cb)
-            if j in final_at:  # dirty pages no remaining launch may write
-                phos.phos_ckpt_precopy_final(cb, specs[j:], app)
+            if j in final_at:  # pages no remaining launch may write
+                ahead = min((j // chunk + 1) * chunk, n_launch) - j  # validated, still to come
+                phos.phos_ckpt_precopy_final(cb, specs[j:], ahead, app)
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 

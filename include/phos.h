@@ -305,20 +305,29 @@ phos_status phos_ckpt_precopy(phos_ckpt *ck, hipStream_t app_stream);
 
 /* Sections 4.3 and 7, iterative recopy with the window's remaining launches
  * known (their access streams validated ahead, as the speculation allows):
- * a pre-copy round that copies only the dirty pages none of the `upcoming`
- * launches may write, i.e. pages outside every write interval of their
- * specs.  Such a page has had its last writer in the window issued on
- * app_stream already, so it is unmarked and copied once, in app_stream
- * order; a later write to it can only be a violation, which marks the victim
- * map, and the recopy at the re-quiesce copies victim pages.  Unlike
- * phos_ckpt_precopy the marks of launches validated ahead of their turn do
- * no harm: their pages are in the upcoming write intervals.  upcoming: the
- * specs of every launch of the window still to be issued on app_stream (any
- * order; n_upcoming 0: none).  E_INVAL for an unknown spec, E_STATE for a
- * copy-on-write checkpoint, after the recopy, or under stream capture (the
- * mask is built on the host at the call).  Asynchronous on app_stream. */
+ * a pre-copy round that copies only pages whose last write in the window has
+ * been issued on app_stream already, and unmarks them.
+ *  - Dirty pages outside every write interval of the `upcoming` specs: no
+ *    remaining launch may write them validly.
+ *  - Victim pages outside those intervals whose latest failing write
+ *    (validation numbers launches in validation order) came from a launch
+ *    issued already: the n_validated_ahead most recently validated launches
+ *    are the ones still to come.
+ * A later write to such a page can only be a violation found by a later
+ * validation, which marks it again, and the recopy at the re-quiesce copies
+ * every marked page.  Unlike phos_ckpt_precopy, launches validated ahead of
+ * their turn do no harm.  upcoming: the specs of every launch of the window
+ * still to be issued on app_stream (any order; n_upcoming 0: none), of which
+ * the first n_validated_ahead have been validated (validations follow the
+ * launch order).  Every tracking validation so far must be complete in
+ * app_stream order (on app_stream or waited for); with tracking validations
+ * on other streams victim pages are left to the recopy.  E_INVAL for an
+ * unknown spec or n_validated_ahead above n_upcoming or above the launches
+ * validated since the maps were cleared; E_STATE for a copy-on-write
+ * checkpoint, after the recopy, or under stream capture (the mask is built
+ * on the host at the call).  Asynchronous on app_stream. */
 phos_status phos_ckpt_precopy_final(phos_ckpt *ck, const phos_spec *upcoming, uint32_t n_upcoming,
-                                    hipStream_t app_stream);
+                                    uint32_t n_validated_ahead, hipStream_t app_stream);
 
 /* Finish: wait for every copy (and app_stream), drain image to host_image if
  * given, free the handle.  A recopy checkpoint not yet recopied is recopied

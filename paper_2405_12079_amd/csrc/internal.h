@@ -67,6 +67,8 @@ struct VArgs {
   uint32_t page_shift, n_pages;
   const uint32_t *page_buf;  // per pool page: buffer index or kNone
   uint8_t *dirty, *victim;   // page maps: one byte per pool page (padded to 32)
+  uint32_t *victim_seq;      // per pool page: the latest launch with a failing write there
+  uint32_t seq0;             // sequence number of the call's first launch (then +1 per launch)
   uint32_t *vlist;           // victim pages newly marked (appended)
   uint32_t *vmeta;           // [0] appended, [1] CoW cursor, [2] CoW exit ticket, [3] overflow
   uint32_t vlist_cap;
@@ -170,6 +172,8 @@ struct TwinArgs {
   uint32_t page_shift, vlist_cap;
   const uint32_t *page_buf;
   uint8_t *dirty, *victim;
+  uint32_t *victim_seq;  // as VArgs
+  uint32_t seq;          // this launch's sequence number
   uint32_t *vlist, *vmeta;
   phos_violation *out;  // unordered
   uint64_t cap;
@@ -199,6 +203,12 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
                              hipStream_t s);
+// Final pages of a pre-copy round: dirty pages, and victim pages whose
+// latest failing write came from a launch numbered <= thr (those are
+// unmarked in the victim map), minus the pages of `exclude`.
+hipError_t launch_finallist(const uint8_t *dirty, uint8_t *victim, const uint32_t *victim_seq,
+                            uint32_t thr, const uint32_t *exclude, uint32_t nwords,
+                            uint32_t n_pages, uint32_t *list, unsigned int *count, hipStream_t s);
 // exclude: optional word mask (32 pages a word) of pages left out of the list
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s,

@@ -152,6 +152,7 @@ struct VShared {
   uint32_t win_fw;   // first global dirty-map word of the LDS window
   uint32_t win_nw;   // window words in use, or kNone (write pages straight to the map)
   VLaunch L;
+  uint32_t seq;  // sequence number of the tile's launch
   unsigned long long off;
 };
 
@@ -171,12 +172,16 @@ __device__ __forceinline__ void track_record(const VArgs &A, const VShared &S, u
     } else {
       A.dirty[page] = 1;
     }
-  } else if (A.page_buf[page] != kNone && A.victim[page] == 0) {
-    // newly marked victim page (a stale read only adds a duplicate)
-    A.victim[page] = 1;
-    const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
-    if (i < A.vlist_cap) A.vlist[i] = page;
-    else A.vmeta[3] = 1;
+  } else if (A.page_buf[page] != kNone) {
+    // the latest launch that writes here out of its speculation
+    atomicMax(&A.victim_seq[page], S.seq);
+    if (A.victim[page] == 0) {
+      // newly marked victim page (a stale read only adds a duplicate)
+      A.victim[page] = 1;
+      const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
+      if (i < A.vlist_cap) A.vlist[i] = page;
+      else A.vmeta[3] = 1;
+    }
   }
 }
 
@@ -287,11 +292,9 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   const uint32_t tile = blockIdx.x;
 
   if (tid == 0) {
-    if (BATCH) {
-      S.L = A.launches[A.tile_launch[tile]];
-    } else {
-      S.L = A.single;
-    }
+    const uint32_t pos = BATCH ? A.tile_launch[tile] : 0u;
+    S.L = BATCH ? A.launches[pos] : A.single;
+    S.seq = A.seq0 + pos;
   }
   __syncthreads();
   const uint32_t niv = rfl(BATCH ? S.L.niv : single.niv);
@@ -959,6 +962,45 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Final pages of a pre-copy round (see launch_finallist): one 32-page word
+// per thread, listed in word order like pagelist_kernel.
+__global__ void __launch_bounds__(256)
+    finallist_kernel(const uint8_t *dirty, uint8_t *victim, const uint32_t *victim_seq,
+                     uint32_t thr, const uint32_t *exclude, uint32_t nwords, uint32_t n_pages,
+                     uint32_t *list, unsigned int *count) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t bits = 0;
+  if (w < nwords) {
+    uint32_t v = bytes_to_mask(victim + 32ull * w);
+    for (uint32_t m = v; m; m &= m - 1) {
+      const uint32_t b = __ffs(m) - 1;
+      const uint32_t q = victim_seq[32ull * w + b];
+      if (q == 0 || q > thr) v &= ~(1u << b);  // a failing write still to come (or unknown)
+    }
+    bits = (bytes_to_mask(dirty + 32ull * w) | v) & ~exclude[w];
+    const uint64_t last = (uint64_t)w * 32 + 32;
+    if (last > n_pages) bits &= (n_pages - w * 32 >= 32) ? ~0u : ((1u << (n_pages - w * 32)) - 1u);
+    for (uint32_t m = v & bits; m; m &= m - 1) victim[32ull * w + __ffs(m) - 1] = 0;
+  }
+  const uint32_t c = __popc(bits);
+  uint32_t incl = c;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t x = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += x;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane == 0 && total) base = atomicAdd(count, total);
+  base = __shfl(base, 0, 64);
+  uint32_t pos = base + incl - c;
+  while (bits) {
+    const uint32_t bit = __ffs(bits) - 1;
+    list[pos++] = w * 32 + bit;
+    bits &= bits - 1;
+  }
+}
+
 // Copy the listed pages (no claims: the application is quiesced).
 __global__ void __launch_bounds__(kBgCopyThreads)
     gather_pages_kernel(CopyArgs C, const uint32_t *list, const unsigned int *count) {
@@ -1087,11 +1129,14 @@ __device__ __forceinline__ void twin_track(const TwinArgs &A, bool act, uint64_t
   const uint32_t dp = reason == 0 ? page : kNone;
   const uint32_t prev = __shfl_up(dp, 1, 64);
   if (dp != kNone && (lane == 0 || prev != dp)) A.dirty[dp] = 1;
-  if (reason != 0 && in && A.page_buf[page] != kNone && A.victim[page] == 0) {
-    A.victim[page] = 1;  // newly marked (a stale read only adds a duplicate)
-    const uint32_t k = atomicAdd(&A.vmeta[0], 1u);
-    if (k < A.vlist_cap) A.vlist[k] = page;
-    else A.vmeta[3] = 1;
+  if (reason != 0 && in && A.page_buf[page] != kNone) {
+    atomicMax(&A.victim_seq[page], A.seq);
+    if (A.victim[page] == 0) {
+      A.victim[page] = 1;  // newly marked (a stale read only adds a duplicate)
+      const uint32_t k = atomicAdd(&A.vmeta[0], 1u);
+      if (k < A.vlist_cap) A.vlist[k] = page;
+      else A.vmeta[3] = 1;
+    }
   }
 }
 
@@ -1325,6 +1370,15 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
   if (!n_pages) return hipSuccess;
   hipLaunchKernelGGL(mark_pieces_kernel, dim3((n_pages + 255) / 256), dim3(256), 0, s, img_page,
                      state, n_pages, chunk_pages, flag, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_finallist(const uint8_t *dirty, uint8_t *victim, const uint32_t *victim_seq,
+                            uint32_t thr, const uint32_t *exclude, uint32_t nwords,
+                            uint32_t n_pages, uint32_t *list, unsigned int *count, hipStream_t s) {
+  if (!nwords) return hipSuccess;
+  hipLaunchKernelGGL(finallist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, dirty, victim,
+                     victim_seq, thr, exclude, nwords, n_pages, list, count);
   return hipGetLastError();
 }
 

@@ -80,6 +80,11 @@ struct phos_ctx {
   uint32_t *d_page_buf = nullptr, *d_img_page = nullptr;
   uint8_t *d_dirty = nullptr, *d_victim = nullptr;  // page maps, n_pages padded to 32
   uint32_t *d_vlist = nullptr, *d_vmeta = nullptr;  // victim pages appended by validation
+  // per pool page (padded to 32): the largest sequence number of a launch
+  // with a failing write there; validated launches are numbered from 1 in
+  // validation order since the maps were last cleared
+  uint32_t *d_victim_seq = nullptr;
+  uint32_t vseq = 0;
   uint32_t vlist_cap = 0;
   uint32_t *d_err = nullptr;
 
@@ -248,7 +253,7 @@ static bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
 static phos_status ctx_free(phos_ctx *c) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_page_buf, c->d_img_page, c->d_dirty, c->d_victim, c->d_err, c->d_vlist,
-                  c->d_vmeta, c->d_scratch,
+                  c->d_vmeta, c->d_victim_seq, c->d_scratch,
                   c->d_cursor, c->d_tile_count, c->d_tile_off, c->d_seg_sum, c->d_seg_prefix};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -328,6 +333,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   CK(dalloc(&c->d_img_page, c->n_pages));
   CK(dalloc(&c->d_dirty, 32ull * c->nwords));
   CK(dalloc(&c->d_victim, 32ull * c->nwords));
+  CK(dalloc(&c->d_victim_seq, 32ull * c->nwords));
   CK(dalloc(&c->d_err, 1));
   c->vlist_cap = 2 * c->n_pages + 4096;
   CK(dalloc(&c->d_vlist, c->vlist_cap));
@@ -352,6 +358,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       !hipck(hipMemset(c->d_img_page, 0xFF, c->n_pages * 4ull), "hipMemset") ||
       !hipck(hipMemset(c->d_dirty, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_victim, 0, c->nwords * 32ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_victim_seq, 0, c->nwords * 128ull), "hipMemset") ||
       !hipck(hipMemset(c->d_err, 0, 4), "hipMemset") ||
       !hipck(hipMemset(c->d_vmeta, 0, 16), "hipMemset") ||
       !hipck(hipMemset(c->d_cursor, 0, 8), "hipMemset") ||
@@ -601,6 +608,7 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   a.page_buf = c->d_page_buf;
   a.dirty = c->d_dirty;
   a.victim = c->d_victim;
+  a.victim_seq = c->d_victim_seq;
   a.vlist = c->d_vlist;
   a.vmeta = c->d_vmeta;
   a.vlist_cap = c->vlist_cap;
@@ -686,6 +694,8 @@ extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const ui
   a.page_buf = c->d_page_buf;
   a.dirty = c->d_dirty;
   a.victim = c->d_victim;
+  a.victim_seq = c->d_victim_seq;
+  a.seq = ++c->vseq;
   a.vlist = c->d_vlist;
   a.vmeta = c->d_vmeta;
   a.vlist_cap = c->vlist_cap;
@@ -722,6 +732,7 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   a.single.n = n;
   a.single.launch_id = h->launch_id;
   a.single.tile0 = 0;
+  a.seq0 = ++c->vseq;
   a.nlaunch = 1;
   a.ntiles = (uint32_t)ntiles;
   return run_validation(c, a, &ds, out, cap, n_violations, stream);
@@ -821,6 +832,8 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   a.tile_launch = reinterpret_cast<const uint32_t *>(hit->dev + head);
   a.nlaunch = nlaunch;
   a.ntiles = (uint32_t)tiles;
+  a.seq0 = c->vseq + 1;  // launch i is numbered seq0 + i
+  c->vseq += nlaunch;
   static DevSpec unused;  // kernel parameter of the single-launch path
   return run_validation(c, a, &unused, out, cap, n_violations, stream);
 }
@@ -832,6 +845,8 @@ extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
   DeviceGuard g(c->device);
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, s));
   HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, s));
+  HIP_TRY(launch_fill_u32(c->d_victim_seq, 32ull * c->nwords, 0, s));
+  c->vseq = 0;
   HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, s));
   return PHOS_OK;
 }
@@ -990,6 +1005,8 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   if (!c->open_ckpt[PHOS_COW] && !c->open_ckpt[PHOS_RECOPY]) {
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, c->aux));
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_victim), 8ull * c->nwords, 0, c->aux));
+    HIP_TRY(launch_fill_u32(c->d_victim_seq, 32ull * c->nwords, 0, c->aux));
+    c->vseq = 0;
     HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, c->aux));
     c->victims_pending = false;
     c->victim_stream_set = c->victim_streams_many = false;
@@ -1181,11 +1198,14 @@ extern "C" phos_status phos_ckpt_precopy(phos_ckpt *k, hipStream_t app) {
 }
 
 extern "C" phos_status phos_ckpt_precopy_final(phos_ckpt *k, const phos_spec *upcoming,
-                                               uint32_t n_upcoming, hipStream_t app) {
-  if (!k || (n_upcoming && !upcoming)) return fail(PHOS_E_INVAL, "phos_ckpt_precopy_final: bad argument");
+                                               uint32_t n_upcoming, uint32_t n_validated_ahead,
+                                               hipStream_t app) {
+  if (!k || (n_upcoming && !upcoming) || n_validated_ahead > n_upcoming)
+    return fail(PHOS_E_INVAL, "phos_ckpt_precopy_final: bad argument");
   if (k->protocol != PHOS_RECOPY) return fail(PHOS_E_STATE, "pre-copy needs a recopy checkpoint");
   if (k->recopied) return fail(PHOS_E_STATE, "recopy already done");
   phos_ctx *c = k->ctx;
+  if (n_validated_ahead > c->vseq) return fail(PHOS_E_INVAL, "more launches ahead than validated");
   std::vector<const HostSpec *> hs(n_upcoming);
   for (uint32_t i = 0; i < n_upcoming; ++i) {
     hs[i] = get_spec(c, upcoming[i]);
@@ -1220,10 +1240,20 @@ extern "C" phos_status phos_ckpt_precopy_final(phos_ckpt *k, const phos_spec *up
   HIP_TRY(hipEventRecord(k->mask_evt, app));
   k->mask_used = true;
   // in app_stream order: after the launches issued so far; the dirty pages
-  // outside the mask have had their last writer issued already
+  // outside the mask have had their last valid writer issued already, and so
+  // have the victim pages whose latest failing write came from a launch
+  // numbered at most thr (the launches validated so far, minus those still
+  // to come).  Victim pages are left alone when tracking calls went to
+  // other streams: their marks are not ordered before this round.
+  const bool victims_ordered =
+      !c->victim_streams_many && (!c->victim_stream_set || c->victim_stream == app);
   HIP_TRY(launch_fill_u32(s.list_count, 1, 0, app));
-  HIP_TRY(launch_pagelist(c->d_dirty, nullptr, c->nwords, c->n_pages, s.list, s.list_count, app,
-                          k->d_mask));
+  if (victims_ordered)
+    HIP_TRY(launch_finallist(c->d_dirty, c->d_victim, c->d_victim_seq, c->vseq - n_validated_ahead,
+                             k->d_mask, c->nwords, c->n_pages, s.list, s.list_count, app));
+  else
+    HIP_TRY(launch_pagelist(c->d_dirty, nullptr, c->nwords, c->n_pages, s.list, s.list_count, app,
+                            k->d_mask));
   CopyArgs a = copy_args(c, s, k->image, true, &s.counters[5]);
   HIP_TRY(launch_precopy(a, s.list, s.list_count, c->d_dirty, c->bg_grid, app));
   return PHOS_OK;

@@ -88,7 +88,7 @@ SIGNATURES = [
     ("phos_ckpt_cow", [P, U32, P]),
     ("phos_ckpt_recopy", [P, P]),
     ("phos_ckpt_precopy", [P, P]),
-    ("phos_ckpt_precopy_final", [P, P, U32, P]),
+    ("phos_ckpt_precopy_final", [P, P, U32, U32, P]),
     ("phos_ckpt_staging", [P, P, U64]),
     ("phos_ckpt_start", [P, P]),
     ("phos_ckpt_end", [P, P, P]),
@@ -290,10 +290,10 @@ def phos_ckpt_precopy(ck, app_stream) -> None:
     _call("phos_ckpt_precopy", ck, _stream(app_stream))
 
 
-def phos_ckpt_precopy_final(ck, upcoming, app_stream) -> None:
+def phos_ckpt_precopy_final(ck, upcoming, n_validated_ahead, app_stream) -> None:
     k = len(upcoming)
     sp = (U32 * max(1, k))(*upcoming)
-    _call("phos_ckpt_precopy_final", ck, sp, k, _stream(app_stream))
+    _call("phos_ckpt_precopy_final", ck, sp, k, n_validated_ahead, _stream(app_stream))
 
 
 def phos_ckpt_end(ck, app_stream) -> phos_ckpt_stats:

@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_harness import Env, bits_to_pages
+from tests.gpu_harness import Env, bits_to_pages, final_rounds_expected
 
 pytestmark = pytest.mark.gpu
 N = 1_000_000
@@ -333,13 +333,31 @@ def _write_pages(env, launches):
     return m
 
 
+def _victim_last(env, launches, j0, j1):
+    """Per pool page: the last launch j in [j0, j1) with a failing write
+    inside a buffer there (-1: none), from the oracle's tracking of each
+    launch on its own."""
+    w = env.world
+    last = np.full(w.n_pages, -1, np.int64)
+    for j in range(j0, j1):
+        L = launches[j]
+        d, v = np.zeros(w.n_pages, np.uint8), np.zeros(w.n_pages, np.uint8)
+        oracle.track(oracle.spec_build(env.table, L.arg_values(env.base)),
+                     synth.records_host(env.hw, L), env.table, env.base, w.page_bytes,
+                     w.n_pages, d, v)
+        last[v != 0] = j
+    return last
+
+
 def test_precopy_final_rounds(env):
     """Iterative recopy with the window's remaining launches known: every
     launch of the window is validated up front in one batched call (as the
-    training step does), and two rounds copy the dirty pages none of the
-    launches still to come may write.  The final dirty map is the oracle's
-    dirty map restricted to the last round's upcoming write pages, the
-    rounds copy the rest of it, and the image is the snapshot at t2."""
+    training step does), and two rounds copy the pages whose last write in
+    the window has been issued: dirty pages outside the write intervals of
+    the launches still to come, and victim pages (outside them too) whose
+    last failing write came from a launch issued already.  The maps left,
+    the pages copied by the rounds and by the recopy follow the oracle, and
+    the image is the snapshot at t2."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -348,6 +366,7 @@ def test_precopy_final_rounds(env):
     res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
                             lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
                             host, snap_before=(T2 - T1,), window=(0, T2 - T1), keep_violations=False)
+    last = _victim_last(env, launches, T1, T2)
     T.cuda.synchronize()
     groups = {g: env.records(launches[g * 20:(g + 1) * 20], N) for g in range(T1 // 20, T2 // 20)}
     T.cuda.synchronize()
@@ -360,14 +379,17 @@ def test_precopy_final_rounds(env):
     phos.phos_validate_batch(env.ctx, [specs[j] for j in range(T1, T2)],
                              [ptr[j] for j in range(T1, T2)], [N] * (T2 - T1), V, out, cap, cnt,
                              env.app)
+    with pytest.raises(phos.PhosError) as e:  # more launches ahead than upcoming
+        phos.phos_ckpt_precopy_final(ck, [specs[T2 - 1]], 2, env.app)
+    assert e.value.status == phos.E_INVAL
     rounds = [T1 + (T2 - T1) // 2, T2 - 6]
     for j in range(T1, T2):
         if j in rounds:
-            phos.phos_ckpt_precopy_final(ck, [specs[i] for i in range(j, T2)], env.app)
+            phos.phos_ckpt_precopy_final(ck, [specs[i] for i in range(j, T2)], T2 - j, env.app)
         env.mutate(launches[j], ptr[j], N)
     phos.phos_ckpt_recopy(ck, env.app)
     with pytest.raises(phos.PhosError) as e:  # no round after the recopy
-        phos.phos_ckpt_precopy_final(ck, [], env.app)
+        phos.phos_ckpt_precopy_final(ck, [], 0, env.app)
     assert e.value.status == phos.E_STATE
     d = phos.phos_track_read(env.ctx, 0, w.n_pages)
     v = phos.phos_track_read(env.ctx, 1, w.n_pages)
@@ -375,14 +397,14 @@ def test_precopy_final_rounds(env):
     T.cuda.synchronize()
     for j in range(T1, T2):
         phos.phos_spec_release(env.ctx, specs[j])
-    upcoming = _write_pages(env, launches[rounds[-1]:T2])
-    dirty_left = res.dirty & upcoming
-    assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left, w.n_pages))
-    assert np.array_equal(v, oracle.pages_to_bitmap(res.victim, w.n_pages))
     inbuf = _buffer_pages(w)
-    assert stats.precopy_pages == int((res.dirty & (1 - upcoming) & inbuf).sum())
-    assert stats.precopy_pages > 0
-    assert stats.recopy_pages == int(((dirty_left | res.victim) & inbuf).sum())
+    dirty_left, victim_left, pre = final_rounds_expected(
+        res.dirty, res.victim, last, rounds, lambda r: _write_pages(env, launches[r:T2]), inbuf)
+    assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left.astype(np.uint8), w.n_pages))
+    assert np.array_equal(v, oracle.pages_to_bitmap(victim_left.astype(np.uint8), w.n_pages))
+    assert int(victim_left.sum()) < int(res.victim.astype(bool).sum())  # victims went early too
+    assert stats.precopy_pages == pre > 0
+    assert stats.recopy_pages == int(((dirty_left | victim_left) & inbuf.astype(bool)).sum())
     assert np.array_equal(image.cpu().numpy(), res.snapshots[T2 - T1]), "image != snapshot at t2"
 
 

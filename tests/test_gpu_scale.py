@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 import synth
+from tests.gpu_harness import final_rounds_expected
 
 pytestmark = pytest.mark.gpu
 N_LAUNCH, N_REC = 1000, 1_000_000
@@ -37,26 +38,35 @@ def _snapshot_device(torch, pool, w):
 
 
 def _oracle_maps(w, launches, base):
-    """Dirty and victim pages of every launch, by the oracle, on host threads."""
+    """Dirty and victim pages of every launch, by the oracle, on host threads,
+    and per page the last launch with a failing write inside a buffer there
+    (-1: none)."""
     hw = synth.HostWorld(w, base)
     table = oracle.Table.from_world(w, base)
     npg = w.n_pages
 
-    def part(ls):
+    def part(js):
         d, v = np.zeros(npg, np.uint8), np.zeros(npg, np.uint8)
-        for L in ls:
+        last = np.full(npg, -1, np.int64)
+        for j in js:
+            L = launches[j]
             rec = synth.records_host(hw, L)
+            vj = np.zeros(npg, np.uint8)
             oracle.track(oracle.spec_build(table, L.arg_values(base)), rec, table, base,
-                         w.page_bytes, npg, d, v)
-        return d, v
+                         w.page_bytes, npg, d, vj)
+            v |= vj
+            last[vj != 0] = j
+        return d, v, last
 
-    parts = [launches[i::8] for i in range(8)]
+    parts = [list(range(len(launches)))[i::8] for i in range(8)]
     dirty, victim = np.zeros(npg, np.uint8), np.zeros(npg, np.uint8)
+    last = np.full(npg, -1, np.int64)
     with cf.ThreadPoolExecutor(8) as ex:
-        for d, v in ex.map(part, parts):
+        for d, v, lp in ex.map(part, parts):
             dirty |= d
             victim |= v
-    return dirty, victim
+            last = np.maximum(last, lp)
+    return dirty, victim, last
 
 
 def test_training_step_full_size():
@@ -96,8 +106,8 @@ def test_training_step_full_size():
                                  phos.V_READS | phos.V_WRITES | phos.V_TRACK, vout, cap,
                                  vcnt.data_ptr(), app)
         for j, L in enumerate(launches):
-            if j in FINAL_AT:
-                phos.phos_ckpt_precopy_final(cb, specs[j:], app)
+            if j in FINAL_AT:  # every launch was validated up front
+                phos.phos_ckpt_precopy_final(cb, specs[j:], N_LAUNCH - j, app)
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, ptrs[j], N_REC, app)
         phos.phos_ckpt_recopy(cb, app)
@@ -114,26 +124,33 @@ def test_training_step_full_size():
         assert n_img_pages - sb.recopy_pages - sb.precopy_pages <= sb.bg_pages <= n_img_pages
         del want_a, want_b, img_a, img_b
 
-        # write-set tracking of all 1,000 launches against the oracle; the
-        # pre-copy rounds took the dirty pages outside the write intervals of
-        # the launches after the last round
-        dirty, victim = _oracle_maps(w, launches, base)
+        # write-set tracking of all 1,000 launches against the oracle, and the
+        # pages the pre-copy rounds took (their last write issued before the
+        # round)
+        dirty, victim, last = _oracle_maps(w, launches, base)
         table = oracle.Table.from_world(w, base)
-        later = np.zeros(w.n_pages, np.uint8)
-        for L in launches[max(FINAL_AT):] if FINAL_AT else []:
-            for iv in oracle.spec_build(table, L.arg_values(base)):
-                lo = max(int(iv["lo"]), base) - base
-                hi = min(int(iv["hi"]), base + w.pool_bytes) - base
-                if int(iv["mode"]) & 2 and hi > lo:
-                    later[lo // page:(hi - 1) // page + 1] = 1
-        dirty_left = dirty & later if FINAL_AT else dirty
-        assert np.array_equal(dirty_gpu, oracle.pages_to_bitmap(dirty_left, w.n_pages))
-        assert np.array_equal(victim_gpu, oracle.pages_to_bitmap(victim, w.n_pages))
+
+        def upcoming(r):
+            m = np.zeros(w.n_pages, np.uint8)
+            for L in launches[r:]:
+                for iv in oracle.spec_build(table, L.arg_values(base)):
+                    lo = max(int(iv["lo"]), base) - base
+                    hi = min(int(iv["hi"]), base + w.pool_bytes) - base
+                    if int(iv["mode"]) & 2 and hi > lo:
+                        m[lo // page:(hi - 1) // page + 1] = 1
+            return m
+
         inbuf = np.zeros(w.n_pages, np.uint8)
         for off, nb in zip(w.alloc_off.tolist(), w.alloc_bytes.tolist()):
             inbuf[off // page:(off + nb) // page] = 1
-        assert sb.recopy_pages == int(((dirty_left | victim) & inbuf).sum())
-        assert sb.precopy_pages == int(((dirty & (1 - dirty_left)) & inbuf).sum())
+        dirty_left, victim_left, pre = final_rounds_expected(dirty, victim, last, FINAL_AT,
+                                                             upcoming, inbuf)
+        assert np.array_equal(dirty_gpu, oracle.pages_to_bitmap(dirty_left.astype(np.uint8),
+                                                                w.n_pages))
+        assert np.array_equal(victim_gpu, oracle.pages_to_bitmap(victim_left.astype(np.uint8),
+                                                                 w.n_pages))
+        assert sb.recopy_pages == int(((dirty_left | victim_left) & inbuf.astype(bool)).sum())
+        assert sb.precopy_pages == pre
 
         # violation lists of sampled launches against the oracle
         nv = int(vcnt.item())

@@ -230,8 +230,10 @@ phos_status phos_twin_scale_add(phos_ctx *ctx, phos_spec spec, const uint64_t *x
                                 phos_violation *out, uint64_t cap, uint64_t *n_violations,
                                 hipStream_t stream);
 
-/* Clear the dirty and victim bitmaps (asynchronous on stream).  E_STATE while
- * a recopy checkpoint is open: its recopy list is read from these maps. */
+/* Clear the dirty and victim bitmaps, the victim list and the launch
+ * numbering of validation (the next validated launch is number 1 again;
+ * asynchronous on stream).  E_STATE while a recopy checkpoint is open: its
+ * recopy list is read from these maps. */
 phos_status phos_track_reset(phos_ctx *ctx, hipStream_t stream);
 /* Synchronous copy of a bitmap to host: which 0 = dirty, 1 = victim.  Bit p%32
  * of word p/32 is pool page p; nwords >= ceil(pool pages / 32). */
@@ -245,8 +247,9 @@ phos_status phos_track_read(phos_ctx *ctx, uint32_t which, uint32_t *host_words,
  * copying straight to the host; E_INVAL for pageable memory).  host_image: optional pinned host memory
  * filled from image by phos_ckpt_end (NULL: none).  The background copy of
  * every page starts on copy_stream unless PHOS_CKPT_DEFER_BACKGROUND.
- * Opening resets the dirty / victim bitmaps when no other checkpoint is
- * open.  At most one checkpoint per protocol may be open (E_STATE). */
+ * Opening resets the dirty / victim bitmaps (and the launch numbering of
+ * validation) when no other checkpoint is open.  At most one checkpoint per
+ * protocol may be open (E_STATE). */
 phos_status phos_ckpt_begin(phos_ctx *ctx, uint32_t protocol, uint32_t flags, void *image,
                             void *host_image, hipStream_t copy_stream, phos_ckpt **out);
 

@@ -848,6 +848,8 @@ extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
   HIP_TRY(launch_fill_u32(c->d_victim_seq, 32ull * c->nwords, 0, s));
   c->vseq = 0;
   HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, s));
+  c->victims_pending = false;  // the list is empty again
+  c->victim_stream_set = c->victim_streams_many = false;
   return PHOS_OK;
 }
 

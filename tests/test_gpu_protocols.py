@@ -349,15 +349,19 @@ def _victim_last(env, launches, j0, j1):
     return last
 
 
-def test_precopy_final_rounds(env):
+@pytest.mark.parametrize("vstream", ["same", "other"])
+def test_precopy_final_rounds(env, vstream):
     """Iterative recopy with the window's remaining launches known: every
     launch of the window is validated up front in one batched call (as the
     training step does), and two rounds copy the pages whose last write in
     the window has been issued: dirty pages outside the write intervals of
     the launches still to come, and victim pages (outside them too) whose
-    last failing write came from a launch issued already.  The maps left,
-    the pages copied by the rounds and by the recopy follow the oracle, and
-    the image is the snapshot at t2."""
+    last failing write came from a launch issued already.  With the
+    validation on a stream of its own ("other", waited for with an event)
+    the victim marks are not ordered before the rounds, which then leave
+    every victim page to the recopy.  The maps left, the pages copied by the
+    rounds and by the recopy follow the oracle, and the image is the
+    snapshot at t2."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -376,9 +380,12 @@ def test_precopy_final_rounds(env):
     ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, None, env.copy)
     cap = 200_000
     out, cnt = env.violations_buffers(cap)
+    vs = T.cuda.Stream() if vstream == "other" else env.app
+    vs.wait_stream(env.app)
     phos.phos_validate_batch(env.ctx, [specs[j] for j in range(T1, T2)],
                              [ptr[j] for j in range(T1, T2)], [N] * (T2 - T1), V, out, cap, cnt,
-                             env.app)
+                             vs)
+    env.app.wait_stream(vs)
     with pytest.raises(phos.PhosError) as e:  # more launches ahead than upcoming
         phos.phos_ckpt_precopy_final(ck, [specs[T2 - 1]], 2, env.app)
     assert e.value.status == phos.E_INVAL
@@ -398,11 +405,14 @@ def test_precopy_final_rounds(env):
     for j in range(T1, T2):
         phos.phos_spec_release(env.ctx, specs[j])
     inbuf = _buffer_pages(w)
+    if vstream == "other":
+        last[:] = -1  # no victim page is known to be final
     dirty_left, victim_left, pre = final_rounds_expected(
         res.dirty, res.victim, last, rounds, lambda r: _write_pages(env, launches[r:T2]), inbuf)
     assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left.astype(np.uint8), w.n_pages))
     assert np.array_equal(v, oracle.pages_to_bitmap(victim_left.astype(np.uint8), w.n_pages))
-    assert int(victim_left.sum()) < int(res.victim.astype(bool).sum())  # victims went early too
+    if vstream == "same":  # victims went early too
+        assert int(victim_left.sum()) < int(res.victim.astype(bool).sum())
     assert stats.precopy_pages == pre > 0
     assert stats.recopy_pages == int(((dirty_left | victim_left) & inbuf.astype(bool)).sum())
     assert np.array_equal(image.cpu().numpy(), res.snapshots[T2 - T1]), "image != snapshot at t2"

@@ -812,6 +812,20 @@ def run_cold_start(args):
         assert same, "cold-start restore differs from stop-the-world restore"
         del ref_back
     phos.phos_destroy(ctx)
+    if not args.no_cpu_baseline:
+        # the oracle's restore: each buffer's image bytes to its place in the
+        # pool, for the buffers in the image's first 2 GiB
+        cap = 2 << 30
+        img_off = np.concatenate([[0], np.cumsum(w.alloc_bytes.astype(np.int64))])
+        so, do, ln = [], [], []
+        for b in range(w.n_alloc):
+            if img_off[b] >= cap:
+                break
+            so.append(int(img_off[b]))
+            do.append(int(w.alloc_off[b]))
+            ln.append(int(min(w.alloc_bytes[b], cap - img_off[b])))
+        res["cpu_baseline"] = cpu_gather_baseline(w.seed, cap, so, do, ln,
+                                                  "image to pool of the image's first 2 GiB")
     return res
 
 
@@ -920,6 +934,24 @@ def run_serving(args):
         "plain_p99_ms": pp99, "batched_p99_ms": bp99,
         "batched": out["batched"], "plain": out["plain"],
     }
+
+
+def cpu_gather_baseline(seed, span, src_off, dst_off, lens, label):
+    """The oracle's gather (plain C, one thread) of runs of a seeded host
+    span: a bounded sample of the copies a workload makes (a snapshot of
+    pages into an image, or an image back into the pool)."""
+    import oracle
+    import synth
+    so, do, ln = (np.asarray(x, dtype=np.uint64) for x in (src_off, dst_off, lens))
+    src = synth.content_host(seed, 0, int(span))
+    dst = np.empty(int((do + ln).max()), np.uint8)
+    t0 = time.perf_counter()
+    oracle.gather(src, dst, so, do, ln)
+    t = time.perf_counter() - t0
+    n = int(ln.sum())
+    return {"value": round(n / t / 1e9, 3), "unit": "GB/s (bytes copied)", "cores": 1,
+            "kind": "oracle", "sample": f"{label}: {n / 2**30:.2f} GiB gathered in {t:.2f} s",
+            "cpu": cpu_model()}
 
 
 def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
@@ -1426,6 +1458,26 @@ def run_cow(args):
         log(f"[bench] {mode}: {rows[mode]}")
     phos.phos_destroy(ctx)
     d = rows["deferred"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's copy-on-write snapshot of the write-interval pages in the
+        # pool's first 2 GiB, each to its place in the image
+        cap = 2 << 30
+        img_off = np.concatenate([[0], np.cumsum(w.alloc_bytes.astype(np.int64))])
+        sel = np.flatnonzero((wpages & inbuf)[:cap // page])
+        so, do, ln = [], [], []
+        for pg in sel.tolist():
+            b = int(np.searchsorted(w.alloc_off, pg * page, side="right") - 1)
+            dst = int(img_off[b]) + pg * page - int(w.alloc_off[b])
+            if so and so[-1] + ln[-1] == pg * page and do[-1] + ln[-1] == dst:
+                ln[-1] += page
+            else:
+                so.append(pg * page)
+                do.append(dst)
+                ln.append(page)
+        if so:
+            cpu = cpu_gather_baseline(w.seed, cap, so, do, ln,
+                                      "write-interval pages of the pool's first 2 GiB to the image")
     return {
         "metric": "copy-on-write copy rate (HBM GB/s over the copy-on-write calls) and the "
                   "launches' stall",
@@ -1443,6 +1495,7 @@ def run_cow(args):
         "write_interval_pages": n_wpages,
         "by_order": rows,
         "parity": "the image equals the pool at t1 (whole image, every run)",
+        "cpu_baseline": cpu,
     }
 
 

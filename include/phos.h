@@ -144,6 +144,8 @@ typedef struct {
  *   PHOS_BG_BATCH        pages a background block claims per batch [64];
  *                        PHOS_BG_BATCH_PCIE when the image is in host memory [4]
  *   PHOS_COPY_NT         streaming (non-temporal) device copies [1]
+ *   PHOS_COW_DEEP        copy-on-write copies keep 16 loads in flight per
+ *                        thread instead of 8 [1]
  *   PHOS_VTILE_MAX       largest validation tile, records [16384 / 32768 tracked]
  *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles order in one kernel [4096]
  *   PHOS_RST_PAUSE       restore: polls (about 0.5 us each) the background

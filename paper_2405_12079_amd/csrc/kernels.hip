@@ -674,6 +674,7 @@ __device__ __forceinline__ bool unit_needed(const CopyArgs &C, uint32_t cand) {
   return __syncthreads_or(cand != kNone && C.img_page[cand] != kNone && C.state[cand] != kDone);
 }
 
+template <bool DEEP>
 __global__ void __launch_bounds__(kCThreads)
     cow_kernel(CopyArgs C, PageRanges R, VictimList V, uint32_t wait) {
   const uint32_t t = threadIdx.x;
@@ -707,8 +708,8 @@ __global__ void __launch_bounds__(kCThreads)
       const uint32_t first = (unit - R.units_prefix[j]) * kUnitPages;
       const uint32_t cand = (t < kUnitPages && first + t < R.np[j]) ? R.p0[j] + first + t : kNone;
       if (!unit_needed(C, cand)) continue;
-      if (wait) claim_copy<true>(cand, C, nullptr);
-      else claim_copy<false>(cand, C, nullptr);
+      if (wait) claim_copy<true, DEEP>(cand, C, nullptr);
+      else claim_copy<false, DEEP>(cand, C, nullptr);
       continue;
     }
     if (unit < range_units + list_units) {
@@ -716,8 +717,8 @@ __global__ void __launch_bounds__(kCThreads)
       uint32_t cand = (t < kVictimUnit && e < end) ? V.list[e] : kNone;
       if (cand >= C.n_pages) cand = kNone;
       if (!unit_needed(C, cand)) continue;
-      if (wait) claim_copy<true>(cand, C, nullptr);
-      else claim_copy<false>(cand, C, nullptr);
+      if (wait) claim_copy<true, DEEP>(cand, C, nullptr);
+      else claim_copy<false, DEEP>(cand, C, nullptr);
       continue;
     }
     // list overflowed: scan the victim page map, 64 words of 32 pages per unit
@@ -733,8 +734,8 @@ __global__ void __launch_bounds__(kCThreads)
         cand = w * 32 + (__ffs(bits) - 1);
         bits &= bits - 1;
       }
-      if (wait) claim_copy<true>(cand, C, nullptr);
-      else claim_copy<false>(cand, C, nullptr);
+      if (wait) claim_copy<true, DEEP>(cand, C, nullptr);
+      else claim_copy<false, DEEP>(cand, C, nullptr);
     }
   }
   // the last block out moves the list cursor past the entries handled here
@@ -1346,8 +1347,11 @@ hipError_t launch_cow(const CopyArgs &c, const PageRanges &r, const VictimList &
   // over them (the whole grid when the caller knows some may be new)
   uint32_t units = r.units_prefix[r.n] + (v.meta ? victim_blocks : 0);
   if (!units) return hipSuccess;
-  hipLaunchKernelGGL(cow_kernel, dim3(units < max_grid ? units : max_grid), dim3(kCThreads), 0, s,
-                     c, r, v, wait ? 1u : 0u);
+  const dim3 g(units < max_grid ? units : max_grid);
+  if (c.deep)
+    hipLaunchKernelGGL(cow_kernel<true>, g, dim3(kCThreads), 0, s, c, r, v, wait ? 1u : 0u);
+  else
+    hipLaunchKernelGGL(cow_kernel<false>, g, dim3(kCThreads), 0, s, c, r, v, wait ? 1u : 0u);
   return hipGetLastError();
 }
 

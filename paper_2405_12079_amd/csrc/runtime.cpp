@@ -143,6 +143,7 @@ struct phos_ctx {
   // while on-demand copies run (0: never), and 16 loads in flight per thread
   // for the on-demand / background copies of an image in host memory
   uint32_t rst_pause = 64, rst_deep_demand = 1, rst_deep_bg = 0;
+  uint32_t cow_deep = 1;  // copy-on-write copies keep 16 loads in flight per thread
   uint64_t drain_chunk = 16u << 20;  // image drain to host: chunk bytes (0: one copy)
   uint32_t drain_window = 2;        // ... and chunks in flight
   uint32_t finish_tiles = kFuseTiles;  // calls up to this many tiles order in one workgroup
@@ -319,6 +320,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);
   c->rst_deep_demand = env_u32("PHOS_RST_DEEP_DEMAND", 1);
+  c->cow_deep = env_u32("PHOS_COW_DEEP", 1);
   c->rst_deep_bg = env_u32("PHOS_RST_DEEP_BG", 0);
   phos_status st = PHOS_OK;
 #define CK(x)                  \
@@ -1136,6 +1138,7 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // earlier copy-on-write calls (one stream) have completed
   a.bg_exit = &k->slot->counters[6];
   a.skip_when_finished = k->cow_streams_many ? 0u : 1u;
+  a.deep = c->cow_deep ? 1u : 0u;
   if (k->stage) {
     a.stage = k->stage;
     a.stage_page = k->d_stage_page;

@@ -418,6 +418,47 @@ def test_precopy_final_rounds(env, vstream):
     assert np.array_equal(image.cpu().numpy(), res.snapshots[T2 - T1]), "image != snapshot at t2"
 
 
+@pytest.mark.parametrize("window", ["whole", "empty"])
+def test_precopy_final_degenerate(env, window):
+    """Degenerate final-page rounds.  "whole": one round after the window's
+    last launch (nothing upcoming) takes every dirty and victim page, and the
+    recopy at the re-quiesce then copies none.  "empty": a window with no
+    launch; the round copies nothing.  The image is the snapshot at t2
+    either way."""
+    phos, w, T = env.phos, env.world, env.T
+    launches = synth.config1_launches(w)
+    st = Stream(env, launches)
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    _run_plain(env, st, host, 0, T1)
+    t2 = T2 if window == "whole" else T1
+    res = oracle.run_stream(w, launches[T1:t2], env.base, lambda L: synth.records_host(env.hw, L),
+                            lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
+                            host, snap_before=(t2 - T1,), window=(0, t2 - T1), keep_violations=False)
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    ck = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, image, None, env.copy)
+    out, cnt = env.violations_buffers(N)
+    for j in range(T1, t2):
+        L = launches[j]
+        sp = env.spec(L)
+        r = st.records(j)
+        _validate(env, sp, r, out, cnt)
+        env.mutate(L, r.data_ptr(), N)
+        phos.phos_spec_release(env.ctx, sp)
+    phos.phos_ckpt_precopy_final(ck, [], 0, env.app)
+    phos.phos_ckpt_recopy(ck, env.app)
+    d = phos.phos_track_read(env.ctx, 0, w.n_pages)
+    v = phos.phos_track_read(env.ctx, 1, w.n_pages)
+    stats = phos.phos_ckpt_end(ck, env.app)
+    assert not d.any() and not v.any()
+    assert stats.recopy_pages == 0
+    inbuf = _buffer_pages(w).astype(bool)
+    assert stats.precopy_pages == int(((res.dirty.astype(bool) | res.victim.astype(bool))
+                                       & inbuf).sum())
+    if window == "whole":
+        assert stats.precopy_pages > 0
+    assert np.array_equal(image.cpu().numpy(), res.snapshots[t2 - T1]), "image != snapshot at t2"
+
+
 def test_both_protocols_open_together(env):
     """A CoW checkpoint (t1 image) and a recopy checkpoint (t2 image) over one window."""
     phos, w, T = env.phos, env.world, env.T

@@ -5,8 +5,12 @@
  * Paper map:
  *   Section 4.1  speculation from launch arguments, runtime validation
  *                -> phos_spec_register, phos_validate, phos_validate_batch
- *   Section 4.2  soft copy-on-write            -> phos_ckpt_begin / _cow / _end
- *   Section 4.3  soft recopy (dirty tracking)   -> PHOS_V_TRACK, phos_ckpt_recopy
+ *   Section 4.1  the validator fused into a kernel (twin) -> phos_twin_scale_add
+ *   Section 4.2  soft copy-on-write            -> phos_ckpt_begin / _cow / _end,
+ *                device staging for a host image -> phos_ckpt_staging
+ *   Section 4.3  soft recopy (dirty tracking)   -> PHOS_V_TRACK, phos_ckpt_recopy,
+ *                phos_ckpt_start (deferred background copy)
+ *   Sections 4.3, 7  iterative recopy           -> phos_ckpt_precopy, phos_ckpt_precopy_final
  *   Section 5    chunked device-to-host drain   -> phos_ckpt_end (host_image)
  *   Section 6    concurrent on-demand restore   -> phos_restore_begin / _on_demand / _end
  *   (no paper analog) batched persistent copy and a serving loop

@@ -40,10 +40,11 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
 KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 counter summary (profiles/<kernel>_<workload>_pmc.txt), or None
-    when there is none or the kernel source changed since it was taken."""
+def measured_traffic(kernel, workload, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch (or the summary's `key`) of `kernel` on `workload`
+    from the committed rocprofv3 counter summary
+    (profiles/<kernel>_<workload>_pmc.txt), or None when there is none or the
+    kernel source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
@@ -54,9 +55,9 @@ def measured_traffic(kernel, workload):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
-    if fields.get("kernels_hip_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernels_hip_sha256") != sha or key not in fields:
         return None
-    return int(float(fields["traffic_bytes_per_launch"]))
+    return int(float(fields[key]))
 
 
 def log(*a):
@@ -1487,9 +1488,12 @@ def run_cow(args):
         "data": "synthetic (seeded layout, access streams and contents)",
         "config": {"workload": "copy-on-write: training-step layout, 1000 launches x 1e6 accesses, "
                                "16 GiB device image, background deferred / beside"},
+        # traffic: HBM bytes of the copy-on-write kernels of one deferred loop
         "roofline": {"bound": "hbm", "kernel": "cow_kernel (background deferred)",
                      "achieved": d["cow_GBps_hbm"], "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(d["cow_GBps_hbm"] / 8000.0, 4), "traffic": None,
+                     "frac": round(d["cow_GBps_hbm"] / 8000.0, 4),
+                     "traffic": measured_traffic("cow_kernel", "copy_on_write",
+                                                 "traffic_bytes_per_loop"),
                      "algorithmic_bytes": 2 * d["cow_pages"] * page},
         "launches_without_checkpoint_ms": round(alone_ms, 3),
         "write_interval_pages": n_wpages,

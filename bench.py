@@ -956,17 +956,18 @@ def cpu_gather_baseline(seed, span, src_off, dst_off, lens, label):
 
 
 def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
-    """The oracle on a bounded sample of the step: validation + tracking of 300
-    launches and snapshots of 4 GiB of buffers, on one thread and on the
-    host's cores (T threads: the oracle's C calls release the GIL; launches
-    and buffers split across them); scaled to the step's work."""
+    """The oracle on a bounded sample of the step: validation + tracking of the
+    step's launches (up to 1000) and snapshots of 4 GiB of buffers, on one
+    thread and on the host's cores (T threads: the oracle's C calls release
+    the GIL; launches and buffers split across them); scaled to the step's
+    work (about 10 s of CPU time in all)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     import synth
     hw = synth.HostWorld(w, base)
     table = oracle.Table.from_world(w, base)
-    sample = launches[: min(300, len(launches))]
+    sample = launches[: min(1000, len(launches))]
     recs = [synth.records_host(hw, L) for L in sample]  # inputs: not timed
     npg = w.n_pages
     n_val = sum(r.shape[0] for r in recs)

@@ -155,6 +155,8 @@ typedef struct {
  *   PHOS_RST_PAUSE       restore: polls (about 0.5 us each) the background
  *                        holds back per batch while on-demand copies run [64];
  *                        0 lets them share the link
+ *   PHOS_RST_HOLD_MS     restore: that hold applies only this long after the
+ *                        background copy starts, 0: always [200]
  *   PHOS_RST_DEEP_DEMAND / PHOS_RST_DEEP_BG  restore from host memory: 16
  *                        loads in flight per thread in on-demand [1] /
  *                        background [0] copies

@@ -96,6 +96,7 @@ struct CopyArgs {
   uint32_t nt = 0;                       // non-temporal page copies
   uint32_t deep = 0;                     // copies keep 16 loads in flight per thread
   uint32_t pause_limit = 0;              // background: longest hold (polls) per batch
+  uint32_t hold_ticks = 0;               // ... only this long (GPU clock, 100 MHz) after it starts; 0: always
   uint32_t chunk_pages = 0;              // pages per image piece (with image_chunks)
   const unsigned long long *image_chunks = nullptr;  // image pieces (device table) or nullptr
   // Recopy background only: pages already marked in either page map are left

@@ -801,13 +801,17 @@ __global__ void __launch_bounds__(kBgThreads)
   if (claimer) bg_claim_batch(C, 0, batch, grab, s_p[0], s_ip[0], &s_n[0]);
   __syncthreads();
   uint32_t cur = 0, copied = 0;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
   for (uint64_t i = 0; bg_live(i, batch, grab, C.n_pages); ++i) {
     if (claimer) {
       // Section 6: on-demand copies go first: claim nothing new while a
       // launch's pages are moving (bounded: this is a policy, not a
       // correctness wait; the pages already claimed are still copied and
-      // published by the copying waves below, which do not wait for this)
-      if (C.demand) {
+      // published by the copying waves below, which do not wait for this).
+      // With hold_ticks the policy lasts that long after the start only:
+      // the first launches get the link, then the whole image streams.
+      if (C.demand &&
+          (C.hold_ticks == 0 || __builtin_amdgcn_s_memrealtime() - t_start < C.hold_ticks)) {
         uint32_t it = 0;
         while (__hip_atomic_load(C.demand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
                ++it < C.pause_limit)

@@ -143,6 +143,7 @@ struct phos_ctx {
   // while on-demand copies run (0: never), and 16 loads in flight per thread
   // for the on-demand / background copies of an image in host memory
   uint32_t rst_pause = 64, rst_deep_demand = 1, rst_deep_bg = 0;
+  uint32_t rst_hold_ms = 200;  // restore: hold only this long after the background starts (0: always)
   uint32_t cow_deep = 1;  // copy-on-write copies keep 16 loads in flight per thread
   uint64_t drain_chunk = 16u << 20;  // image drain to host: chunk bytes (0: one copy)
   uint32_t drain_window = 2;        // ... and chunks in flight
@@ -317,6 +318,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       kVQuantum, env_u32("PHOS_VTILE_MAX", 16 * kVQuantum) / kVQuantum * kVQuantum);
   c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 22);
   c->rst_pause = env_u32("PHOS_RST_PAUSE", 64);
+  c->rst_hold_ms = std::min<uint32_t>(env_u32("PHOS_RST_HOLD_MS", 200), 40000);
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);
   c->rst_deep_demand = env_u32("PHOS_RST_DEEP_DEMAND", 1);
@@ -1382,6 +1384,7 @@ static CopyArgs rst_args(phos_rst *r, unsigned long long *stat, bool deep = fals
   a.want_cap = r->want ? kWantCap : 0;
   a.demand = r->ctx->rst_pause ? &r->slot->counters[4] : nullptr;
   a.pause_limit = std::min(r->ctx->rst_pause, r->ctx->spin_limit);
+  a.hold_ticks = r->ctx->rst_hold_ms * 100000u;  // the clock runs at 100 MHz
   a.deep = deep && r->host_image ? 1u : 0u;
   return a;
 }

@@ -75,6 +75,9 @@ def lib():
         L.orc_snapshot.restype = U64
         L.orc_restore.argtypes = [P, U64, P, P, U32, P]
         L.orc_gather.argtypes = [P, P, P, P, P, U64]
+        L.orc_page_hash.argtypes = [P, U64, U64]
+        L.orc_page_hash.restype = U64
+        L.orc_hash_pages.argtypes = [P, U64, U64, U64, P]
         _lib = L
     return _lib
 
@@ -176,6 +179,23 @@ def gather(src: np.ndarray, dst: np.ndarray, src_off, dst_off, nbytes) -> None:
                      b.ctypes.data, s.shape[0])
 
 
+def page_hash(page: np.ndarray, index: int) -> int:
+    """64-bit fingerprint of one page's bytes at page index `index` (oracle.h)."""
+    page = np.ascontiguousarray(page, dtype=np.uint8)
+    return int(lib().orc_page_hash(page.ctypes.data, page.nbytes, index))
+
+
+def hash_pages(buf: np.ndarray, page_bytes: int, index0: int = 0) -> np.ndarray:
+    """Fingerprints of the whole pages of a contiguous host buffer, the first
+    numbered index0."""
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    n = buf.nbytes // page_bytes
+    out = np.empty(n, dtype=np.uint64)
+    if n:
+        lib().orc_hash_pages(buf.ctypes.data, page_bytes, n, index0, out.ctypes.data)
+    return out
+
+
 def page_set(pages: np.ndarray) -> np.ndarray:
     """Byte-per-page array -> sorted page indices."""
     return np.flatnonzero(pages).astype(np.uint64)
@@ -203,6 +223,8 @@ class StreamResult:
         self.victim: Optional[np.ndarray] = None
         self.cow_sets: List[np.ndarray] = []  # per launch in the CoW window
         self.fault_sets: List[np.ndarray] = []
+        self.hashes: Dict[int, np.ndarray] = {}  # run_stream_hashed: fingerprints of snapshots
+        self.last: Optional[np.ndarray] = None   # run_stream_hashed: last victim launch per page
 
 
 def run_stream(world, launches, pool_base: int, records_fn, apply_fn, pool: np.ndarray,
@@ -250,3 +272,316 @@ def run_stream(world, launches, pool_base: int, records_fn, apply_fn, pool: np.n
     if len(launches) in snap_before:
         res.snapshots[len(launches)] = snapshot(pool, pool_base, table)
     return res
+
+
+# --------------------------------------------------------------------------
+# Page sets of the recopy rounds (Sections 4.3 and 7)
+# --------------------------------------------------------------------------
+def buffer_pages(table: Table, pool_base: int, page_bytes: int, n_pages: int) -> np.ndarray:
+    """Byte per pool page: 1 iff some byte of the page belongs to an allocated
+    buffer.  Only those pages have a place in the image (Section 2.2: the
+    checkpointed state is the buffers), so only they are ever copied."""
+    out = np.zeros(n_pages, np.uint8)
+    for b, nb in zip(table.base.tolist(), table.bytes.tolist()):
+        if nb == 0 or b + nb <= pool_base:
+            continue
+        lo = max(b, pool_base) - pool_base
+        hi = b + nb - pool_base
+        out[lo // page_bytes:min((hi - 1) // page_bytes + 1, n_pages)] = 1
+    return out
+
+
+def write_pages(table: Table, arg_lists, pool_base: int, page_bytes: int,
+                n_pages: int) -> np.ndarray:
+    """Union over launches of the pages of their speculated write intervals:
+    what those launches may write without a violation (Section 4.1)."""
+    m = np.zeros(n_pages, np.uint8)
+    for args in arg_lists:
+        write_interval_pages(spec_build(table, args), pool_base, page_bytes, n_pages, m)
+    return m
+
+
+def track_launches(table: Table, n: int, item_fn, pool_base: int, page_bytes: int,
+                   n_pages: int, threads: int = 1):
+    """Write-set tracking (Section 4.3) of launches 0..n-1, item_fn(j) giving
+    launch j's (args, records).  Returns (dirty, victim, last): the OR of
+    every launch's dirty and victim pages, and per page the last launch j
+    with a failing write inside a buffer there (-1: none).  Launches are
+    tracked independently and combined by OR and max, which is what the
+    per-launch definition composes to; `threads` only splits the launches."""
+    import concurrent.futures as cf
+
+    def part(js):
+        d, v = np.zeros(n_pages, np.uint8), np.zeros(n_pages, np.uint8)
+        last = np.full(n_pages, -1, np.int64)
+        for j in js:
+            args, rec = item_fn(j)
+            vj = np.zeros(n_pages, np.uint8)
+            track(spec_build(table, args), rec, table, pool_base, page_bytes, n_pages, d, vj)
+            v |= vj
+            last[vj != 0] = j
+        return d, v, last
+
+    threads = max(1, min(threads, n)) if n else 1
+    parts = [list(range(n))[i::threads] for i in range(threads)]
+    dirty, victim = np.zeros(n_pages, np.uint8), np.zeros(n_pages, np.uint8)
+    last = np.full(n_pages, -1, np.int64)
+    with cf.ThreadPoolExecutor(threads) as ex:
+        for d, v, lp in ex.map(part, parts):
+            dirty |= d
+            victim |= v
+            last = np.maximum(last, lp)
+    return dirty, victim, last
+
+
+def precopy_rounds(dirty_per_launch: Sequence[np.ndarray], rounds: Sequence[int],
+                   inbuf: np.ndarray):
+    """Plain pre-copy rounds of a recopy checkpoint (Sections 4.3 and 7): a
+    round before launch r copies every page marked dirty so far and unmarks
+    it; later writes mark pages again.  dirty_per_launch[j]: launch j's dirty
+    pages.  Returns (the dirty map left for the final recopy, the number of
+    image pages the rounds copied)."""
+    cur = np.zeros_like(inbuf, dtype=np.uint8)
+    copied = 0
+    for j, d in enumerate(dirty_per_launch):
+        if j in rounds:
+            copied += int((cur & inbuf).astype(bool).sum())
+            cur[:] = 0
+        cur |= d
+    return cur, copied
+
+
+def final_rounds(dirty: np.ndarray, victim: np.ndarray, last: np.ndarray,
+                 rounds: Sequence[int], upcoming_pages, inbuf: np.ndarray):
+    """Final-page pre-copy rounds (Sections 4.3 and 7, with every launch of the
+    window validated up front).  Before launch r, a page is final when no
+    launch from r on may write it validly (outside upcoming_pages(r), the
+    write-interval pages of launches r, r+1, ...): the dirty pages and the
+    victim pages whose last failing write came from a launch before r
+    (last[p] < r) are copied and unmarked.  Returns the dirty and victim maps
+    left for the recopy at the re-quiesce and the number of image pages the
+    rounds copied (a page can be copied by several rounds)."""
+    dirty, victim, inbuf = dirty.astype(bool), victim.astype(bool), inbuf.astype(bool)
+    copied = 0
+    for r in rounds:
+        up = upcoming_pages(r).astype(bool)
+        fin_v = victim & (last >= 0) & (last < r)
+        listed = (dirty | fin_v) & ~up
+        copied += int((listed & inbuf).sum())
+        dirty &= ~listed
+        victim &= ~(fin_v & ~up)
+    return dirty, victim, copied
+
+
+def needed_pages(table: Table, args, rec: np.ndarray, pool_base: int, page_bytes: int,
+                 n_pages: int, prefetch: bool = False) -> np.ndarray:
+    """Section 6: the pages a launch needs present before it runs: those its
+    accesses touch inside buffers; with speculative prefetch, also every page
+    of its speculated intervals (read and write) that lies in a buffer."""
+    t = np.zeros(n_pages, np.uint8)
+    touched_pages(rec, table, pool_base, page_bytes, n_pages, t)
+    if prefetch:
+        iv = spec_build(table, args).copy()
+        iv["mode"] |= W  # every speculated interval, whatever its mode
+        s = np.zeros(n_pages, np.uint8)
+        write_interval_pages(iv, pool_base, page_bytes, n_pages, s)
+        t |= s & buffer_pages(table, pool_base, page_bytes, n_pages)
+    return t
+
+
+def recopy_pages(dirty: np.ndarray, victim: np.ndarray, inbuf: np.ndarray) -> int:
+    """Image pages the recopy at the re-quiesce copies: the dirty pages and the
+    victim pages (Section 4.3), those inside buffers."""
+    return int(((dirty.astype(bool) | victim.astype(bool)) & inbuf.astype(bool)).sum())
+
+
+# --------------------------------------------------------------------------
+# Full-size comparisons: fingerprints of images and pools, and the replay of
+# an application stream on a host pool
+# --------------------------------------------------------------------------
+def _pool_map(fn, items, threads):
+    import concurrent.futures as cf
+    if threads <= 1:
+        return [fn(x) for x in items]
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(fn, items))
+
+
+def image_hashes_from_pool(pool: np.ndarray, pool_base: int, table: Table, page_bytes: int,
+                           threads: int = 1) -> np.ndarray:
+    """Page fingerprints of the image a stop-the-world checkpoint of `pool`
+    writes (orc_snapshot's layout: buffers back to back in ascending base
+    order), in image page order, without building the image.  Buffers are
+    whole pages, so image page i is one pool page."""
+    n_img = int(table.bytes.sum()) // page_bytes
+    out = np.empty(n_img, np.uint64)
+    jobs, ip = [], 0
+    for b, nb in zip(table.base.tolist(), table.bytes.tolist()):
+        assert b % page_bytes == pool_base % page_bytes and nb % page_bytes == 0
+        jobs.append((b - pool_base, nb, ip))
+        ip += nb // page_bytes
+
+    def one(job):
+        off, nb, i0 = job
+        out[i0:i0 + nb // page_bytes] = hash_pages(pool[off:off + nb], page_bytes, i0)
+
+    _pool_map(one, jobs, threads)
+    return out
+
+
+def hash_chunks(read_fn, nbytes: int, page_bytes: int, chunk_bytes: int,
+                threads: int = 1) -> np.ndarray:
+    """Page fingerprints of nbytes of data read chunk by chunk: read_fn(off, n)
+    returns bytes [off, off + n) as a host array; page i is numbered i."""
+    assert nbytes % page_bytes == 0 and chunk_bytes % page_bytes == 0
+    out = np.empty(nbytes // page_bytes, np.uint64)
+    off = 0
+    while off < nbytes:
+        n = min(chunk_bytes, nbytes - off)
+        host = read_fn(off, n)
+        step = max(page_bytes, (n // max(1, threads)) // page_bytes * page_bytes)
+        parts = [(o, min(step, n - o)) for o in range(0, n, step)]
+
+        def one(part, host=host, base=off):
+            o, m = part
+            i0 = (base + o) // page_bytes
+            out[i0:i0 + m // page_bytes] = hash_pages(host[o:o + m], page_bytes, i0)
+
+        _pool_map(one, parts, threads)
+        off += n
+    return out
+
+
+def apply_stream(pool: np.ndarray, launches, records_fn, apply_fn, threads: int = 1,
+                 ahead: int = 32) -> None:
+    """Apply launches' writes to a host pool in launch order (the application,
+    not the method: each write stores a value fixed by the launch and the
+    address).  records_fn(L) is pure, so up to `ahead` launches' records are
+    drawn on `threads` host threads while earlier ones are applied."""
+    import concurrent.futures as cf
+    if threads <= 1:
+        for L in launches:
+            apply_fn(pool, L, records_fn(L))
+        return
+    with cf.ThreadPoolExecutor(threads) as ex:
+        futs = {}
+        nxt = 0
+        for j, L in enumerate(launches):
+            while nxt < len(launches) and nxt < j + ahead:
+                futs[nxt] = ex.submit(records_fn, launches[nxt])
+                nxt += 1
+            apply_fn(pool, L, futs.pop(j).result())
+
+
+def validate_launches(table: Table, pool_base: int, launches, records_fn, flags: int = V_READS | V_WRITES,
+                      threads: int = 1) -> List[np.ndarray]:
+    """Section 4.1 violations of every launch (list in launch order); launches
+    are independent, so `threads` only splits them."""
+    def one(L):
+        return validate(spec_build(table, L.arg_values(pool_base)), records_fn(L), table, L.k, flags)
+
+    return _pool_map(one, list(launches), threads)
+
+
+def run_stream_hashed(world, launches, pool_base: int, records_fn, apply_fn, pool: np.ndarray,
+                      hash_before: Sequence[int] = (), window: Optional[Tuple[int, int]] = None,
+                      flags: int = V_READS | V_WRITES, threads: int = 1,
+                      ahead: int = 16) -> StreamResult:
+    """run_stream for windows too large to snapshot twice on the host: the same
+    per-launch definitions (speculation, validation, tracking, then the
+    launch's writes, in launch order), with each launch's records drawn,
+    validated and tracked on host threads ahead of the in-order application
+    of the writes, and every snapshot replaced by its page fingerprints
+    (res.hashes[j], as image_hashes_from_pool).  res.last[p] is the last
+    launch position in the window with a failing write inside a buffer on
+    page p (-1: none)."""
+    import concurrent.futures as cf
+    table = Table.from_world(world, pool_base)
+    npg, page = world.n_pages, world.page_bytes
+    res = StreamResult()
+    if window is not None:
+        res.dirty = np.zeros(npg, np.uint8)
+        res.victim = np.zeros(npg, np.uint8)
+        res.last = np.full(npg, -1, np.int64)
+
+    def prep(j):
+        L = launches[j]
+        iv = spec_build(table, L.arg_values(pool_base))
+        rec = records_fn(L)
+        viol = validate(iv, rec, table, L.k, flags)
+        dv = None
+        if window is not None and window[0] <= j < window[1]:
+            d, v = np.zeros(npg, np.uint8), np.zeros(npg, np.uint8)
+            track(iv, rec, table, pool_base, page, npg, d, v)
+            dv = (np.flatnonzero(d), np.flatnonzero(v))
+        return iv, rec, viol, dv
+
+    with cf.ThreadPoolExecutor(max(1, threads)) as ex:
+        futs, nxt = {}, 0
+        for j, L in enumerate(launches):
+            while nxt < len(launches) and nxt < j + ahead:
+                futs[nxt] = ex.submit(prep, nxt)
+                nxt += 1
+            if j in hash_before:
+                res.hashes[j] = image_hashes_from_pool(pool, pool_base, table, page, threads)
+            iv, rec, viol, dv = futs.pop(j).result()
+            res.intervals.append(iv)
+            res.violations.append(viol)
+            if dv is not None:
+                res.dirty[dv[0]] = 1
+                res.victim[dv[1]] = 1
+                res.last[dv[1]] = j
+            apply_fn(pool, L, rec)
+    if len(launches) in hash_before:
+        res.hashes[len(launches)] = image_hashes_from_pool(pool, pool_base, table, page, threads)
+    return res
+
+
+def image_hashes_from_reader(read_fn, pool_base: int, table: Table, page_bytes: int,
+                             chunk_bytes: int = 1 << 30, threads: int = 1) -> np.ndarray:
+    """As image_hashes_from_pool, for a pool read piece by piece: read_fn(off,
+    n) returns pool bytes [off, off + n) (pool-relative) as a host array."""
+    n_img = int(table.bytes.sum()) // page_bytes
+    out = np.empty(n_img, np.uint64)
+    ip = 0
+    for b, nb in zip(table.base.tolist(), table.bytes.tolist()):
+        assert nb % page_bytes == 0
+        off = b - pool_base
+        for o in range(0, nb, chunk_bytes):
+            n = min(chunk_bytes, nb - o)
+            host = read_fn(off + o, n)
+            i0 = ip + o // page_bytes
+            step = max(page_bytes, (n // max(1, threads)) // page_bytes * page_bytes)
+
+            def one(p, host=host, i0=i0, n=n):
+                m = min(step, n - p)
+                out[i0 + p // page_bytes:i0 + (p + m) // page_bytes] = hash_pages(
+                    host[p:p + m], page_bytes, i0 + p // page_bytes)
+
+            _pool_map(one, range(0, n, step), threads)
+        ip += nb // page_bytes
+    return out
+
+
+def gather_hashes(src_fn, src_off, dst_off, nbytes, page_bytes: int, n_dst_pages: int,
+                  threads: int = 1, piece_bytes: int = 64 << 20) -> np.ndarray:
+    """Page fingerprints of the destination of orc_gather's segment copy
+    (dst[dst_off[i] ..) = src[src_off[i] ..), bytes[i] each) without building
+    it: src_fn(off, n) returns source bytes [off, off + n) as a host array.
+    Segments are whole pages at page-aligned destinations; destination pages
+    no segment writes keep the fingerprint 0."""
+    out = np.zeros(n_dst_pages, np.uint64)
+    jobs = []
+    for s, d, n in zip(np.asarray(src_off).tolist(), np.asarray(dst_off).tolist(),
+                       np.asarray(nbytes).tolist()):
+        assert d % page_bytes == 0 and n % page_bytes == 0
+        for o in range(0, n, piece_bytes):
+            jobs.append((s + o, d + o, min(piece_bytes, n - o)))
+
+    def one(job):
+        s, d, n = job
+        out[d // page_bytes:(d + n) // page_bytes] = hash_pages(src_fn(s, n), page_bytes,
+                                                                d // page_bytes)
+
+    _pool_map(one, jobs, threads)
+    return out

@@ -201,3 +201,27 @@ void orc_gather(const uint8_t *src, uint8_t *dst, const uint64_t *src_off,
   uint64_t i;
   for (i = 0; i < nseg; ++i) memcpy(dst + dst_off[i], src + src_off[i], bytes[i]);
 }
+
+#define ORC_GOLDEN 0x9E3779B97F4A7C15ull
+
+static uint64_t orc_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t orc_page_hash(const uint8_t *page, uint64_t page_bytes, uint64_t index) {
+  uint64_t h = orc_mix(ORC_GOLDEN * (index + 1)), off;
+  for (off = 0; off + 8 <= page_bytes; off += 8) {
+    uint64_t w;
+    memcpy(&w, page + off, 8);
+    h = orc_mix(h ^ w) + ORC_GOLDEN;
+  }
+  return h;
+}
+
+void orc_hash_pages(const uint8_t *buf, uint64_t page_bytes, uint64_t npages, uint64_t index0,
+                    uint64_t *out) {
+  uint64_t i;
+  for (i = 0; i < npages; ++i) out[i] = orc_page_hash(buf + i * page_bytes, page_bytes, index0 + i);
+}

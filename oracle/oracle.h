@@ -88,4 +88,16 @@ void orc_restore(uint8_t *pool, uint64_t pool_base, const uint64_t *abase,
 void orc_gather(const uint8_t *src, uint8_t *dst, const uint64_t *src_off,
                 const uint64_t *dst_off, const uint64_t *bytes, uint64_t nseg);
 
+/* Page fingerprints for comparing images too large to hold twice: a 64-bit
+ * hash of one page's bytes, keyed by its page index (so equal content at two
+ * different places hashes differently).  The splitmix64 output function
+ * (Steele, Lea and Flood, OOPSLA 2014) is folded over the page's 8-byte
+ * little-endian words in order: h <- mix(h ^ word) + golden, starting from
+ * mix(golden * (index + 1)).  page_bytes is a multiple of 8. */
+uint64_t orc_page_hash(const uint8_t *page, uint64_t page_bytes, uint64_t index);
+
+/* out[i] = orc_page_hash(buf + i * page_bytes, page_bytes, index0 + i), i < npages. */
+void orc_hash_pages(const uint8_t *buf, uint64_t page_bytes, uint64_t npages, uint64_t index0,
+                    uint64_t *out);
+
 #endif

@@ -557,6 +557,18 @@ __device__ __forceinline__ void copy_page(const CopyArgs &C, uint32_t p, uint32_
   block_copy16(src, dst, pb >> 4, C.nt != 0, tid, nthreads, DEEP);
 }
 
+// A bounded wait gives up after C.spin_limit polls, or as soon as any other
+// wait of the same context has given up (the error word is read every 64
+// polls): one lost publication then ends every waiter promptly, and the call
+// reports PHOS_E_TIMEOUT, instead of each waiter spending its whole budget.
+__device__ __forceinline__ bool wait_expired(const CopyArgs &C, uint32_t it) {
+  if (it > C.spin_limit || ((it & 63u) == 0 && ld_relaxed(C.err) != 0u)) {
+    atomicOr(C.err, 1u);
+    return true;
+  }
+  return false;
+}
+
 // Block-collective: every thread offers at most one candidate page.  Pages
 // still free are claimed (one winner per page across the whole GPU), copied
 // by this block, then published as done; with WAIT, a thread whose page is
@@ -657,10 +669,7 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
     uint32_t it = 0;
     while (ld_acquire(&C.state[cand]) != kDone) {
       __builtin_amdgcn_s_sleep(8);
-      if (++it > C.spin_limit) {
-        atomicOr(C.err, 1u);
-        break;
-      }
+      if (wait_expired(C, ++it)) break;
     }
   }
   __syncthreads();
@@ -821,22 +830,32 @@ __global__ void __launch_bounds__(kBgThreads)
     } else {
       const uint32_t n = s_n[cur];
       for (uint32_t m = 0; m < n; ++m) copy_page<DEEP>(C, s_p[cur][m], s_ip[cur][m], t, kBgCopyThreads);
-      // towards the pool the writes must reach memory before other XCDs
-      // read the page
-      if (!C.to_image && n) __threadfence();
-      // The last copying wave to get here publishes the batch.  Towards the
-      // image no store needs to land before "done": the host reads the
-      // image after the kernel, and a copy-on-write waiter only needs this
-      // block's reads of the pool to have returned, which every wave's
-      // stores already depended on before its arrival.
+      // Stores that must land before "done":
+      //  - towards the pool (restore): other XCDs read the page right after;
+      //  - into a recopy image (skip_dirty set): a pre-copy round on the
+      //    application's stream may overwrite a page this copy published,
+      //    from another XCD; if this copy's stores could still sit in this
+      //    XCD's L2, their write-back could land after the round's fresh
+      //    page and leave a stale one in the image.
+      // Each wave makes its stores visible at device scope before it
+      // arrives, and the publisher releases "done".  Into a copy-on-write
+      // image no store needs to land first: the host reads the image after
+      // the kernel, nothing else writes a page this copy claimed, and a
+      // copy-on-write waiter only needs this block's reads of the pool to
+      // have returned, which every wave's stores depended on before it
+      // arrived.
+      const bool ordered = !C.to_image || C.skip_dirty != nullptr;
+      if (ordered && n) __threadfence();
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       uint32_t order = 0;
       if ((t & 63u) == 0) order = atomicAdd(&s_arrive, 1u);
       order = rfl(order);
       if (order == kBgCopyThreads / 64 - 1) {
-        for (uint32_t m = t & 63u; m < n; m += 64)
-          __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t m = t & 63u; m < n; m += 64) {
+          if (ordered) st_release(&C.state[s_p[cur][m]], kDone);
+          else __hip_atomic_store(&C.state[s_p[cur][m]], kDone, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+        }
         if ((t & 63u) == 0) s_arrive = 0;
       }
       copied += n;
@@ -901,10 +920,7 @@ __global__ void __launch_bounds__(kBgCopyThreads)
         uint32_t it = 0;
         while (ld_acquire(&C.state[p]) != kDone) {
           __builtin_amdgcn_s_sleep(8);
-          if (++it > C.spin_limit) {
-            atomicOr(C.err, 1u);
-            break;
-          }
+          if (wait_expired(C, ++it)) break;
         }
       }
       s_own = own;

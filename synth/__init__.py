@@ -466,6 +466,23 @@ def content_host(seed: int, byte0: int, nbytes: int) -> np.ndarray:
     return out
 
 
+def content_host_parallel(seed: int, byte0: int, nbytes: int, threads: int = 16,
+                          out: Optional[np.ndarray] = None) -> np.ndarray:
+    """content_host in slices on host threads (the C generator releases the GIL)."""
+    import concurrent.futures as cf
+    out = np.empty(nbytes, dtype=np.uint8) if out is None else out
+    step = max(4, (nbytes // max(1, threads) + 3) // 4 * 4)
+    L = host_lib()
+
+    def one(o):
+        n = min(step, nbytes - o)
+        L.synth_content_host(seed, byte0 + o, n, out[o:o + n].ctypes.data)
+
+    with cf.ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(one, range(0, nbytes, step)))
+    return out
+
+
 def apply_writes_host(pool: np.ndarray, pool_base: int, seed: int, k: int, rec: np.ndarray):
     rec = np.ascontiguousarray(rec, dtype=np.uint64)
     host_lib().synth_apply_writes_host(pool.ctypes.data, pool_base, pool.nbytes, seed, k,

@@ -80,21 +80,3 @@ class Env:
 def bits_to_pages(words: np.ndarray, n_pages: int) -> np.ndarray:
     b = np.unpackbits(words.view(np.uint8), bitorder="little")[:n_pages]
     return b.astype(np.uint8)
-
-
-def final_rounds_expected(dirty, victim, last, rounds, upcoming_pages, inbuf):
-    """The oracle's account of final-page rounds: before launch r, the dirty
-    pages and the victim pages whose last failing write came from a launch
-    before r, outside the write pages of the launches from r on, are copied
-    and unmarked.  Returns the dirty and victim maps left and the pages the
-    rounds copied (a page can be copied by several rounds)."""
-    dirty, victim, inbuf = dirty.astype(bool), victim.astype(bool), inbuf.astype(bool)
-    pre = 0
-    for r in rounds:
-        up = upcoming_pages(r).astype(bool)
-        fin_v = victim & (last >= 0) & (last < r)
-        listed = (dirty | fin_v) & ~up
-        pre += int((listed & inbuf).sum())
-        dirty &= ~listed
-        victim &= ~(fin_v & ~up)
-    return dirty, victim, pre

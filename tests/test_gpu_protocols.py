@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_harness import Env, bits_to_pages, final_rounds_expected
+from tests.gpu_harness import Env, bits_to_pages
 
 pytestmark = pytest.mark.gpu
 N = 1_000_000
@@ -32,11 +32,9 @@ def env():
     e.close()
 
 
-def _buffer_pages(w):
-    m = np.zeros(w.n_pages, np.uint8)
-    for o, b in zip(w.alloc_off, w.alloc_bytes):
-        m[int(o) // w.page_bytes:(int(o) + int(b)) // w.page_bytes] = 1
-    return m
+def _buffer_pages(env):
+    w = env.world
+    return oracle.buffer_pages(env.table, env.base, w.page_bytes, w.n_pages)
 
 
 class Stream:
@@ -243,15 +241,14 @@ def test_staging_rejects_bad_use(env):
 
 
 def _tracked(env, launches, j0, j1):
-    """The oracle's dirty and victim pages of launches j0..j1-1."""
+    """The oracle's dirty and victim pages of launches j0..j1-1, and per page
+    the last launch j with a failing write inside a buffer there (-1: none)."""
     w = env.world
-    d = np.zeros(w.n_pages, np.uint8)
-    v = np.zeros(w.n_pages, np.uint8)
-    for L in launches[j0:j1]:
-        iv = oracle.spec_build(env.table, L.arg_values(env.base))
-        oracle.track(iv, synth.records_host(env.hw, L), env.table, env.base, w.page_bytes,
-                     w.n_pages, d, v)
-    return d, v
+    d, v, last = oracle.track_launches(
+        env.table, j1 - j0,
+        lambda i: (launches[j0 + i].arg_values(env.base), synth.records_host(env.hw, launches[j0 + i])),
+        env.base, w.page_bytes, w.n_pages, threads=4)
+    return d, v, np.where(last >= 0, last + j0, -1)
 
 
 @pytest.mark.parametrize("mode", ["plain", "drain", "deferred", "implicit", "precopy"])
@@ -292,9 +289,10 @@ def test_soft_recopy_config1(env, mode):
         assert e.value.status == phos.E_STATE
     d = phos.phos_track_read(env.ctx, 0, w.n_pages)
     v = phos.phos_track_read(env.ctx, 1, w.n_pages)
-    dirty_left = res.dirty
-    if rounds:  # the final recopy sees only the marks made after the last round
-        dirty_left = _tracked(env, launches, rounds[-1], T2)[0]
+    # the final recopy sees only the marks made after the last round
+    per_launch = [_tracked(env, launches, j, j + 1)[0] for j in range(T1, T2)] if rounds else []
+    dirty_left, pre = (oracle.precopy_rounds(per_launch, [r - T1 for r in rounds], _buffer_pages(env))
+                       if rounds else (res.dirty, 0))
     assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left, w.n_pages))
     assert np.array_equal(v, oracle.pages_to_bitmap(res.victim, w.n_pages))
     stats = phos.phos_ckpt_end(ck, env.app)
@@ -302,10 +300,7 @@ def test_soft_recopy_config1(env, mode):
     assert np.array_equal(image.cpu().numpy(), want), "recopy image != snapshot at t2"
     if drain:
         assert np.array_equal(himg.numpy(), want), "drained host image differs"
-    rset = (dirty_left | res.victim) & _buffer_pages(w)
-    assert stats.recopy_pages == int(rset.sum())
-    pre = sum(int((_tracked(env, launches, a, b)[0] & _buffer_pages(w)).sum())
-              for a, b in zip([T1] + rounds[:-1], rounds))
+    assert stats.recopy_pages == oracle.recopy_pages(dirty_left, res.victim, _buffer_pages(env))
     assert stats.precopy_pages == pre
     n_img_pages = env.image_bytes // w.page_bytes
     if mode == "deferred":
@@ -315,38 +310,6 @@ def test_soft_recopy_config1(env, mode):
     # launches after t2 leave the image unchanged
     _run_plain(env, st, host, T2, T2 + 5)
     assert np.array_equal(image.cpu().numpy(), want)
-
-
-def _write_pages(env, launches):
-    """Pool pages overlapping any write interval of the launches' specs, as
-    the oracle builds them (Section 4.1)."""
-    w = env.world
-    m = np.zeros(w.n_pages, np.uint8)
-    for L in launches:
-        for iv in oracle.spec_build(env.table, L.arg_values(env.base)):
-            if not int(iv["mode"]) & 2:
-                continue
-            lo = max(int(iv["lo"]), env.base) - env.base
-            hi = min(int(iv["hi"]), env.base + w.pool_bytes) - env.base
-            if hi > lo:
-                m[lo // w.page_bytes:(hi - 1) // w.page_bytes + 1] = 1
-    return m
-
-
-def _victim_last(env, launches, j0, j1):
-    """Per pool page: the last launch j in [j0, j1) with a failing write
-    inside a buffer there (-1: none), from the oracle's tracking of each
-    launch on its own."""
-    w = env.world
-    last = np.full(w.n_pages, -1, np.int64)
-    for j in range(j0, j1):
-        L = launches[j]
-        d, v = np.zeros(w.n_pages, np.uint8), np.zeros(w.n_pages, np.uint8)
-        oracle.track(oracle.spec_build(env.table, L.arg_values(env.base)),
-                     synth.records_host(env.hw, L), env.table, env.base, w.page_bytes,
-                     w.n_pages, d, v)
-        last[v != 0] = j
-    return last
 
 
 @pytest.mark.parametrize("vstream", ["same", "other"])
@@ -370,7 +333,7 @@ def test_precopy_final_rounds(env, vstream):
     res = oracle.run_stream(w, launches[T1:T2], env.base, lambda L: synth.records_host(env.hw, L),
                             lambda p, L, rec: synth.apply_writes_host(p, env.base, w.seed, L.k, rec),
                             host, snap_before=(T2 - T1,), window=(0, T2 - T1), keep_violations=False)
-    last = _victim_last(env, launches, T1, T2)
+    last = _tracked(env, launches, T1, T2)[2]
     T.cuda.synchronize()
     groups = {g: env.records(launches[g * 20:(g + 1) * 20], N) for g in range(T1 // 20, T2 // 20)}
     T.cuda.synchronize()
@@ -404,17 +367,19 @@ def test_precopy_final_rounds(env, vstream):
     T.cuda.synchronize()
     for j in range(T1, T2):
         phos.phos_spec_release(env.ctx, specs[j])
-    inbuf = _buffer_pages(w)
+    inbuf = _buffer_pages(env)
     if vstream == "other":
         last[:] = -1  # no victim page is known to be final
-    dirty_left, victim_left, pre = final_rounds_expected(
-        res.dirty, res.victim, last, rounds, lambda r: _write_pages(env, launches[r:T2]), inbuf)
+    dirty_left, victim_left, pre = oracle.final_rounds(
+        res.dirty, res.victim, last, rounds,
+        lambda r: oracle.write_pages(env.table, [L.arg_values(env.base) for L in launches[r:T2]],
+                                     env.base, w.page_bytes, w.n_pages), inbuf)
     assert np.array_equal(d, oracle.pages_to_bitmap(dirty_left.astype(np.uint8), w.n_pages))
     assert np.array_equal(v, oracle.pages_to_bitmap(victim_left.astype(np.uint8), w.n_pages))
     if vstream == "same":  # victims went early too
         assert int(victim_left.sum()) < int(res.victim.astype(bool).sum())
     assert stats.precopy_pages == pre > 0
-    assert stats.recopy_pages == int(((dirty_left | victim_left) & inbuf.astype(bool)).sum())
+    assert stats.recopy_pages == oracle.recopy_pages(dirty_left, victim_left, inbuf)
     assert np.array_equal(image.cpu().numpy(), res.snapshots[T2 - T1]), "image != snapshot at t2"
 
 
@@ -451,9 +416,7 @@ def test_precopy_final_degenerate(env, window):
     stats = phos.phos_ckpt_end(ck, env.app)
     assert not d.any() and not v.any()
     assert stats.recopy_pages == 0
-    inbuf = _buffer_pages(w).astype(bool)
-    assert stats.precopy_pages == int(((res.dirty.astype(bool) | res.victim.astype(bool))
-                                       & inbuf).sum())
+    assert stats.precopy_pages == oracle.recopy_pages(res.dirty, res.victim, _buffer_pages(env))
     if window == "whole":
         assert stats.precopy_pages > 0
     assert np.array_equal(image.cpu().numpy(), res.snapshots[t2 - T1]), "image != snapshot at t2"
@@ -559,18 +522,8 @@ def test_concurrent_restore_config1(env, mode):
         phos.phos_restore_on_demand(rs, s, r, N, env.app, faulted)
         env.mutate(L, r.data_ptr(), N)
         rec_h = synth.records_host(env.hw, L)
-        t = np.zeros(w.n_pages, np.uint8)
-        oracle.touched_pages(rec_h, env.table, env.base, w.page_bytes, w.n_pages, t)
-        if mode == "prefetch":
-            oracle.write_interval_pages(oracle.spec_build(env.table, L.arg_values(env.base)),
-                                        env.base, w.page_bytes, w.n_pages, t)
-            iv = oracle.spec_build(env.table, L.arg_values(env.base))
-            for x in iv:  # read intervals too
-                p0 = (int(x["lo"]) - env.base) // w.page_bytes
-                p1 = (int(x["hi"]) - 1 - env.base) // w.page_bytes
-                t[p0:p1 + 1] = 1
-            t &= _buffer_pages(w)
-        present |= t
+        present |= oracle.needed_pages(env.table, L.arg_values(env.base), rec_h, env.base,
+                                       w.page_bytes, w.n_pages, prefetch=mode == "prefetch")
         if mode in ("deferred", "prefetch") and j % 5 == 0:
             env.app.synchronize()
             got = bits_to_pages(phos.phos_restore_present(rs, w.n_pages), w.n_pages)
@@ -582,7 +535,7 @@ def test_concurrent_restore_config1(env, mode):
     stats = phos.phos_restore_end(rs, env.app)
     assert stats.dma_pages == dma_want
     assert stats.bg_pages + stats.demand_pages + stats.dma_pages == env.image_bytes // w.page_bytes
-    inbuf = np.repeat(_buffer_pages(w).astype(bool), w.page_bytes)
+    inbuf = np.repeat(_buffer_pages(env).astype(bool), w.page_bytes)
     got = env.pool_host()
     assert np.array_equal(got[inbuf], host[inbuf]), "restored pool + launches != oracle"
 

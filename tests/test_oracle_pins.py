@@ -311,3 +311,392 @@ def test_restore_sets_disjoint_and_cover_touched_pages():
         present |= f
         union |= t
     assert np.array_equal(present, union)
+
+
+# ------------------------------------------- page sets: brute-force pins
+# A tiny pool [0, 512) with buffers [64, 128), [192, 320), [384, 448) and gaps
+# between them; page sizes from one word to the whole pool.
+TINY_BUFS = [(64, 64), (192, 128), (384, 64)]
+TINY_POOL = 512
+TINY_PAGES = (8, 16, 32, 64, 128, 512)
+
+
+def _allocated_bytes(bufs):
+    s = set()
+    for b, n in bufs:
+        s |= set(range(b, b + n))
+    return s
+
+
+def test_touched_pages_brute_force_tiny_pool():
+    """Section 6: a launch touches the pages holding its accesses that lie
+    inside allocated buffers.  Every 8-aligned address (and a few outside the
+    pool) x read/write x page size, alone and all together, against a set
+    built by enumerating the buffers' bytes."""
+    table = oracle.Table([b for b, _ in TINY_BUFS], [n for _, n in TINY_BUFS])
+    alloc = _allocated_bytes(TINY_BUFS)
+    addrs = list(range(0, TINY_POOL, 8)) + [TINY_POOL, TINY_POOL + 64]
+    for page in TINY_PAGES:
+        npg = TINY_POOL // page
+        for a in addrs:
+            for w in (0, 1):
+                got = np.zeros(npg, np.uint8)
+                oracle.touched_pages(np.array([a | w], np.uint64), table, 0, page, npg, got)
+                want = {a // page} if a in alloc else set()
+                assert set(np.flatnonzero(got).tolist()) == want, (page, a, w)
+        rec = np.array([a | (i & 1) for i, a in enumerate(addrs)], np.uint64)
+        got = np.zeros(npg, np.uint8)
+        oracle.touched_pages(rec, table, 0, page, npg, got)
+        want = {a // page for a in addrs if a in alloc}
+        assert set(np.flatnonzero(got).tolist()) == want, page
+    # a pool that starts above address 0: pages count from its base
+    got = np.zeros(8, np.uint8)
+    table2 = oracle.Table([1024 + 64], [64])
+    oracle.touched_pages(np.array([1024 + 64, 1024 + 120, 1024 + 128, 8], np.uint64), table2,
+                         1024, 64, 8, got)
+    assert np.flatnonzero(got).tolist() == [1]
+
+
+def test_write_interval_pages_brute_force():
+    """The pages a launch may write (Section 4.2's copy-before-write set):
+    the pages overlapping its intervals that hold the W mode, clipped to the
+    pool.  Every interval of 8-aligned bounds in a 256-byte pool x mode
+    {R, W, R|W} x page size, against an enumeration of the interval's
+    bytes; then mixed sets of read and write intervals."""
+    pool = 256
+    for page in (8, 16, 64, 256):
+        npg = pool // page
+        for lo in range(0, pool, 8):
+            for hi in range(lo + 8, pool + 16, 8):
+                for mode in (1, 2, 3):
+                    iv = np.zeros(1, dtype=oracle.INTERVAL_DTYPE)
+                    iv[0] = (lo, hi, mode, 0)
+                    got = np.zeros(npg, np.uint8)
+                    oracle.write_interval_pages(iv, 0, page, npg, got)
+                    want = {x // page for x in range(lo, min(hi, pool))} if mode & 2 else set()
+                    assert set(np.flatnonzero(got).tolist()) == want, (page, lo, hi, mode)
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        k = int(rng.integers(1, 6))
+        parts = []
+        for _ in range(k):
+            lo = int(rng.integers(0, 60)) * 8
+            hi = lo + 8 * int(rng.integers(1, 20))
+            parts.append((lo, hi, int(rng.integers(1, 4))))
+        iv = np.zeros(k, dtype=oracle.INTERVAL_DTYPE)
+        for j, p in enumerate(parts):
+            iv[j] = (*p, 0)
+        for page in (8, 32, 128):
+            npg = 512 // page
+            got = np.zeros(npg, np.uint8)
+            oracle.write_interval_pages(iv, 0, page, npg, got)
+            want = set()
+            for lo, hi, m in parts:
+                if m & 2:
+                    want |= {x // page for x in range(lo, min(hi, 512))}
+            assert set(np.flatnonzero(got).tolist()) == want
+
+
+def test_needed_pages_brute_force():
+    """Section 6: touched pages inside buffers, plus with prefetch every page
+    of the speculated intervals lying in a buffer; against enumeration."""
+    table = oracle.Table([b for b, _ in TINY_BUFS], [n for _, n in TINY_BUFS])
+    alloc = _allocated_bytes(TINY_BUFS)
+    rec = np.array([8 | 1, 72, 136 | 1, 200, 400 | 1, 456], np.uint64)
+    for page in TINY_PAGES:
+        npg = TINY_POOL // page
+        for args in ([], [(oracle.ARG_PTR_CONST, 0, 200, 0)], [(oracle.ARG_PTR_MUT, 0, 64, 0)],
+                     [(oracle.ARG_RANGE, oracle.R, 120, 96)],
+                     [(oracle.ARG_PTR_CONST, 0, 400, 0), (oracle.ARG_RANGE, oracle.W, 0, 512)]):
+            touched = {int(a) // page for a in (rec & ~np.uint64(7)).tolist() if int(a) in alloc}
+            spec_bytes = set()
+            for x in oracle.spec_build(table, args):
+                spec_bytes |= set(range(int(x["lo"]), int(x["hi"])))
+            pre = {x // page for x in spec_bytes & alloc}
+            for prefetch, want in ((False, touched), (True, touched | pre)):
+                got = oracle.needed_pages(table, args, rec, 0, page, npg, prefetch)
+                assert set(np.flatnonzero(got).tolist()) == want, (page, args, prefetch)
+
+
+def test_buffer_pages_brute_force():
+    table = oracle.Table([b for b, _ in TINY_BUFS], [n for _, n in TINY_BUFS])
+    alloc = _allocated_bytes(TINY_BUFS)
+    for page in TINY_PAGES:
+        npg = TINY_POOL // page
+        got = oracle.buffer_pages(table, 0, page, npg)
+        want = {x // page for x in alloc}
+        assert set(np.flatnonzero(got).tolist()) == want, page
+
+
+# --------------------------------- copy-on-write sets: a hand-built stream
+# Pool of 16 pages of 64 bytes at HAND_BASE: buffer A = pages 0-2, gap page 3,
+# B = pages 4-7, gap pages 8-9, C = pages 10-11, free pages 12-15.
+HAND_BASE = 0x10000
+HAND_PAGE = 64
+
+
+def _hand_world():
+    return synth.World(seed=7, pool_bytes=16 * HAND_PAGE, page_bytes=HAND_PAGE,
+                       alloc_off=np.array([0, 4 * HAND_PAGE, 10 * HAND_PAGE], np.uint64),
+                       alloc_bytes=np.array([3 * HAND_PAGE, 4 * HAND_PAGE, 2 * HAND_PAGE],
+                                            np.uint64), name="hand")
+
+
+def _hand_stream():
+    """Three launches (buffer index, mutable?) and their accesses (page, offset, write?)."""
+    A, B, C = 0, 1, 2
+    named = {0: [(A, 1), (B, 0)], 1: [(B, 1), (C, 0)], 2: [(A, 1), (C, 1)]}
+    acc = {
+        # valid write A/p1; write to read-only B/p5 (victim); write to gap p3;
+        # read of unnamed C/p10 (a violation: its record names buffer C, but a
+    # read marks no victim page)
+        0: [(1, 8, 1), (5, 16, 1), (3, 0, 1), (10, 24, 0)],
+        # valid write B/p6; write to read-only C/p11 (victim); write to
+        # unnamed A/p0 (victim, copied already)
+        1: [(6, 0, 1), (11, 8, 1), (0, 32, 1)],
+        # valid write C/p10; write to the free p13; write to unnamed B/p7
+        2: [(10, 40, 1), (13, 0, 1), (7, 56, 1)],
+    }
+    w = _hand_world()
+    launches = [synth.launch_custom(w, k, named[k], len(acc[k])) for k in range(3)]
+    recs = {k: np.array([(HAND_BASE + p * HAND_PAGE + o) | wr for p, o, wr in acc[k]], np.uint64)
+            for k in range(3)}
+    return w, launches, recs
+
+
+def _hand_apply(pool, L, rec):
+    """The hand stream's application: a write stores 8 bytes of value k + 1."""
+    for r in rec.tolist():
+        if r & 1:
+            off = (r & ~7) - HAND_BASE
+            pool[off:off + 8] = L.k + 1
+
+
+def test_cow_sets_hand_built_three_launches():
+    """Section 4.2 with the background copy paused: before launch k, copy the
+    pages of its write intervals and the victim pages of its violating writes
+    that no earlier launch of the window copied.  Sets worked out by hand:
+    launch 0 writes A (pages 0-2) and hits read-only B on page 5; launch 1
+    writes B (4-7) and hits C on 11 and A on 0; launch 2 writes A and C
+    (10-11) and hits B on 7."""
+    w, launches, recs = _hand_stream()
+    pool = np.zeros(w.pool_bytes, np.uint8)
+    res = oracle.run_stream(w, launches, HAND_BASE, lambda L: recs[L.k], _hand_apply, pool,
+                            snap_before=(0, 3), window=(0, 3), cow_window=(0, 3))
+    assert [s.tolist() for s in res.cow_sets] == [[0, 1, 2, 5], [4, 6, 7, 11], [10]]
+    # Section 4.3 on the same window: dirty = valid-write pages, victim =
+    # pages of failing writes inside buffers (gap and free pages excluded)
+    assert np.flatnonzero(res.dirty).tolist() == [1, 6, 10]
+    assert np.flatnonzero(res.victim).tolist() == [0, 5, 7, 11]
+    # the violations, in order, with their reasons and victims
+    v = [[(int(x["index"]), int(x["reason"]), int(x["victim"])) for x in vk]
+         for vk in res.violations]
+    assert v == [[(1, 2, 1), (2, 1, -1), (3, 1, 2)], [(1, 2, 2), (2, 1, 0)],
+                 [(1, 1, -1), (2, 1, 1)]]
+    # images: t1 all zero; t2 holds each write's value (gaps excluded)
+    assert not res.snapshots[0].any()
+    img = res.snapshots[3].reshape(-1, HAND_PAGE)  # image pages: A 0-2, B 4-7, C 10-11
+    want = np.zeros_like(img)
+    want[1, 8:16] = 1    # A p1 (image page 1) by launch 0
+    want[0, 32:40] = 2   # A p0 (image page 0) by launch 1
+    want[4, 16:24] = 1   # B p5 (image page 4) by launch 0
+    want[5, 0:8] = 2     # B p6 (image page 5) by launch 1
+    want[6, 56:64] = 3   # B p7 (image page 6) by launch 2
+    want[7, 40:48] = 3   # C p10 (image page 7) by launch 2
+    want[8, 8:16] = 2    # C p11 (image page 8) by launch 1
+    assert np.array_equal(img, want)
+
+
+def test_precopy_rounds_hand_built():
+    """Plain pre-copy rounds (Sections 4.3 and 7): a round copies and unmarks
+    everything marked so far.  Five launches' dirty pages by hand; rounds
+    before launches 2 and 4; page 5 lies outside every buffer."""
+    n = 6
+    inbuf = np.array([1, 1, 1, 1, 1, 0], np.uint8)
+
+    def d(*p):
+        a = np.zeros(n, np.uint8)
+        a[list(p)] = 1
+        return a
+
+    per = [d(0, 1), d(1, 5), d(2), d(0), d(3)]
+    left, copied = oracle.precopy_rounds(per, [2, 4], inbuf)
+    # round at 2 copies {0, 1} (5 is no image page); round at 4 copies {2, 0}
+    assert copied == 4 and np.flatnonzero(left).tolist() == [3]
+    left, copied = oracle.precopy_rounds(per, [], inbuf)
+    assert copied == 0 and np.flatnonzero(left).tolist() == [0, 1, 2, 3, 5]
+    left, copied = oracle.precopy_rounds(per, [0], inbuf)  # nothing marked yet
+    assert copied == 0
+
+
+def test_final_rounds_hand_built():
+    """Final-page rounds: dirty {0, 1, 2, 6}, victim {3, 4, 5} with their last
+    failing writes from launches 0, 3 and 1; launches 2 and 3 may write pages
+    1 and 4; page 6 lies outside every buffer.  Worked out by hand: the round
+    before launch 2 takes {0, 2, 3, 5, 6} (4 image pages) and leaves dirty {1}
+    and victim {4}; the round before launch 4 takes both."""
+    n = 8
+    dirty = np.zeros(n, np.uint8)
+    dirty[[0, 1, 2, 6]] = 1
+    victim = np.zeros(n, np.uint8)
+    victim[[3, 4, 5]] = 1
+    last = np.full(n, -1, np.int64)
+    last[3], last[4], last[5] = 0, 3, 1
+    inbuf = np.array([1, 1, 1, 1, 1, 1, 0, 1], np.uint8)
+    up = {2: [1, 4], 4: []}
+
+    def upcoming(r):
+        m = np.zeros(n, np.uint8)
+        m[up[r]] = 1
+        return m
+
+    dl, vl, copied = oracle.final_rounds(dirty, victim, last, [2], upcoming, inbuf)
+    assert (np.flatnonzero(dl).tolist(), np.flatnonzero(vl).tolist(), copied) == ([1], [4], 4)
+    dl, vl, copied = oracle.final_rounds(dirty, victim, last, [2, 4], upcoming, inbuf)
+    assert (dl.any(), vl.any(), copied) == (False, False, 6)
+    assert oracle.recopy_pages(dirty, victim, inbuf) == 6
+
+
+def test_final_rounds_give_the_snapshot_at_t2():
+    """The invariant that makes a final-page round safe (Section 4.3): an image
+    copied once at t1, overwritten by each round's pages as the pool stands
+    at the round, and by the pages left marked at t2, equals the snapshot at
+    t2.  Checked on seeded streams where later launches keep writing the
+    pages of earlier ones, with rounds at several places."""
+    w, pool0, launches, records_fn, apply_fn = _stream_setup(20, 4000)
+    table = oracle.Table.from_world(w, POOL_BASE)
+    npg, page = w.n_pages, w.page_bytes
+    n = len(launches)
+    dirty, victim, last = oracle.track_launches(
+        table, n, lambda j: (launches[j].arg_values(POOL_BASE), records_fn(launches[j])),
+        POOL_BASE, page, npg, threads=4)
+    inbuf = oracle.buffer_pages(table, POOL_BASE, page, npg).astype(bool)
+
+    def upcoming(r):
+        return oracle.write_pages(table, [L.arg_values(POOL_BASE) for L in launches[r:]],
+                                  POOL_BASE, page, npg)
+
+    for rounds in ([5], [3, 9, 15], [1, 2, 19], [10, 20]):
+        pool = pool0.copy()
+        image = pool.copy()  # every page copied at t1 (the background copy)
+        d, v = dirty.astype(bool), victim.astype(bool)
+        copied = 0
+        for j in range(n + 1):
+            if j in rounds:
+                fin_v = v & (last >= 0) & (last < j)
+                listed = (d | fin_v) & ~upcoming(j).astype(bool)
+                for p in np.flatnonzero(listed & inbuf).tolist():
+                    image[p * page:(p + 1) * page] = pool[p * page:(p + 1) * page]
+                copied += int((listed & inbuf).sum())
+                d &= ~listed
+                v &= ~(fin_v & ~upcoming(j).astype(bool))
+            if j < n:
+                apply_fn(pool, launches[j], records_fn(launches[j]))
+        for p in np.flatnonzero((d | v) & inbuf).tolist():  # the recopy at t2
+            image[p * page:(p + 1) * page] = pool[p * page:(p + 1) * page]
+        assert np.array_equal(oracle.snapshot(image, POOL_BASE, table),
+                              oracle.snapshot(pool, POOL_BASE, table)), rounds
+        dl, vl, c = oracle.final_rounds(dirty, victim, last, rounds, upcoming, inbuf)
+        assert np.array_equal(dl, d) and np.array_equal(vl, v) and c == copied
+    # rounds that take nothing: every marked page is still to be written
+    dl, vl, c = oracle.final_rounds(dirty, victim, last, [0], lambda r: np.ones(npg, np.uint8),
+                                    inbuf)
+    assert c == 0 and np.array_equal(dl, dirty.astype(bool))
+
+
+# ------------------------------------------------------ page fingerprints
+def test_page_hash_sees_every_byte_and_place():
+    """The full-size comparisons rest on the fingerprint changing with any
+    byte of the page, with the order of its words and with the page index."""
+    rng = np.random.default_rng(3)
+    page = rng.integers(0, 256, 256, dtype=np.uint8)
+    h0 = oracle.page_hash(page, 5)
+    seen = {h0}
+    for i in range(page.size):
+        for delta in (1, 128):
+            q = page.copy()
+            q[i] ^= delta
+            h = oracle.page_hash(q, 5)
+            assert h != h0
+            seen.add(h)
+    assert len(seen) == 2 * page.size + 1
+    sw = page.copy().view(np.uint64)
+    sw[[0, 1]] = sw[[1, 0]]
+    assert oracle.page_hash(sw.view(np.uint8), 5) != h0
+    assert oracle.page_hash(page, 6) != h0
+    assert oracle.page_hash(np.zeros(64, np.uint8), 0) != oracle.page_hash(np.zeros(64, np.uint8), 1)
+
+
+def test_image_hashes_match_the_snapshot():
+    """Fingerprints taken straight from the pool equal those of the snapshot
+    (whose layout is pinned by the hand example above), and chunked hashing
+    equals hashing in one piece."""
+    w = _small_world()
+    pool = synth.content_host(w.seed, 0, w.pool_bytes)
+    table = oracle.Table.from_world(w, POOL_BASE)
+    img = oracle.snapshot(pool, POOL_BASE, table)
+    want = oracle.hash_pages(img, w.page_bytes)
+    for threads in (1, 3):
+        got = oracle.image_hashes_from_pool(pool, POOL_BASE, table, w.page_bytes, threads)
+        assert np.array_equal(got, want)
+    for chunk in (w.page_bytes, 5 * w.page_bytes, img.nbytes):
+        got = oracle.hash_chunks(lambda o, n: img[o:o + n], img.nbytes, w.page_bytes, chunk, 3)
+        assert np.array_equal(got, want)
+    for i in (0, 7, want.size - 1):
+        assert int(want[i]) == oracle.page_hash(img[i * w.page_bytes:(i + 1) * w.page_bytes], i)
+
+
+def test_apply_stream_and_validate_launches_match_run_stream():
+    """The threaded full-size helpers compose the per-launch definitions as
+    run_stream does."""
+    w, pool0, launches, records_fn, apply_fn = _stream_setup(12, 3000)
+    table = oracle.Table.from_world(w, POOL_BASE)
+    res = oracle.run_stream(w, launches, POOL_BASE, records_fn, apply_fn, pool0.copy(),
+                            snap_before=(len(launches),))
+    pool = pool0.copy()
+    oracle.apply_stream(pool, launches, records_fn, apply_fn, threads=3, ahead=4)
+    assert np.array_equal(oracle.snapshot(pool, POOL_BASE, table), res.snapshots[len(launches)])
+    vl = oracle.validate_launches(table, POOL_BASE, launches, records_fn, threads=3)
+    assert all(np.array_equal(a, b) for a, b in zip(vl, res.violations))
+
+
+def test_run_stream_hashed_matches_run_stream():
+    """The full-size replay composes the same per-launch definitions as
+    run_stream, its fingerprints are those of run_stream's snapshots, and its
+    last-victim positions are those of launch-by-launch tracking."""
+    w, pool0, launches, records_fn, apply_fn = _stream_setup(15, 3000)
+    table = oracle.Table.from_world(w, POOL_BASE)
+    res = oracle.run_stream(w, launches, POOL_BASE, records_fn, apply_fn, pool0.copy(),
+                            snap_before=(0, 6, 15), window=(3, 12))
+    h = oracle.run_stream_hashed(w, launches, POOL_BASE, records_fn, apply_fn, pool0.copy(),
+                                 hash_before=(0, 6, 15), window=(3, 12), threads=3, ahead=4)
+    assert all(np.array_equal(a, b) for a, b in zip(h.violations, res.violations))
+    assert np.array_equal(h.dirty, res.dirty) and np.array_equal(h.victim, res.victim)
+    for j in (0, 6, 15):
+        assert np.array_equal(h.hashes[j], oracle.hash_pages(res.snapshots[j], w.page_bytes))
+    _, _, last = oracle.track_launches(
+        table, 9, lambda i: (launches[3 + i].arg_values(POOL_BASE), records_fn(launches[3 + i])),
+        POOL_BASE, w.page_bytes, w.n_pages)
+    assert np.array_equal(h.last, np.where(last >= 0, last + 3, -1))
+
+
+def test_reader_and_gather_hashes_match_their_definitions():
+    """Chunked fingerprints of a pool read piece by piece equal those of its
+    snapshot; fingerprints of a gather equal those of orc_gather's output."""
+    w = _small_world()
+    pool = synth.content_host(w.seed, 0, w.pool_bytes)
+    table = oracle.Table.from_world(w, POOL_BASE)
+    want = oracle.hash_pages(oracle.snapshot(pool, POOL_BASE, table), w.page_bytes)
+    for chunk in (w.page_bytes, 3 * w.page_bytes, 1 << 30):
+        got = oracle.image_hashes_from_reader(lambda o, n: pool[o:o + n], POOL_BASE, table,
+                                              w.page_bytes, chunk, threads=3)
+        assert np.array_equal(got, want)
+    page = 4096
+    src_off = np.array([0, 5, 9, 20], np.uint64) * page
+    dst_off = np.array([0, 2, 3, 6], np.uint64) * page
+    ln = np.array([2, 1, 3, 1], np.uint64) * page
+    dst = np.zeros(8 * page, np.uint8)
+    oracle.gather(pool, dst, src_off, dst_off, ln)
+    got = oracle.gather_hashes(lambda o, n: pool[o:o + n], src_off, dst_off, ln, page, 7,
+                               threads=2, piece_bytes=page)
+    assert np.array_equal(got, oracle.hash_pages(dst[:7 * page], page))

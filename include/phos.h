@@ -14,7 +14,10 @@
  *   Section 5    chunked device-to-host drain   -> phos_ckpt_end (host_image)
  *   Section 6    concurrent on-demand restore   -> phos_restore_begin / _on_demand / _end
  *   (no paper analog) batched persistent copy and a serving loop
- *                -> phos_batch_*, phos_copy_plain, phos_serve_run
+ *                -> phos_batch_*, phos_copy_plain, phos_copy_batch(_tuned),
+ *                   phos_serve_run
+ *   Section 2.2  image manifest                 -> phos_manifest_write / _check,
+ *                phos_restore_begin_manifest
  *
  * Conventions.  Every call returns a phos_status; nothing throws across the
  * ABI; on failure phos_last_error() holds a thread-local message.  "Device
@@ -72,8 +75,10 @@ enum {
 enum {
   PHOS_V_READS = 1u,  /* report reads outside the read set                            */
   PHOS_V_WRITES = 2u, /* report writes outside the write set                          */
-  PHOS_V_TRACK = 4u   /* set the context's dirty bitmap for validated writes and its
+  PHOS_V_TRACK = 4u,  /* set the context's dirty bitmap for validated writes and its
                          victim bitmap for failing writes inside a buffer (Section 4.3) */
+  PHOS_V_SYNC = 8u    /* wait for the call (not under stream capture) and return
+                         PHOS_E_OVERFLOW if its violations exceed cap                  */
 };
 
 enum { PHOS_COW = 1, PHOS_RECOPY = 2 }; /* checkpoint protocols */
@@ -140,6 +145,12 @@ typedef struct {
  * page_bytes; page_bytes a power of two in [4 KiB, 2 MiB].  The caller owns
  * the pool memory.  E_INVAL on bad sizes, E_NOMEM / E_HIP on allocation.
  *
+ * Status.  The asynchronous calls raise sticky status words on the device
+ * that phos_stream_status reports: a validation with more violations than
+ * its cap (PHOS_E_OVERFLOW) and a device-side segment batch with a malformed
+ * segment (PHOS_E_INVAL).  An expired device wait (PHOS_E_TIMEOUT) and a
+ * misspeculation of an inline validator (PHOS_E_MISSPEC) are reported by the
+ * phos_ckpt_end / phos_restore_end of the checkpoint or restore they spoil.
  * Tuning, read from the environment here (defaults in brackets):
  *   PHOS_SPIN_LIMIT      polls before a device wait gives up [1 << 22]
  *   PHOS_BG_GRID         background copy blocks [2 x CUs; at most CUs when
@@ -204,8 +215,10 @@ phos_status phos_spec_release(phos_ctx *ctx, phos_spec spec);
  * memory, one uint64_t).  With PHOS_V_TRACK the dirty / victim bitmaps are
  * updated.  d_records: device memory, 8-byte aligned (16-byte alignment is
  * faster).  Asynchronous on `stream`; if *n_violations > cap the contents of
- * out are unspecified.  Validation calls on one context are serialized by
- * the library. */
+ * out are unspecified and the overflow is reported by phos_stream_status,
+ * or by this call itself with PHOS_V_SYNC (PHOS_E_OVERFLOW, the true count
+ * in *n_violations).  Validation calls on one context are serialized by the
+ * library. */
 phos_status phos_validate(phos_ctx *ctx, phos_spec spec, const uint64_t *d_records, uint64_t n,
                           uint32_t flags, phos_violation *out, uint64_t cap,
                           uint64_t *n_violations, hipStream_t stream);
@@ -232,11 +245,23 @@ phos_status phos_validate_batch(phos_ctx *ctx, const phos_spec *specs,
  * count to *n_violations (device memory, zeroed by the call; E_INVAL if
  * flags != 0 and it is NULL).  x, y, idx: device memory, 8-byte aligned; the
  * caller guarantees every y + j lies in memory it may write.  Asynchronous
- * on `stream`. */
+ * on `stream` (PHOS_V_SYNC as for phos_validate).  Section 4.2 with an
+ * inline validator: the write is made before its check fails, so with a
+ * copy-on-write checkpoint open (and PHOS_V_WRITES or PHOS_V_TRACK) a
+ * failing write inside a buffer, on a page that checkpoint has not copied
+ * yet, is a misspeculation: that checkpoint's phos_ckpt_end returns
+ * PHOS_E_MISSPEC, and the caller takes a stop-the-world checkpoint instead. */
 phos_status phos_twin_scale_add(phos_ctx *ctx, phos_spec spec, const uint64_t *x, uint64_t *y,
                                 const int64_t *idx, uint64_t n, uint32_t flags,
                                 phos_violation *out, uint64_t cap, uint64_t *n_violations,
                                 hipStream_t stream);
+
+/* Synchronous: wait for the work enqueued on `stream`, then report and clear
+ * the sticky status the context's asynchronous calls raised so far:
+ * PHOS_E_INVAL if a phos_copy_batch* call met a malformed segment (that call
+ * copied nothing), else PHOS_E_OVERFLOW if a validation or twin call found
+ * more violations than its cap, else PHOS_OK. */
+phos_status phos_stream_status(phos_ctx *ctx, hipStream_t stream);
 
 /* Clear the dirty and victim bitmaps, the victim list and the launch
  * numbering of validation (the next validated launch is number 1 again;
@@ -345,7 +370,11 @@ phos_status phos_ckpt_precopy_final(phos_ckpt *ck, const phos_spec *upcoming, ui
  * first (ending is a quiesce point).  The drain (Section 5) is issued in
  * chunks from the calling thread with a few in flight, so device-to-host
  * copies the application issues meanwhile wait for a few chunks, not for
- * the whole image.  E_TIMEOUT if a device wait expired. */
+ * the whole image.  E_TIMEOUT if a device wait expired.  E_MISSPEC for a
+ * copy-on-write checkpoint if an instrumented launch (phos_twin_scale_add)
+ * wrote outside its speculation into a page the checkpoint had not copied
+ * (Section 4.2: the image is then not the state at t1; take a stop-the-world
+ * checkpoint).  The handle is freed in every case. */
 phos_status phos_ckpt_end(phos_ckpt *ck, hipStream_t app_stream, phos_ckpt_stats *stats);
 
 /* Synchronous: copied-page bitmap of an open checkpoint (bit p = pool page p);
@@ -365,6 +394,25 @@ phos_status phos_ckpt_copied(phos_ckpt *ck, uint32_t *host_words, uint64_t nword
  * E_TIMEOUT if a device wait expired.  One restore per context at a time. */
 phos_status phos_restore_begin(phos_ctx *ctx, uint32_t flags, const void *image,
                                hipStream_t copy_stream, phos_rst **out);
+
+/* Section 2.2: an image holds the buffers' bytes only, so a restore must go
+ * into the same buffers.  A manifest records them: magic "PHOSIMG1",
+ * version 1, the protocol (PHOS_COW / PHOS_RECOPY, 0: none), the page size,
+ * the buffer count and the image bytes (a 32-byte header), then per buffer
+ * its pool-relative offset and size (2 x uint64), then an FNV-1a 64 checksum
+ * of everything before it.  Host only, synchronous.  phos_manifest_write
+ * writes the context's manifest (out NULL: only *bytes, the size;
+ * E_OVERFLOW if cap is smaller).  phos_manifest_check returns E_INVAL unless
+ * the manifest is intact and its page size, buffer count, image bytes and
+ * buffer sizes (in order) equal the context's registered buffers (their
+ * places in the pool may differ).  phos_restore_begin_manifest checks, then
+ * opens the restore as phos_restore_begin. */
+phos_status phos_manifest_write(phos_ctx *ctx, uint32_t protocol, void *out, uint64_t cap,
+                                uint64_t *bytes);
+phos_status phos_manifest_check(phos_ctx *ctx, const void *manifest, uint64_t bytes);
+phos_status phos_restore_begin_manifest(phos_ctx *ctx, uint32_t flags, const void *image,
+                                        const void *manifest, uint64_t manifest_bytes,
+                                        hipStream_t copy_stream, phos_rst **out);
 
 /* As phos_restore_begin, with the image split into nchunks pieces of
  * chunk_bytes each (a multiple of the page size; the last may be partly
@@ -448,6 +496,28 @@ phos_status phos_copy_plain(const phos_seglist *l, uint64_t chunk_bytes, uint32_
  * distribution (log2 of total bytes, segment count and mean size). */
 phos_status phos_batch_tune(int device, const phos_copy_seg *segs, uint64_t nseg,
                             const char *cache_path, phos_batch_cfg *best, double *best_ms);
+
+/* Segments already in device memory (or pinned host memory), copied by the
+ * context (no paper analog; the paper copies buffer by buffer in 4 MB
+ * chunks, Section 5).  d_segs: nseg phos_copy_seg entries, 8-byte aligned;
+ * each segment's src, dst and bytes must be non-NULL 16-byte multiples, or
+ * the whole call copies nothing and phos_stream_status reports E_INVAL; req
+ * is ignored.  Segments must not overlap one another's destinations or
+ * sources.  Asynchronous on `stream`; calls of one context must not overlap
+ * (they share its segment header).  phos_copy_batch: one workgroup writes
+ * the byte prefix of the segment stream, then one persistent launch copies
+ * it in chunks with the default configuration (1 MiB chunks, 2 workgroups of
+ * 512 threads per CU; PHOS_BATCH_CHUNK / _WG_PER_CU / _THREADS override).
+ * phos_copy_batch_tuned: the same pair of kernels captured in a HIP graph
+ * and replayed; the first call for a (d_segs, nseg) pair reads the segments
+ * back (synchronously), runs phos_batch_tune on them (which performs the
+ * copies; cache file: $PHOS_TUNE_CACHE) and captures the graph with the
+ * configuration it picks; later calls with the same pair replay it (the
+ * segments' contents may change between calls; the choice is kept). */
+phos_status phos_copy_batch(phos_ctx *ctx, const phos_copy_seg *d_segs, uint64_t nseg,
+                            hipStream_t stream);
+phos_status phos_copy_batch_tuned(phos_ctx *ctx, const phos_copy_seg *d_segs, uint64_t nseg,
+                                  hipStream_t stream);
 
 /* Run the loaded queue with the plain kernel (one workgroup per chunk, no
  * graph, no persistence) — the per-request path the batch is compared with. */

@@ -253,6 +253,8 @@ extern "C" phos_status phos_batch_load(phos_batch *b, const phos_copy_seg *segs,
 }
 
 namespace phos {
+phos_batch_cfg batch_default_cfg() { return default_cfg(); }
+bool batch_cfg_ok(const phos_batch_cfg &c) { return cfg_ok(c); }
 const volatile unsigned long long *batch_stamps(const phos_batch *b) { return b->d_req_time; }
 double batch_clock_khz(const phos_batch *b) { return b->clock_khz; }
 }  // namespace phos

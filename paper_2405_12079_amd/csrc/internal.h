@@ -179,18 +179,26 @@ struct TwinArgs {
   phos_violation *out;  // unordered
   uint64_t cap;
   unsigned long long *count;
+  uint32_t *overflow;          // set to 1 when the count exceeds cap (sticky)
+  // an open copy-on-write checkpoint's page states (nullptr: none), and the
+  // word raised when a failing write lands on a page it has not copied
+  const uint32_t *cow_state;
+  uint32_t *misspec;
 };
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_validate(const VArgs &a, const DevSpec *single, bool track, hipStream_t s);
+// overflow: optional word set to 1 (sticky) when the call's count exceeds cap
 hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
-                        uint64_t *n_out, unsigned long long *cursor, hipStream_t s);
+                        uint64_t *n_out, unsigned long long *cursor, uint64_t cap,
+                        uint32_t *overflow, hipStream_t s);
 hipError_t launch_vfinish(const uint32_t *tile_count, const unsigned long long *tile_off,
                           uint32_t ntiles, const phos_violation *scratch, uint64_t scratch_cap,
                           phos_violation *out, uint64_t cap, uint64_t *n_out,
-                          unsigned long long *cursor, unsigned long long *seg_sum, hipStream_t s);
+                          unsigned long long *cursor, unsigned long long *seg_sum,
+                          uint32_t *overflow, hipStream_t s);
 hipError_t launch_vscatter(const uint32_t *tile_count, const unsigned long long *tile_off,
                            uint32_t ntiles, const unsigned long long *seg_prefix,
                            const phos_violation *scratch, uint64_t scratch_cap,
@@ -230,11 +238,20 @@ hipError_t launch_read_clock(unsigned long long *out, hipStream_t s);  // GPU wa
 hipError_t launch_twin(const TwinArgs &a, const DevSpec &spec, uint64_t blocks, uint32_t n_cu,
                        hipStream_t s);
 hipError_t launch_batch_copy(const BatchQ &q, uint32_t grid, uint32_t threads, hipStream_t s);
+// Device-resident segments: header, byte prefix and cursor reset (one block);
+// bad: word raised when a segment is malformed (the call then copies nothing)
+hipError_t launch_segs_prefix(const phos_copy_seg *segs, uint64_t nseg, unsigned long long *hdr,
+                              unsigned long long *prefix, unsigned long long *cursor,
+                              uint32_t *bad, hipStream_t s);
 hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);
 
 // Completion stamps of a batch's last run ([0] start, [1 + r] request r),
 // host-visible (pinned), and the GPU wall-clock rate in kHz.
 const volatile unsigned long long *batch_stamps(const phos_batch *b);
+// The batch copy's default configuration (environment overrides applied) and
+// the configuration check phos_batch_create applies.
+phos_batch_cfg batch_default_cfg();
+bool batch_cfg_ok(const phos_batch_cfg &c);
 double batch_clock_khz(const phos_batch *b);
 
 }  // namespace phos

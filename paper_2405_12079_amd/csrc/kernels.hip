@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(1024)
     vfinish_kernel(const uint32_t *tile_count, const unsigned long long *tile_off, uint32_t ntiles,
                    const phos_violation *scratch, uint64_t scratch_cap, phos_violation *out,
                    uint64_t cap, uint64_t *n_out, unsigned long long *cursor,
-                   unsigned long long *seg_sum) {
+                   unsigned long long *seg_sum, uint32_t *overflow) {
   __shared__ unsigned long long s[1024];
   const uint32_t t = threadIdx.x;
   const uint32_t per = (ntiles + 1023) / 1024;
@@ -449,6 +449,7 @@ __global__ void __launch_bounds__(1024)
   if (t == 1023) {
     *n_out = s[1023];
     *cursor = 0;
+    if (overflow && s[1023] > cap) atomicOr(overflow, 1u);  // sticky until read
   }
   for (uint32_t i = t; i < (ntiles + kSeg - 1) / kSeg; i += 1024) seg_sum[i] = 0;
 }
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(1024)
 // Exclusive scan of per-segment violation counts (one block of 1024).
 __global__ void __launch_bounds__(1024)
     vscan_kernel(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
-                 uint64_t *n_out, unsigned long long *cursor) {
+                 uint64_t *n_out, unsigned long long *cursor, uint64_t cap, uint32_t *overflow) {
   __shared__ unsigned long long s[1024];
   const uint32_t t = threadIdx.x;
   unsigned long long carry = 0;
@@ -480,6 +481,7 @@ __global__ void __launch_bounds__(1024)
   if (t == 0) {
     *n_out = carry;
     *cursor = 0;
+    if (overflow && carry > cap) atomicOr(overflow, 1u);  // sticky until read
   }
 }
 
@@ -1122,7 +1124,10 @@ __device__ __forceinline__ void twin_report(const TwinArgs &A, bool bad, uint64_
   if (!m) return;
   const uint32_t lane = threadIdx.x & 63u, lead = (uint32_t)__ffsll((unsigned long long)m) - 1u;
   unsigned long long base = 0;
-  if (lane == lead) base = atomicAdd(A.count, (unsigned long long)__popcll(m));
+  if (lane == lead) {
+    base = atomicAdd(A.count, (unsigned long long)__popcll(m));
+    if (A.overflow && base + (unsigned long long)__popcll(m) > A.cap) atomicOr(A.overflow, 1u);
+  }
   base = __shfl(base, (int)lead, 64);
   if (!bad) return;
   const unsigned long long pos = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
@@ -1159,6 +1164,18 @@ __device__ __forceinline__ void twin_track(const TwinArgs &A, bool act, uint64_t
       else A.vmeta[3] = 1;
     }
   }
+}
+
+// Section 4.2 with the validator inside the kernel: the write has already
+// been made when its check fails, so if it lands on a page that the open
+// copy-on-write checkpoint has not copied yet, that image can no longer be
+// the state at t1 (the caller must fall back to a stop-the-world copy).
+__device__ __forceinline__ void twin_misspec(const TwinArgs &A, bool bad_write, uint64_t a) {
+  const uint64_t off = a - A.pool_base;
+  if (!bad_write || off >= A.pool_bytes) return;
+  const uint32_t page = (uint32_t)(off >> A.page_shift);
+  if (A.page_buf[page] != kNone && ld_relaxed(const_cast<uint32_t *>(&A.cow_state[page])) != kDone)
+    atomicOr(A.misspec, 1u);
 }
 
 // Each thread takes kTwinU elements per pass (stride: the grid): all their
@@ -1218,6 +1235,7 @@ __global__ void __launch_bounds__(256) twin_kernel(TwinArgs A, DevSpec S) {
           const uint32_t r3 = twin_classify<NIV>(R, S, ya, 1);
           if (wr) twin_report(A, act[k] && r3 != 0, i, ya, 1, r3);
           if (tr) twin_track(A, act[k], ya, r3);
+          if (A.cow_state) twin_misspec(A, act[k] && r3 != 0, ya);
         }
       }
     }
@@ -1248,7 +1266,7 @@ __device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, u
       const phos_copy_seg g = Q.segs[s];
       block_copy16(reinterpret_cast<const uint4 *>(g.src + (lo - seg_lo)),
                    reinterpret_cast<uint4 *>(g.dst + (lo - seg_lo)), (hi - lo) >> 4);
-      if (threadIdx.x == 0) {
+      if (threadIdx.x == 0 && Q.done) {
         const unsigned long long old = atomicAdd(&Q.done[g.req], (unsigned long long)(hi - lo));
         // the request's last piece: stamp its completion on the GPU wall clock
         if (Q.req_total && old + (hi - lo) == Q.req_total[g.req])
@@ -1257,6 +1275,50 @@ __device__ void copy_stream_range(const BatchQ &Q, uint64_t nseg, uint64_t b0, u
       pos = hi;
     }
     ++s;
+  }
+}
+
+// Segments handed over in device memory: one workgroup checks them and
+// writes the byte stream's header and exclusive prefix, then resets the chunk
+// cursor.  A segment that is not 16-byte aligned or has a NULL address makes
+// the whole call copy nothing (total 0) and raises the bad-segment word.
+__global__ void __launch_bounds__(1024)
+    segs_prefix_kernel(const phos_copy_seg *segs, uint64_t nseg, unsigned long long *hdr,
+                       unsigned long long *prefix, unsigned long long *cursor, uint32_t *bad) {
+  __shared__ unsigned long long s[1024];
+  __shared__ uint32_t s_bad;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) s_bad = 0;
+  __syncthreads();
+  unsigned long long carry = 0;
+  for (uint64_t b0 = 0; b0 < nseg; b0 += 1024) {
+    const uint64_t i = b0 + t;
+    unsigned long long v = 0;
+    if (i < nseg) {
+      const phos_copy_seg g = segs[i];
+      v = g.bytes;
+      if (((g.src | g.dst | g.bytes) & 15u) || (g.bytes && (!g.src || !g.dst))) s_bad = 1;
+    }
+    s[t] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      const unsigned long long x = t >= d ? s[t - d] : 0ull;
+      __syncthreads();
+      s[t] += x;
+      __syncthreads();
+    }
+    if (i < nseg) prefix[i] = carry + s[t] - v;
+    carry += s[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    prefix[nseg] = carry;
+    hdr[0] = nseg;
+    hdr[1] = s_bad ? 0ull : carry;
+    hdr[2] = 0;
+    hdr[3] = 0;
+    *cursor = 0;
+    if (s_bad && bad) atomicOr(bad, 1u);
   }
 }
 
@@ -1336,18 +1398,20 @@ hipError_t launch_validate(const VArgs &a, const DevSpec *single, bool track, hi
 }
 
 hipError_t launch_vscan(unsigned long long *seg_sum, uint32_t nseg, unsigned long long *seg_prefix,
-                        uint64_t *n_out, unsigned long long *cursor, hipStream_t s) {
+                        uint64_t *n_out, unsigned long long *cursor, uint64_t cap,
+                        uint32_t *overflow, hipStream_t s) {
   hipLaunchKernelGGL(vscan_kernel, dim3(1), dim3(1024), 0, s, seg_sum, nseg, seg_prefix, n_out,
-                     cursor);
+                     cursor, cap, overflow);
   return hipGetLastError();
 }
 
 hipError_t launch_vfinish(const uint32_t *tile_count, const unsigned long long *tile_off,
                           uint32_t ntiles, const phos_violation *scratch, uint64_t scratch_cap,
                           phos_violation *out, uint64_t cap, uint64_t *n_out,
-                          unsigned long long *cursor, unsigned long long *seg_sum, hipStream_t s) {
+                          unsigned long long *cursor, unsigned long long *seg_sum,
+                          uint32_t *overflow, hipStream_t s) {
   hipLaunchKernelGGL(vfinish_kernel, dim3(1), dim3(1024), 0, s, tile_count, tile_off, ntiles,
-                     scratch, scratch_cap, out, cap, n_out, cursor, seg_sum);
+                     scratch, scratch_cap, out, cap, n_out, cursor, seg_sum, overflow);
   return hipGetLastError();
 }
 
@@ -1472,6 +1536,14 @@ hipError_t launch_read_clock(unsigned long long *out, hipStream_t s) {
 hipError_t launch_batch_reset(const BatchQ &q, hipStream_t s) {
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, s, q.hdr, q.cursor, q.done,
                      q.req_time ? q.req_time - 1 : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_segs_prefix(const phos_copy_seg *segs, uint64_t nseg, unsigned long long *hdr,
+                              unsigned long long *prefix, unsigned long long *cursor,
+                              uint32_t *bad, hipStream_t s) {
+  hipLaunchKernelGGL(segs_prefix_kernel, dim3(1), dim3(1024), 0, s, segs, nseg, hdr, prefix, cursor,
+                     bad);
   return hipGetLastError();
 }
 

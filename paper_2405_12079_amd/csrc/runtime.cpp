@@ -86,7 +86,28 @@ struct phos_ctx {
   uint32_t *d_victim_seq = nullptr;
   uint32_t vseq = 0;
   uint32_t vlist_cap = 0;
+  // status words the kernels raise (device memory, kErr* entries): a bounded
+  // wait expired; a validation found more violations than its cap; a
+  // device-side batch met a malformed segment; a write out of speculation
+  // landed on a page an open copy-on-write checkpoint had not copied
   uint32_t *d_err = nullptr;
+
+  // device-resident segment batches (phos_copy_batch*): [hdr 4][prefix cap+1]
+  // and a chunk cursor; tuned calls replay a captured graph per (segments,
+  // count) with the autotuner's configuration
+  unsigned long long *d_bq = nullptr, *d_bcursor = nullptr;
+  uint64_t bq_cap = 0;
+  struct SegGraph {
+    const phos_copy_seg *segs;
+    uint64_t nseg;
+    phos_batch_cfg cfg;
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+    uint64_t last_use;
+  };
+  std::vector<SegGraph> seg_graphs;
+  uint64_t seg_clock = 0;
+  hipStream_t cap_stream = nullptr;  // capture stream of those graphs
 
   // validation workspace
   phos_violation *d_scratch = nullptr;
@@ -196,6 +217,8 @@ struct phos_ckpt {
   }
 };
 
+constexpr uint32_t kErrWait = 0, kErrOverflow = 1, kErrSegment = 2, kErrMisspec = 3, kErrWords = 4;
+
 constexpr uint32_t kWantCap = 16384;      // asked-for pages the host can see per restore
 constexpr uint64_t kDmaRunBytes = 4u << 20;  // largest single bulk DMA (one bounce slot)
 constexpr uint64_t kBounceBytes = 2 * kDmaRunBytes;  // two staging slots
@@ -270,6 +293,13 @@ static phos_status ctx_free(phos_ctx *c) {
   if (c->h_want) (void)hipHostFree(c->h_want);
   if (c->h_bounce) (void)hipHostFree(c->h_bounce);
   if (c->hsa_inited) (void)hsa_shut_down();
+  for (auto &g : c->seg_graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  if (c->d_bq) (void)hipFree(c->d_bq);
+  if (c->d_bcursor) (void)hipFree(c->d_bcursor);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->v_evt) (void)hipEventDestroy(c->v_evt);
   if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
   if (c->aux) (void)hipStreamDestroy(c->aux);
@@ -338,7 +368,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   CK(dalloc(&c->d_dirty, 32ull * c->nwords));
   CK(dalloc(&c->d_victim, 32ull * c->nwords));
   CK(dalloc(&c->d_victim_seq, 32ull * c->nwords));
-  CK(dalloc(&c->d_err, 1));
+  CK(dalloc(&c->d_err, kErrWords));
   c->vlist_cap = 2 * c->n_pages + 4096;
   CK(dalloc(&c->d_vlist, c->vlist_cap));
   CK(dalloc(&c->d_vmeta, 4));
@@ -363,7 +393,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       !hipck(hipMemset(c->d_dirty, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_victim, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_victim_seq, 0, c->nwords * 128ull), "hipMemset") ||
-      !hipck(hipMemset(c->d_err, 0, 4), "hipMemset") ||
+      !hipck(hipMemset(c->d_err, 0, 4 * kErrWords), "hipMemset") ||
       !hipck(hipMemset(c->d_vmeta, 0, 16), "hipMemset") ||
       !hipck(hipMemset(c->d_cursor, 0, 8), "hipMemset") ||
       !hipck(hipMemset(c->d_seg_sum, 0, c->seg_cap * 8), "hipMemset") ||
@@ -640,21 +670,23 @@ static void note_victims(phos_ctx *c, hipStream_t s) {
 // capture no event is used (captured validations must share one stream).
 static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *single,
                                   phos_violation *out, uint64_t cap, uint64_t *n_out,
-                                  hipStream_t s) {
+                                  hipStream_t s, unsigned long long *seg_prefix = nullptr) {
+  if (!seg_prefix) seg_prefix = c->d_seg_prefix;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(s, &cs));
   const bool capturing = cs != hipStreamCaptureStatusNone;
   if (!capturing && c->v_evt_used && s != c->v_stream) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
   HIP_TRY(launch_validate(a, single, (a.flags & PHOS_V_TRACK) != 0, s));
   if (a.flags & PHOS_V_TRACK) note_victims(c, s);
+  uint32_t *overflow = c->d_err + kErrOverflow;
   if (a.ntiles <= c->finish_tiles) {
-    HIP_TRY(launch_vfinish(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_scratch, c->scratch_cap,
-                           out, cap, n_out, c->d_cursor, c->d_seg_sum, s));
+    HIP_TRY(launch_vfinish(a.tile_count, a.tile_off, a.ntiles, a.scratch, a.scratch_cap, out, cap,
+                           n_out, a.cursor, a.seg_sum, overflow, s));
   } else {
     const uint32_t nseg = (a.ntiles + kSeg - 1) / kSeg;
-    HIP_TRY(launch_vscan(c->d_seg_sum, nseg, c->d_seg_prefix, n_out, c->d_cursor, s));
-    HIP_TRY(launch_vscatter(c->d_tile_count, c->d_tile_off, a.ntiles, c->d_seg_prefix,
-                            c->d_scratch, c->scratch_cap, out, cap, s));
+    HIP_TRY(launch_vscan(a.seg_sum, nseg, seg_prefix, n_out, a.cursor, cap, overflow, s));
+    HIP_TRY(launch_vscatter(a.tile_count, a.tile_off, a.ntiles, seg_prefix, a.scratch,
+                            a.scratch_cap, out, cap, s));
   }
   if (!capturing) {
     HIP_TRY(hipEventRecord(c->v_evt, s));
@@ -664,7 +696,24 @@ static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *si
   return PHOS_OK;
 }
 
-static const uint32_t kFlagMask = PHOS_V_READS | PHOS_V_WRITES | PHOS_V_TRACK;
+static const uint32_t kKernelFlags = PHOS_V_READS | PHOS_V_WRITES | PHOS_V_TRACK;
+static const uint32_t kFlagMask = kKernelFlags | PHOS_V_SYNC;
+
+// PHOS_V_SYNC: wait for the call and report whether its true count exceeds cap.
+static phos_status sync_count(phos_ctx *c, const uint64_t *n_out, uint64_t cap, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(PHOS_E_STATE, "PHOS_V_SYNC waits for the stream: not under stream capture");
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 16, n_out, 8, hipMemcpyDefault, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint64_t n = c->h_pinned[16];
+  if (n > cap)
+    return fail(PHOS_E_OVERFLOW, "%llu violations for a capacity of %llu (*n_violations holds the "
+                "true count; the contents of out are unspecified)", (unsigned long long)n,
+                (unsigned long long)cap);
+  return PHOS_OK;
+}
 
 extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const uint64_t *x,
                                            uint64_t *y, const int64_t *idx, uint64_t n,
@@ -706,11 +755,20 @@ extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const ui
   a.out = out;
   a.cap = out ? cap : 0;
   a.count = reinterpret_cast<unsigned long long *>(n_violations);
+  a.overflow = c->d_err + kErrOverflow;
+  // Section 4.2: with the validator inside the kernel a failing write is
+  // made before it is reported, so one landing on a page the open
+  // copy-on-write checkpoint has not copied is a misspeculation
+  phos_ckpt *cow = c->open_ckpt[PHOS_COW];
+  a.cow_state = cow ? cow->slot->state : nullptr;
+  a.misspec = c->d_err + kErrMisspec;
+  a.flags = flags & kKernelFlags;
   DeviceGuard g(c->device);
   if (flags) HIP_TRY(launch_fill_u64(a.count, 1, 0, stream));
   const uint64_t blocks = (n + 4 * 256 - 1) / (4 * 256);  // four elements per thread
   HIP_TRY(launch_twin(a, ds, blocks, c->n_cu, stream));
   if (flags & PHOS_V_TRACK) note_victims(c, stream);
+  if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, a.cap, stream);
   return PHOS_OK;
 }
 
@@ -730,7 +788,7 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   TRY(ensure_workspace(c, ntiles, cap));
   DevSpec ds;
   fill_devspec(*h, &ds);
-  VArgs a = base_vargs(c, flags, tile);
+  VArgs a = base_vargs(c, flags & kKernelFlags, tile);
   a.launches = nullptr;
   a.single.rec = d_records;
   a.single.n = n;
@@ -739,7 +797,9 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   a.seq0 = ++c->vseq;
   a.nlaunch = 1;
   a.ntiles = (uint32_t)ntiles;
-  return run_validation(c, a, &ds, out, cap, n_violations, stream);
+  TRY(run_validation(c, a, &ds, out, cap, n_violations, stream));
+  if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
+  return PHOS_OK;
 }
 
 extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
@@ -830,7 +890,7 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
     hit = &c->vcache.back();
   }
   hit->last_use = ++c->vclock;
-  VArgs a = base_vargs(c, flags, tile);
+  VArgs a = base_vargs(c, flags & kKernelFlags, tile);
   a.launches = reinterpret_cast<const VLaunch *>(hit->dev);
   a.ivs = reinterpret_cast<const DevIv *>(hit->dev + nlaunch * sizeof(VLaunch));
   a.tile_launch = reinterpret_cast<const uint32_t *>(hit->dev + head);
@@ -839,7 +899,227 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   a.seq0 = c->vseq + 1;  // launch i is numbered seq0 + i
   c->vseq += nlaunch;
   static DevSpec unused;  // kernel parameter of the single-launch path
-  return run_validation(c, a, &unused, out, cap, n_violations, stream);
+  TRY(run_validation(c, a, &unused, out, cap, n_violations, stream));
+  if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_stream_status(phos_ctx *c, hipStream_t s) {
+  if (!c) return fail(PHOS_E_INVAL, "phos_stream_status: NULL context");
+  DeviceGuard g(c->device);
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 8, c->d_err, 4 * kErrWords, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint32_t *w = reinterpret_cast<const uint32_t *>(c->h_pinned + 8);
+  const bool ov = w[kErrOverflow] != 0, seg = w[kErrSegment] != 0;
+  if (ov) HIP_TRY(launch_fill_u32(c->d_err + kErrOverflow, 1, 0, s));
+  if (seg) HIP_TRY(launch_fill_u32(c->d_err + kErrSegment, 1, 0, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (seg)
+    return fail(PHOS_E_INVAL, "a phos_copy_batch call met a segment that is not 16-byte aligned "
+                "or has a NULL address, and copied nothing%s",
+                ov ? "; a validation also found more violations than its capacity" : "");
+  if (ov) return fail(PHOS_E_OVERFLOW, "a validation found more violations than its capacity");
+  return PHOS_OK;
+}
+
+static bool device_readable(const void *p, bool *in_host);
+
+// ------------------------------------------- device-resident segment batches
+// (no paper analog; the paper copies buffer by buffer in 4 MB chunks,
+// Section 5)
+static phos_status ensure_bq(phos_ctx *c, uint64_t nseg) {
+  if (c->d_bq && nseg <= c->bq_cap) return PHOS_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto &g : c->seg_graphs) {  // they name the old queue
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  c->seg_graphs.clear();
+  if (c->d_bq) (void)hipFree(c->d_bq);
+  c->d_bq = nullptr;
+  const uint64_t cap = std::max<uint64_t>({nseg, 2 * c->bq_cap, 1024});
+  c->bq_cap = 0;
+  TRY(dalloc(&c->d_bq, 4 + cap + 1));
+  if (!c->d_bcursor) TRY(dalloc(&c->d_bcursor, 1));
+  c->bq_cap = cap;
+  return PHOS_OK;
+}
+
+// The segment header and prefix, then the persistent copy (the same kernel
+// as the batch graph's), on stream s.
+static phos_status enqueue_seg_copy(phos_ctx *c, const phos_copy_seg *d_segs, uint64_t nseg,
+                                    const phos_batch_cfg &cfg, hipStream_t s) {
+  HIP_TRY(launch_segs_prefix(d_segs, nseg, c->d_bq, c->d_bq + 4, c->d_bcursor,
+                             c->d_err + kErrSegment, s));
+  BatchQ q;
+  memset(&q, 0, sizeof q);
+  q.segs = d_segs;
+  q.hdr = c->d_bq;
+  q.byte_prefix = c->d_bq + 4;
+  q.cursor = c->d_bcursor;
+  q.chunk_bytes = cfg.chunk_bytes;
+  HIP_TRY(launch_batch_copy(q, cfg.wg_per_cu * c->n_cu, cfg.threads, s));
+  return PHOS_OK;
+}
+
+static phos_status seg_args_ok(phos_ctx *c, const phos_copy_seg *d_segs, uint64_t nseg,
+                               const char *who) {
+  if (!c || (nseg && !d_segs)) return fail(PHOS_E_INVAL, "%s: NULL argument", who);
+  if (((uintptr_t)d_segs) & 7) return fail(PHOS_E_INVAL, "%s: segments must be 8-byte aligned", who);
+  if (nseg > (1ull << 32)) return fail(PHOS_E_INVAL, "%s: too many segments", who);
+  if (nseg && !device_readable(d_segs, nullptr))
+    return fail(PHOS_E_INVAL, "%s: segments must be in device (or pinned host) memory", who);
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_copy_batch(phos_ctx *c, const phos_copy_seg *d_segs, uint64_t nseg,
+                                       hipStream_t stream) {
+  TRY(seg_args_ok(c, d_segs, nseg, "phos_copy_batch"));
+  if (!nseg) return PHOS_OK;
+  DeviceGuard g(c->device);
+  TRY(ensure_bq(c, nseg));
+  return enqueue_seg_copy(c, d_segs, nseg, batch_default_cfg(), stream);
+}
+
+extern "C" phos_status phos_copy_batch_tuned(phos_ctx *c, const phos_copy_seg *d_segs,
+                                             uint64_t nseg, hipStream_t stream) {
+  TRY(seg_args_ok(c, d_segs, nseg, "phos_copy_batch_tuned"));
+  if (!nseg) return PHOS_OK;
+  DeviceGuard g(c->device);
+  TRY(ensure_bq(c, nseg));
+  phos_ctx::SegGraph *hit = nullptr;
+  for (auto &e : c->seg_graphs)
+    if (e.segs == d_segs && e.nseg == nseg) hit = &e;
+  if (!hit) {
+    // first call for these segments: read them (synchronously), tune on
+    // them (the tuner performs the copies), capture the graph
+    std::vector<phos_copy_seg> h(nseg);
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(h.data(), d_segs, nseg * sizeof(phos_copy_seg), hipMemcpyDefault));
+    for (uint64_t i = 0; i < nseg; ++i) {
+      const phos_copy_seg &x = h[i];
+      if (((x.src | x.dst | x.bytes) & 15) || (x.bytes && (!x.src || !x.dst)))
+        return fail(PHOS_E_INVAL, "segment %llu: addresses and size must be non-NULL 16-byte "
+                    "multiples", (unsigned long long)i);
+      h[i].req = 0;  // the tuner's per-request accounting is not needed
+    }
+    phos_batch_cfg cfg = batch_default_cfg();
+    TRY(phos_batch_tune(c->device, h.data(), nseg, getenv("PHOS_TUNE_CACHE"), &cfg, nullptr));
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (c->seg_graphs.size() >= 16) {  // evict the least recently used
+      auto lru = std::min_element(c->seg_graphs.begin(), c->seg_graphs.end(),
+                                  [](const phos_ctx::SegGraph &x, const phos_ctx::SegGraph &y) {
+                                    return x.last_use < y.last_use;
+                                  });
+      HIP_TRY(hipDeviceSynchronize());
+      (void)hipGraphExecDestroy(lru->exec);
+      (void)hipGraphDestroy(lru->graph);
+      c->seg_graphs.erase(lru);
+    }
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const phos_status st = enqueue_seg_copy(c, d_segs, nseg, cfg, c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st != PHOS_OK || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st != PHOS_OK ? st : fail(PHOS_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(PHOS_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    }
+    c->seg_graphs.push_back({d_segs, nseg, cfg, exec, graph, 0});
+    hit = &c->seg_graphs.back();
+  }
+  hit->last_use = ++c->seg_clock;
+  HIP_TRY(hipGraphLaunch(hit->exec, stream));
+  return PHOS_OK;
+}
+
+// ------------------------------------------------------------ image manifest
+// Section 2.2: the checkpointed state is the process's buffers; an image is
+// their bytes back to back in ascending base order.  The manifest says which
+// buffers those were, so a restore can refuse an image that does not match
+// the buffers registered for it.
+namespace {
+constexpr char kManifestMagic[8] = {'P', 'H', 'O', 'S', 'I', 'M', 'G', '1'};
+struct ManifestHead {
+  char magic[8];
+  uint32_t version, protocol;
+  uint32_t page_bytes, n_buffers;
+  uint64_t image_bytes;
+};
+static_assert(sizeof(ManifestHead) == 32, "manifest header is 32 bytes");
+uint64_t fnv1a(const uint8_t *p, uint64_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (uint64_t i = 0; i < n; ++i) h = (h ^ p[i]) * 1099511628211ull;
+  return h;
+}
+uint64_t manifest_bytes(uint64_t n_buffers) { return sizeof(ManifestHead) + 16 * n_buffers + 8; }
+}  // namespace
+
+extern "C" phos_status phos_manifest_write(phos_ctx *c, uint32_t protocol, void *out, uint64_t cap,
+                                           uint64_t *bytes) {
+  if (!c || !bytes) return fail(PHOS_E_INVAL, "phos_manifest_write: NULL argument");
+  if (protocol > PHOS_RECOPY) return fail(PHOS_E_INVAL, "unknown protocol %u", protocol);
+  const uint64_t need = manifest_bytes(c->bufs.size());
+  *bytes = need;
+  if (!out) return PHOS_OK;  // size query
+  if (cap < need) return fail(PHOS_E_OVERFLOW, "manifest needs %llu bytes", (unsigned long long)need);
+  std::vector<uint8_t> m(need);
+  ManifestHead h;
+  memcpy(h.magic, kManifestMagic, 8);
+  h.version = 1;
+  h.protocol = protocol;
+  h.page_bytes = c->page_bytes;
+  h.n_buffers = (uint32_t)c->bufs.size();
+  h.image_bytes = c->image_bytes;
+  memcpy(m.data(), &h, sizeof h);
+  uint8_t *p = m.data() + sizeof h;
+  for (const phos_buffer &b : c->bufs) {
+    const uint64_t rel[2] = {b.base - c->pool_base, b.bytes};
+    memcpy(p, rel, 16);
+    p += 16;
+  }
+  const uint64_t sum = fnv1a(m.data(), need - 8);
+  memcpy(p, &sum, 8);
+  memcpy(out, m.data(), need);
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_manifest_check(phos_ctx *c, const void *manifest, uint64_t bytes) {
+  if (!c || !manifest) return fail(PHOS_E_INVAL, "phos_manifest_check: NULL argument");
+  const uint8_t *m = static_cast<const uint8_t *>(manifest);
+  ManifestHead h;
+  if (bytes < sizeof h + 8) return fail(PHOS_E_INVAL, "manifest: %llu bytes is too short",
+                                        (unsigned long long)bytes);
+  memcpy(&h, m, sizeof h);
+  if (memcmp(h.magic, kManifestMagic, 8) || h.version != 1)
+    return fail(PHOS_E_INVAL, "manifest: not an image manifest of this format");
+  if (bytes != manifest_bytes(h.n_buffers))
+    return fail(PHOS_E_INVAL, "manifest: %llu bytes for %u buffers", (unsigned long long)bytes,
+                h.n_buffers);
+  uint64_t sum;
+  memcpy(&sum, m + bytes - 8, 8);
+  if (sum != fnv1a(m, bytes - 8)) return fail(PHOS_E_INVAL, "manifest: checksum mismatch");
+  if (h.page_bytes != c->page_bytes || h.n_buffers != c->bufs.size() ||
+      h.image_bytes != c->image_bytes)
+    return fail(PHOS_E_INVAL, "manifest: image of %u buffers, %llu bytes, %u-byte pages; this "
+                "context has %zu buffers, %llu bytes, %u-byte pages", h.n_buffers,
+                (unsigned long long)h.image_bytes, h.page_bytes, c->bufs.size(),
+                (unsigned long long)c->image_bytes, c->page_bytes);
+  // buffer i of the image goes to registered buffer i: their sizes must agree
+  // (their places in the pool may differ from the checkpointed process's)
+  for (uint32_t i = 0; i < h.n_buffers; ++i) {
+    uint64_t rel[2];
+    memcpy(rel, m + sizeof h + 16ull * i, 16);
+    if (rel[1] != c->bufs[i].bytes)
+      return fail(PHOS_E_INVAL, "manifest: buffer %u holds %llu bytes in the image, %llu here", i,
+                  (unsigned long long)rel[1], (unsigned long long)c->bufs[i].bytes);
+  }
+  return PHOS_OK;
 }
 
 extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
@@ -904,7 +1184,7 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
   a.state = s.state;
   a.img_page = c->d_img_page;
   a.stat = stat;
-  a.err = c->d_err;
+  a.err = c->d_err + kErrWait;
   a.page_shift = c->page_shift;
   a.n_pages = c->n_pages;
   a.to_image = to_image ? 1u : 0u;
@@ -1266,11 +1546,17 @@ extern "C" phos_status phos_ckpt_precopy_final(phos_ckpt *k, const phos_spec *up
   return PHOS_OK;
 }
 
-static phos_status read_err(phos_ctx *c, hipStream_t s, bool *timeout) {
-  HIP_TRY(hipMemcpyAsync(c->h_pinned + 8, c->d_err, 4, hipMemcpyDeviceToHost, s));
+// Read (after the work enqueued on s) and clear the status words of a
+// checkpoint or restore: the expired-wait word, and with misspec != nullptr
+// the misspeculation word.
+static phos_status read_err(phos_ctx *c, hipStream_t s, bool *timeout, bool *misspec = nullptr) {
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 8, c->d_err, 4 * kErrWords, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *timeout = (((uint32_t *)(c->h_pinned + 8))[0] & 1u) != 0;
-  if (*timeout) HIP_TRY(hipMemsetAsync(c->d_err, 0, 4, s));
+  const uint32_t *w = reinterpret_cast<const uint32_t *>(c->h_pinned + 8);
+  *timeout = w[kErrWait] != 0;
+  if (misspec) *misspec = w[kErrMisspec] != 0;
+  if (*timeout) HIP_TRY(launch_fill_u32(c->d_err + kErrWait, 1, 0, s));
+  if (misspec && *misspec) HIP_TRY(launch_fill_u32(c->d_err + kErrMisspec, 1, 0, s));
   HIP_TRY(hipStreamSynchronize(s));
   return PHOS_OK;
 }
@@ -1346,14 +1632,18 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     stats->staged_pages = k->stage ? std::min<uint64_t>(c->h_pinned[6], k->stage_cap) : 0;
     stats->image_bytes = c->image_bytes;
   }
-  bool timeout = false;
-  TRY(read_err(c, k->copy, &timeout));
+  bool timeout = false, misspec = false;
+  TRY(read_err(c, k->copy, &timeout, k->protocol == PHOS_COW ? &misspec : nullptr));
   c->open_ckpt[k->protocol] = nullptr;
   if (k->bg_done) (void)hipEventDestroy(k->bg_done);
   if (k->d_stage_page) (void)hipFree(k->d_stage_page);
   if (k->d_stage_head) (void)hipFree(k->d_stage_head);
   delete k;
   if (timeout) return fail(PHOS_E_TIMEOUT, "a device-side wait expired; the image is not valid");
+  if (misspec)
+    return fail(PHOS_E_MISSPEC, "a launch wrote outside its speculation into a page the "
+                                "checkpoint had not copied; the image is not the state at the "
+                                "checkpoint's start (take a stop-the-world checkpoint)");
   return PHOS_OK;
 }
 
@@ -1405,6 +1695,14 @@ extern "C" phos_status phos_restore_begin(phos_ctx *c, uint32_t flags, const voi
     return restore_open(c, flags, image, one, 1, cb, copy, out);
   }
   return restore_open(c, flags, image, nullptr, 0, 0, copy, out);
+}
+
+extern "C" phos_status phos_restore_begin_manifest(phos_ctx *c, uint32_t flags, const void *image,
+                                                   const void *manifest, uint64_t manifest_bytes,
+                                                   hipStream_t copy, phos_rst **out) {
+  if (out) *out = nullptr;
+  TRY(phos_manifest_check(c, manifest, manifest_bytes));
+  return phos_restore_begin(c, flags, image, copy, out);
 }
 
 extern "C" phos_status phos_restore_begin_chunked(phos_ctx *c, uint32_t flags,

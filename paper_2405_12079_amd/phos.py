@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libphos.so")
 OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_OVERFLOW, E_MISSPEC, E_TIMEOUT = range(8)
 R, W = 1, 2
 ARG_SCALAR, ARG_PTR_CONST, ARG_PTR_MUT, ARG_STRUCT, ARG_RANGE = 0, 1, 2, 3, 4
-V_READS, V_WRITES, V_TRACK = 1, 2, 4
+V_READS, V_WRITES, V_TRACK, V_SYNC = 1, 2, 4, 8
 COW, RECOPY = 1, 2
 CKPT_DEFER_BACKGROUND = 1
 RST_DEFER_BACKGROUND, RST_PREFETCH_SPEC = 1, 2
@@ -82,6 +82,7 @@ SIGNATURES = [
     ("phos_validate", [P, U32, P, U64, U32, P, U64, P, P]),
     ("phos_twin_scale_add", [P, U32, P, P, P, U64, U32, P, U64, P, P]),
     ("phos_validate_batch", [P, P, P, P, U32, U32, P, U64, P, P]),
+    ("phos_stream_status", [P, P]),
     ("phos_track_reset", [P, P]),
     ("phos_track_read", [P, U32, P, U64]),
     ("phos_ckpt_begin", [P, U32, U32, P, P, P, PP]),
@@ -94,6 +95,9 @@ SIGNATURES = [
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
+    ("phos_manifest_write", [P, U32, P, U64, ctypes.POINTER(U64)]),
+    ("phos_manifest_check", [P, P, U64]),
+    ("phos_restore_begin_manifest", [P, U32, P, P, U64, P, PP]),
     ("phos_restore_begin_chunked", [P, U32, P, U32, U64, P, PP]),
     ("phos_restore_on_demand", [P, U32, P, U64, P, P]),
     ("phos_restore_present", [P, P, U64]),
@@ -110,6 +114,8 @@ SIGNATURES = [
     ("phos_seglist_create", [ctypes.c_int, P, U64, PP]),
     ("phos_seglist_destroy", [P]),
     ("phos_copy_plain", [P, U64, U32, P]),
+    ("phos_copy_batch", [P, P, U64, P]),
+    ("phos_copy_batch_tuned", [P, P, U64, P]),
     ("phos_batch_tune", [ctypes.c_int, P, U64, ctypes.c_char_p, P, ctypes.POINTER(ctypes.c_double)]),
 ]
 
@@ -251,6 +257,10 @@ def phos_twin_scale_add(ctx, spec, x, y, idx, n, flags, out=None, cap=0, n_viola
           _ptr(n_violations), _stream(stream))
 
 
+def phos_stream_status(ctx, stream=None) -> None:
+    _call("phos_stream_status", ctx, _stream(stream))
+
+
 def phos_track_reset(ctx, stream=None) -> None:
     _call("phos_track_reset", ctx, _stream(stream))
 
@@ -313,6 +323,25 @@ def phos_ckpt_copied(ck, n_pages: int) -> np.ndarray:
 def phos_restore_begin(ctx, flags, image, copy_stream) -> int:
     out = ctypes.c_void_p()
     _call("phos_restore_begin", ctx, flags, _ptr(image), _stream(copy_stream), ctypes.byref(out))
+    return out.value
+
+
+def phos_manifest_write(ctx, protocol: int = 0) -> bytes:
+    n = U64()
+    _call("phos_manifest_write", ctx, protocol, None, 0, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(n.value)
+    _call("phos_manifest_write", ctx, protocol, buf, n.value, ctypes.byref(n))
+    return buf.raw[:n.value]
+
+
+def phos_manifest_check(ctx, manifest: bytes) -> None:
+    _call("phos_manifest_check", ctx, manifest, len(manifest))
+
+
+def phos_restore_begin_manifest(ctx, flags, image, manifest: bytes, copy_stream) -> int:
+    out = ctypes.c_void_p()
+    _call("phos_restore_begin_manifest", ctx, flags, _ptr(image), manifest, len(manifest),
+          _stream(copy_stream), ctypes.byref(out))
     return out.value
 
 
@@ -409,6 +438,15 @@ def phos_seglist_destroy(l) -> None:
 
 def phos_copy_plain(l, chunk_bytes: int, threads: int, stream=None) -> None:
     _call("phos_copy_plain", l, chunk_bytes, threads, _stream(stream))
+
+
+def phos_copy_batch(ctx, d_segs, nseg: int, stream=None) -> None:
+    """d_segs: device memory holding nseg SEG_DTYPE entries."""
+    _call("phos_copy_batch", ctx, _ptr(d_segs), nseg, _stream(stream))
+
+
+def phos_copy_batch_tuned(ctx, d_segs, nseg: int, stream=None) -> None:
+    _call("phos_copy_batch_tuned", ctx, _ptr(d_segs), nseg, _stream(stream))
 
 
 def phos_batch_tune(device, segs: np.ndarray, cache_path: Optional[str] = None):

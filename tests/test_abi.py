@@ -31,9 +31,11 @@ def phos():
 def test_header_declares_the_boundary():
     names = _declared()
     for core in ("phos_create", "phos_destroy", "phos_buffers_register", "phos_spec_register",
-                 "phos_validate", "phos_validate_batch", "phos_ckpt_begin", "phos_ckpt_cow",
-                 "phos_ckpt_recopy", "phos_ckpt_end", "phos_restore_begin",
-                 "phos_restore_on_demand", "phos_restore_end", "phos_last_error"):
+                 "phos_spec_release", "phos_validate", "phos_validate_batch", "phos_ckpt_begin",
+                 "phos_ckpt_cow", "phos_ckpt_recopy", "phos_ckpt_end", "phos_restore_begin",
+                 "phos_restore_on_demand", "phos_restore_end", "phos_copy_batch",
+                 "phos_copy_batch_tuned", "phos_stream_status", "phos_manifest_write",
+                 "phos_manifest_check", "phos_last_error"):
         assert core in names, core
 
 
@@ -96,3 +98,24 @@ def test_create_rejects_bad_pools(phos, base, nbytes, page, why):
 
 def test_create_rejects_null_out(phos):
     assert phos.lib().phos_create(0, 1 << 30, 1 << 30, 65536, None) == phos.E_INVAL
+
+
+def test_status_codes_and_flags_match_the_header(phos):
+    """The binding's constants are the header's values (E_OVERFLOW and
+    E_MISSPEC included, which asynchronous calls report later)."""
+    text = open(HEADER).read()
+    for name, val in (("PHOS_E_OVERFLOW", phos.E_OVERFLOW), ("PHOS_E_MISSPEC", phos.E_MISSPEC),
+                      ("PHOS_E_TIMEOUT", phos.E_TIMEOUT), ("PHOS_V_SYNC", phos.V_SYNC),
+                      ("PHOS_V_TRACK", phos.V_TRACK)):
+        m = re.search(name + r"\s*=\s*(\d+)u?", text)
+        assert m and int(m.group(1)) == val, name
+
+
+def test_manifest_and_batch_calls_check_before_device_work(phos):
+    lib = phos.lib()
+    n = ctypes.c_uint64(0)
+    assert lib.phos_manifest_write(None, 1, None, 0, ctypes.byref(n)) == phos.E_INVAL
+    assert lib.phos_manifest_check(None, b"PHOSIMG1", 8) == phos.E_INVAL
+    assert lib.phos_copy_batch(None, None, 0, None) == phos.E_INVAL
+    assert lib.phos_copy_batch_tuned(None, None, 0, None) == phos.E_INVAL
+    assert lib.phos_stream_status(None, None) == phos.E_INVAL

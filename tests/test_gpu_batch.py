@@ -142,3 +142,55 @@ def test_batch_rejects_misaligned_segments(work):
             phos.phos_batch_load(b, bad)
     finally:
         phos.phos_batch_destroy(b)
+
+
+def _small_ctx(torch, phos):
+    """A context for the device-segment batch calls (their pool is not used)."""
+    back = torch.empty(2 * PAGE, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + PAGE - 1) // PAGE * PAGE
+    return back, phos.phos_create(0, base, PAGE, PAGE)
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_copy_batch_device_segments_match_oracle(work, tuned):
+    """phos_copy_batch / phos_copy_batch_tuned with the segments in device
+    memory: the deltas equal the oracle's gather on three calls in a row (the
+    tuned one replays its graph after the first); a malformed segment makes a
+    call copy nothing and phos_stream_status report E_INVAL, once."""
+    import torch
+    from paper_2405_12079_amd import phos
+    reqs, src, dst_bytes, want = work
+    dst = torch.zeros(dst_bytes, dtype=torch.uint8, device="cuda")
+    segs = _segs_for(reqs, src, dst)
+    d_segs = torch.from_numpy(segs.view(np.uint8).copy()).cuda()
+    back, ctx = _small_ctx(torch, phos)
+    s = torch.cuda.Stream()
+    call = phos.phos_copy_batch_tuned if tuned else phos.phos_copy_batch
+    try:
+        for rep in range(3):
+            dst.zero_()
+            torch.cuda.synchronize()
+            call(ctx, d_segs, len(segs), s)
+            s.synchronize()
+            assert np.array_equal(dst.cpu().numpy(), want), f"call {rep}"
+            phos.phos_stream_status(ctx, s)
+        bad = segs.copy()
+        bad["bytes"][len(bad) // 2] += np.uint64(8)
+        d_bad = torch.from_numpy(bad.view(np.uint8).copy()).cuda()
+        dst.zero_()
+        torch.cuda.synchronize()
+        if tuned:  # the first call for these segments checks them on the host
+            with pytest.raises(phos.PhosError) as e:
+                call(ctx, d_bad, len(bad), s)
+            assert e.value.status == phos.E_INVAL
+        else:
+            call(ctx, d_bad, len(bad), s)
+            with pytest.raises(phos.PhosError) as e:
+                phos.phos_stream_status(ctx, s)
+            assert e.value.status == phos.E_INVAL
+        phos.phos_stream_status(ctx, s)  # reported once
+        assert int(dst.count_nonzero().item()) == 0
+        call(ctx, d_segs, 0, s)  # nothing to copy
+    finally:
+        torch.cuda.synchronize()
+        phos.phos_destroy(ctx)

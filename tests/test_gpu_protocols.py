@@ -540,6 +540,96 @@ def test_concurrent_restore_config1(env, mode):
     assert np.array_equal(got[inbuf], host[inbuf]), "restored pool + launches != oracle"
 
 
+def test_restore_wait_timeout_ends_every_wait():
+    """Section 6, failure handling forced from the host: launches wait for
+    pages of a pageable image that the host's DMA has not brought in yet,
+    under a device wait budget of one poll.  Every wait gives up, every
+    kernel exits normally, the restore reports PHOS_E_TIMEOUT within seconds,
+    and the device and the context keep working afterwards."""
+    import os
+    import time
+    from paper_2405_12079_amd import phos
+    w = synth.config1_world()
+    old = os.environ.get("PHOS_SPIN_LIMIT")
+    os.environ["PHOS_SPIN_LIMIT"] = "1"  # read when the context is created
+    try:
+        env = Env(w)
+    finally:
+        if old is None:
+            del os.environ["PHOS_SPIN_LIMIT"]
+        else:
+            os.environ["PHOS_SPIN_LIMIT"] = old
+    T = env.T
+    try:
+        launches = synth.config1_launches(w)[:4]
+        recs = env.records(launches, N)
+        host = synth.content_host(w.seed, 0, w.pool_bytes)
+        image = T.from_numpy(oracle.snapshot(host, env.base, env.table))  # pageable: DMA only
+        T.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = phos.phos_restore_begin(env.ctx, 0, image, env.copy)
+        for j, L in enumerate(launches):
+            s = env.spec(L)
+            phos.phos_restore_on_demand(rs, s, recs[j * N:(j + 1) * N], N, env.app, None)
+            phos.phos_spec_release(env.ctx, s)
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_restore_end(rs, env.app)
+        assert e.value.status == phos.E_TIMEOUT
+        assert time.perf_counter() - t0 < 30
+        # the error was consumed; the device and the context still work
+        T.cuda.synchronize()
+        x = T.arange(1 << 20, device="cuda", dtype=T.int64)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+        image_d = image.cuda()
+        rs = phos.phos_restore_begin(env.ctx, 0, image_d, env.copy)
+        phos.phos_restore_end(rs, env.app)
+        got = env.pool_host()
+        inbuf = np.repeat(_buffer_pages(env).astype(bool), w.page_bytes)
+        assert np.array_equal(got[inbuf], host[inbuf])
+    finally:
+        env.close()
+
+
+def test_image_manifest_guards_the_restore(env):
+    """Section 2.2: the image holds the buffers' bytes only; its manifest
+    names them.  A restore through the manifest of the same buffers gives
+    the image back; a damaged manifest, or one written for other buffers, is
+    refused before anything is copied."""
+    phos, w, T = env.phos, env.world, env.T
+    host = synth.content_host(w.seed, 0, w.pool_bytes)
+    image = T.from_numpy(oracle.snapshot(host, env.base, env.table)).cuda()
+    m = phos.phos_manifest_write(env.ctx, phos.COW)
+    assert len(m) == 32 + 16 * w.n_alloc + 8 and m[:8] == b"PHOSIMG1"
+    phos.phos_manifest_check(env.ctx, m)
+    for bad in (m[:-1] + bytes([m[-1] ^ 1]), m[:40] + bytes([m[40] ^ 1]) + m[41:], m[:-8]):
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_manifest_check(env.ctx, bad)
+        assert e.value.status == phos.E_INVAL
+    # the same buffer sizes at other places in the pool: accepted (an image
+    # maps buffer i to buffer i); one buffer of another size: refused
+    other = Env(synth.config1_world())
+    try:
+        bufs = other.world.buffers(other.base)
+        phos.phos_manifest_check(other.ctx, m)
+        b0, n0 = bufs[0]
+        phos.phos_buffers_register(other.ctx, [(b0, n0 + w.page_bytes)] + bufs[1:]
+                                   if bufs[1][0] >= b0 + n0 + w.page_bytes else bufs[:-1])
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_manifest_check(other.ctx, m)
+        assert e.value.status == phos.E_INVAL
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_restore_begin_manifest(other.ctx, 0, image, m, other.copy)
+        assert e.value.status == phos.E_INVAL
+    finally:
+        other.close()
+    env.pool.zero_()
+    T.cuda.synchronize()
+    rs = phos.phos_restore_begin_manifest(env.ctx, 0, image, m, env.copy)
+    phos.phos_restore_end(rs, env.app)
+    got = env.pool_host()
+    assert np.array_equal(oracle.snapshot(got, env.base, env.table), image.cpu().numpy())
+
+
 def test_restore_without_launches_is_the_image(env):
     phos, w, T = env.phos, env.world, env.T
     host = synth.content_host(w.seed, 0, w.pool_bytes)

@@ -194,3 +194,42 @@ def test_twin_rejects_bad_arguments(env1):
         phos.phos_twin_scale_add(env.ctx, 99999, env.base, env.base, 0, 8, 2, out.data_ptr(), 4,
                                  cnt.data_ptr(), env.app)
     assert e.value.status == phos.E_INVAL
+
+
+@pytest.mark.parametrize("inject", [0, 3])
+def test_twin_write_out_of_speculation_during_copy_on_write_is_a_misspeculation(env1, inject):
+    """Section 4.2 with the validator inside the kernel: a copy-on-write
+    checkpoint is open (background copy deferred, so only what copy-on-write
+    takes is copied), copy-on-write takes the launch's write pages, then the
+    twin runs.  Writes out of speculation into other buffers land on pages
+    the checkpoint has not copied: phos_ckpt_end reports PHOS_E_MISSPEC.
+    With none, the image is the snapshot at t1.  The next checkpoint starts
+    clean either way."""
+    env, w, phos, T = env1, env1.world, env1.phos, env1.T
+    xo, yo, io, j, args, n = _case(env, 40_000, inject, True, 0, seed=11 + inject)
+    spec = phos.phos_spec_register(env.ctx, 9, args)
+    image = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
+    try:
+        # the index array the kernel reads is part of the state at t1
+        env.pool.view(T.int64)[io // 8: io // 8 + n] = T.from_numpy(j).to("cuda")
+        t1 = oracle.snapshot(env.pool_host(), env.base, env.table)
+        ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, image, None,
+                                  env.copy)
+        phos.phos_ckpt_cow(ck, spec, env.app)
+        _run(env, xo, yo, io, j, n, spec, RW_T, True, 64)
+        if inject:
+            with pytest.raises(phos.PhosError) as e:
+                phos.phos_ckpt_end(ck, env.app)
+            assert e.value.status == phos.E_MISSPEC
+        else:
+            phos.phos_ckpt_end(ck, env.app)
+            assert np.array_equal(image.cpu().numpy(), t1)
+        # a later checkpoint with no instrumented launch in it ends cleanly
+        ck = phos.phos_ckpt_begin(env.ctx, phos.COW, 0, image, None, env.copy)
+        phos.phos_ckpt_end(ck, env.app)
+        assert np.array_equal(image.cpu().numpy(),
+                              oracle.snapshot(env.pool_host(), env.base, env.table))
+    finally:
+        env.pool.copy_(env.T.from_numpy(synth.content_host(w.seed, 0, w.pool_bytes)).to("cuda"))
+        env.T.cuda.synchronize()
+        phos.phos_spec_release(env.ctx, spec)

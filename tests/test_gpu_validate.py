@@ -188,12 +188,39 @@ def test_validate_naming_nothing_overflows_lds_lists(env1):
 
 
 def test_validate_reports_true_count_beyond_cap(env1):
+    """More violations than cap (Section 4.1 reports into a buffer of fixed
+    size): the true count comes back, phos_stream_status reports
+    PHOS_E_OVERFLOW once, and PHOS_V_SYNC reports it from the call itself;
+    a call within its cap reports nothing."""
+    from paper_2405_12079_amd import phos
     L = synth.config1_launches(env1.world, 1, 1_000_000)[0]
     recs = env1.records([L], 1_000_000)
-    n, _ = _validate_one(env1, L, recs, 1_000_000, cap=10)
     iv = oracle.spec_build(env1.table, L.arg_values(env1.base))
     want = oracle.validate(iv, synth.records_host(env1.hw, L), env1.table, L.k)
+    phos.phos_stream_status(env1.ctx, env1.app)  # nothing pending
+    n, _ = _validate_one(env1, L, recs, 1_000_000, cap=10)
     assert n == len(want) > 10
+    with pytest.raises(phos.PhosError) as e:
+        phos.phos_stream_status(env1.ctx, env1.app)
+    assert e.value.status == phos.E_OVERFLOW
+    phos.phos_stream_status(env1.ctx, env1.app)  # reported once
+    out, cnt = env1.violations_buffers(len(want))
+    s = env1.spec(L)
+    try:
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_validate(env1.ctx, s, recs, 1_000_000, FLAGS | phos.V_SYNC, out, 10, cnt,
+                               env1.app)
+        assert e.value.status == phos.E_OVERFLOW and int(cnt.item()) == len(want)
+        phos.phos_validate(env1.ctx, s, recs, 1_000_000, FLAGS | phos.V_SYNC, out, len(want),
+                           cnt, env1.app)
+        n, got = Env.read_violations(out, cnt, len(want))
+        assert n == len(want) and np.array_equal(got, want)
+        with pytest.raises(phos.PhosError) as e:  # the V_SYNC overflow is also sticky
+            phos.phos_stream_status(env1.ctx, env1.app)
+        assert e.value.status == phos.E_OVERFLOW
+        phos.phos_stream_status(env1.ctx, env1.app)
+    finally:
+        phos.phos_spec_release(env1.ctx, s)
 
 
 @pytest.mark.parametrize("flags", [1, 2])

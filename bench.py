@@ -37,11 +37,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, GB/s
-# Host threads for the oracle's parity replays and the CPU baseline: the CPUs
-# this process may run on, at most 16 (the host share of one GPU on the
-# MI355X boxes measured here; more threads would time cores not allotted to
-# this job).
-HOST_THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def host_cpu_share():
+    """CPUs this process may use: (threads, detail).  The scheduler affinity
+    bounds it, and a cgroup CPU quota (cpu.max: quota per period) bounds it
+    further: threads beyond the quota would share the same CPU time, so the
+    oracle would be timed on cores the job is not given."""
+    affinity = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+        if q != "max":
+            quota = max(1, int(int(q) // int(period)))
+    except (OSError, ValueError):
+        pass
+    threads = max(1, min(affinity, quota) if quota else affinity)
+    return threads, {"host_cpus": os.cpu_count(), "affinity_cpus": affinity,
+                     "cgroup_cpu_quota": quota}
+
+
+# Host threads for the oracle's parity replays and the CPU baseline.
+HOST_THREADS, HOST_CPU_DETAIL = host_cpu_share()
 KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
 
 
@@ -125,10 +143,11 @@ class HipGraph:
             self.hip.hipGraphDestroy(self.graph)
 
 
-def copy_roofs(torch, phos, nbytes=4 << 30, reps=5):
-    """Practical HBM copy roofs on this GPU: the runtime's device-to-device copy
-    and one contiguous segment through the persistent batch kernel
-    (GB/s of HBM traffic = 2 x bytes copied / time)."""
+def copy_samples(torch, phos, nbytes=4 << 30, reps=5):
+    """Sample HBM copy rates on this GPU, for context (not ceilings: a tuned
+    kernel can beat them): the runtime's device-to-device copy and one
+    contiguous segment through the persistent batch kernel (GB/s of HBM
+    traffic = 2 x bytes copied / time)."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     src.fill_(7)
@@ -279,6 +298,8 @@ def run_training_step(args):
             phos.phos_ckpt_cow(ca, specs[j], app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 
+    e_first = torch.cuda.Event(enable_timing=True)  # launch 0 may start
+
     def app_loop(ca, cb):
         if vstream is not None:
             return app_loop_pipelined(ca, cb)
@@ -296,6 +317,8 @@ def run_training_step(args):
                 ahead = min((j // chunk + 1) * chunk, n_launch) - j  # validated, still to come
                 phos.phos_ckpt_precopy_final(cb, specs[j:], ahead, app)
             phos.phos_ckpt_cow(ca, specs[j], app)
+            if j == 0:
+                e_first.record(app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 
     warm = False
@@ -340,8 +363,10 @@ def run_training_step(args):
         ts0 = time.perf_counter()
         sa, sb = step()  # ends with both checkpoints finished (synchronous)
         step_s.append(time.perf_counter() - ts0)
+        stall = t_app.e0.elapsed_time(e_first) if not (args.app_graph or vstream) else float("nan")
         rows.append(dict(bg_a=t_bg_a.ms(), bg_b=t_bg_b.ms(), app=t_app.ms(),
-                         rec=t_rec.ms(), bg_a_pages=sa.bg_pages, cow_pages=sa.cow_pages,
+                         rec=t_rec.ms(), stall_t1=stall, bg_a_pages=sa.bg_pages,
+                         cow_pages=sa.cow_pages,
                          bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages,
                          precopy_pages=sb.precopy_pages))
         log(f"[bench] step {i}: " + ", ".join(f"{k}={v:.3f}" if isinstance(v, float) else f"{k}={v}"
@@ -386,6 +411,36 @@ def run_training_step(args):
     app_alone_ms = float(np.median(ts))
     log(f"[bench] background copy alone {bg_alone_ms:.3f} ms; application launches alone "
         f"{app_alone_ms:.3f} ms")
+    # The stop-the-world step the method replaces, in the same run: the
+    # application stops while image A is copied (the library's background
+    # copy with nothing beside it, its fastest whole-image copy), runs its
+    # launches (no checkpoint open, so no validation), and stops again while
+    # image B is copied.  Each part is timed with HIP events on its stream;
+    # the sum leaves out the host's gaps between them.
+    stw = []
+    t_stw = [Timer(torch, cpy), Timer(torch, app), Timer(torch, cpy)]
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t_stw[0].start()
+        ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
+        t_stw[0].stop()
+        phos.phos_ckpt_end(ck, cpy)
+        app.wait_stream(cpy)
+        t_stw[1].start()
+        for j, L in enumerate(launches):
+            synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
+        t_stw[1].stop()
+        cpy.wait_stream(app)
+        t_stw[2].start()
+        ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_b, None, cpy)
+        t_stw[2].stop()
+        phos.phos_ckpt_end(ck, cpy)
+        torch.cuda.synchronize()
+        stw.append([t.ms() for t in t_stw])
+    stw_parts = np.median(np.array(stw), axis=0)
+    stw_ms = float(np.median([sum(x) for x in stw]))
+    log(f"[bench] stop-the-world step {stw_ms:.3f} ms (copy A {stw_parts[0]:.3f}, launches "
+        f"{stw_parts[1]:.3f}, copy B {stw_parts[2]:.3f})")
     # the Section 5 drain of a finished image to pinned host memory (PCIe)
     host_img = pinned_tensor(torch, nimg)
     ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, host_img.data_ptr(), cpy)
@@ -394,8 +449,8 @@ def run_training_step(args):
     phos.phos_ckpt_end(ca, cpy)
     d2h_s = time.perf_counter() - t0d
     log(f"[bench] D2H drain of the image: {nimg / d2h_s / 1e9:.1f} GB/s")
-    roofs = copy_roofs(torch, phos)
-    log(f"[bench] copy roofs: {roofs}")
+    roofs = copy_samples(torch, phos)
+    log(f"[bench] contiguous copy samples: {roofs}")
 
     # checkpoint image bytes finished per step (two images), and the bytes
     # actually copied into them
@@ -441,6 +496,21 @@ def run_training_step(args):
         "validated_addr_per_s": round(n_addr / (alone["track"] / 1e3), 1),
         "validation_ms_alone": {k: round(v, 4) for k, v in alone.items()},
         "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
+        "stop_the_world_step_ms": round(stw_ms, 3),
+        "stop_the_world_parts_ms": {"copy_A": round(float(stw_parts[0]), 3),
+                                    "launches": round(float(stw_parts[1]), 3),
+                                    "copy_B": round(float(stw_parts[2]), 3)},
+        # the application's stall where the checkpoint opens (t1): from the
+        # step's start on the application stream to the moment launch 0 may
+        # run (its accesses validated, its copy-on-write done); stop-the-world
+        # stalls for the whole copy of image A
+        "stall_t1_ms": {"concurrent": round(float(np.nanmedian([r["stall_t1"] for r in rows])), 3)
+                        if rows and not np.isnan(rows[0]["stall_t1"]) else None,
+                        "stop_the_world": round(float(stw_parts[0]), 3)},
+        # downtime at the re-quiesce (t2): from the application's last launch
+        # to the recopy's end; stop-the-world copies the whole image B there
+        "downtime_t2_ms": {"concurrent": round(rec_ms, 3),
+                           "stop_the_world": round(float(stw_parts[2]), 3)},
         "recopy_ms": round(rec_ms, 3),
         "recopy_pages": int(np.mean([r["recopy_pages"] for r in rows])),
         "precopy": {"rounds": ((nchunk - 1) if args.precopy else 0) + len(final_at),
@@ -448,7 +518,7 @@ def run_training_step(args):
                     "pages": int(np.mean([r["precopy_pages"] for r in rows]))},
         "app_loop_graph": bool(args.app_graph),
         "launches_per_validation_call": chunk,
-        "copy_roofs": roofs,
+        "copy_samples": dict(roofs, note="contiguous 4 GiB copies for context; not ceilings"),
         "violations_per_step": nviol,
         "image_bytes_per_step": int(img_bytes),
         "bytes_copied_into_images_per_step": int(copied_bytes),
@@ -476,11 +546,12 @@ def run_training_step(args):
                               "traffic": measured_traffic("validate_kernel", "training_step")},
         # the recopy at the re-quiesce: page list + gather, from the
         # application's last launch to the recopy's end
-        "roofline_recopy": {"bound": "hbm", "kernel": "gather_pages_kernel (+ page list), recopy",
-                            "achieved": round(2 * rec_bytes / rec_ms / 1e6, 1),
-                            "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                            "frac": round(2 * rec_bytes / rec_ms / 1e6 / HBM_PEAK_GBPS, 4),
-                            "traffic": measured_traffic("gather_pages_kernel", "training_step")},
+        # (no fraction of the roofline: a working set under 1 GiB partly sits
+        # in the 256 MB last-level cache)
+        "recopy_rate": {"kernel": "gather_pages_kernel (+ page list), recopy",
+                        "achieved": round(2 * rec_bytes / rec_ms / 1e6, 1), "unit": "GB/s",
+                        "working_set_bytes": int(2 * rec_bytes),
+                        "traffic": measured_traffic("gather_pages_kernel", "training_step")},
     }
     if graph is not None:
         graph.close()
@@ -490,6 +561,54 @@ def run_training_step(args):
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_training_step(w, launches, base, img_bytes, n_addr)
     return result
+
+
+def config1_validation_rate(reps=5):
+    """Validated addresses per second on the plain tiny workload (64 MiB pool
+    of 256 buffers, 4 KiB pages, 100 launches x 10^6 accesses, tracked), one
+    batched call over all launches, median of `reps` after one warm-up.  Its
+    800 MB of records is under the 1 GiB floor for roofline claims."""
+    import torch
+
+    import synth
+    from paper_2405_12079_amd import phos
+    w = synth.config1_world()
+    n_launch, n_rec = 100, 1_000_000
+    launches = synth.config1_launches(w, n_launch, n_rec)
+    page = w.page_bytes
+    back = torch.empty(w.pool_bytes + page, dtype=torch.uint8, device="cuda")
+    base = (back.data_ptr() + page - 1) // page * page
+    recs = synth.records_device(synth.DeviceWorld(w, base), launches, n_rec)
+    ctx = phos.phos_create(0, base, w.pool_bytes, page)
+    try:
+        phos.phos_buffers_register(ctx, w.buffers(base))
+        specs = [phos.phos_spec_register(ctx, L.k, L.arg_values(base)) for L in launches]
+        ptrs = [recs.data_ptr() + j * n_rec * 8 for j in range(n_launch)]
+        cap = 400_000
+        out = torch.empty(cap * 32, dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        s = torch.cuda.Stream()
+        t = Timer(torch, s)
+        ts = []
+        for _ in range(reps + 1):
+            t.start()
+            phos.phos_validate_batch(ctx, specs, ptrs, [n_rec] * n_launch,
+                                     phos.V_READS | phos.V_WRITES | phos.V_TRACK, out, cap,
+                                     cnt.data_ptr(), s)
+            t.stop()
+            s.synchronize()
+            ts.append(t.ms())
+        ms = float(np.median(ts[1:]))
+        nv = int(cnt.item())
+    finally:
+        torch.cuda.synchronize()
+        phos.phos_destroy(ctx)
+    del recs, back
+    torch.cuda.empty_cache()
+    return {"workload": "plain tiny: 64 MiB pool, 256 buffers, 4 KiB pages, "
+                        f"{n_launch} launches x {n_rec} accesses, reads+writes checked, tracked",
+            "validated_addr_per_s": round(n_launch * n_rec / (ms / 1e3), 1),
+            "ms": round(ms, 4), "violations": nv}
 
 
 # ---------------------------------------------------------------- config 3
@@ -564,7 +683,8 @@ def run_batched(args):
     parity = None
     if args.parity:
         torch.cuda.synchronize()
-        dst.fill_(0)
+        with torch.cuda.stream(s):  # the clear and the copy in stream order
+            dst.fill_(0)
         phos.phos_batch_run(b, s)
         s.synchronize()
         t0 = time.perf_counter()
@@ -811,7 +931,8 @@ def run_cold_start(args):
         host = synth.content_host_parallel(w.seed, 0, w.pool_bytes, HOST_THREADS)
         oracle.apply_stream(host, launches, lambda L: synth.records_host(hw, L),
                             lambda p, L, rec: synth.apply_writes_host(p, base, w.seed, L.k, rec),
-                            threads=HOST_THREADS)
+                            threads=HOST_THREADS,
+                            log=lambda j: log(f"[bench] parity: oracle replay at launch {j}"))
         want = oracle.image_hashes_from_pool(host, base, table, page, HOST_THREADS)
         del host
         bad = np.flatnonzero(got != want)
@@ -993,7 +1114,7 @@ def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
     t0 = time.perf_counter()
     validate_some(range(len(sample)))
     t_val = time.perf_counter() - t0
-    T = max(1, min(16, os.cpu_count() or 1))
+    T = HOST_THREADS
     t0 = time.perf_counter()
     with ThreadPoolExecutor(T) as ex:
         list(ex.map(validate_some, [range(t, len(sample), T) for t in range(T)]))
@@ -1032,7 +1153,7 @@ def cpu_baseline_training_step(w, launches, base, img_bytes, n_addr):
             "validated_addr_per_s": round(aT, 1), "snapshot_GBps": round(sT / 1e9, 3),
             "single_thread": {"value": round(gb1, 3), "validated_addr_per_s": round(a1, 1),
                               "snapshot_GBps": round(s1 / 1e9, 3)},
-            "cpu": cpu_model()}
+            "cpu": cpu_model(), **HOST_CPU_DETAIL}
 
 
 def run_twin(args):
@@ -1545,6 +1666,9 @@ def parse_args(argv=None):
     ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",
                     help="config 8: staging budgets in MiB")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
+    ap.add_argument("--step-only", dest="step_only", action="store_true",
+                    help="config 2: only the training step (no plain-tiny validation rate and "
+                         "no batched-uneven latency beside it)")
     ap.add_argument("--app-graph", action="store_true",
                     help="replay the per-launch copy-on-write + application loop as one HIP "
                          "graph (eager is faster: it skips copy-on-write once the background "
@@ -1569,6 +1693,16 @@ def main():
         sys.exit(2)
     if args.config == 2:
         res = run_training_step(args)
+        if not args.step_only:
+            # the metric's other two parts, on their own workloads
+            res["plain_tiny_validation"] = config1_validation_rate()
+            log(f"[bench] plain tiny validation: {res['plain_tiny_validation']}")
+            b = run_batched(parse_args(["--config", "3", "--steps", "5", "--warmup", "1",
+                                        "--no-parity", "--no-cpu-baseline"]))
+            res["batched_uneven"] = {k: b[k] for k in ("config", "batched_ms", "plain_ms",
+                                                       "latency_ms", "tuned", "roofline")}
+            res["batched_uneven"]["steps"] = 5
+            log(f"[bench] batched uneven: {res['batched_uneven']['latency_ms']}")
     elif args.config == 3:
         res = run_batched(args)
     elif args.config == 4:

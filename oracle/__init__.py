@@ -453,15 +453,18 @@ def hash_chunks(read_fn, nbytes: int, page_bytes: int, chunk_bytes: int,
 
 
 def apply_stream(pool: np.ndarray, launches, records_fn, apply_fn, threads: int = 1,
-                 ahead: int = 32) -> None:
+                 ahead: int = 32, log=None, log_every: int = 5000) -> None:
     """Apply launches' writes to a host pool in launch order (the application,
     not the method: each write stores a value fixed by the launch and the
     address).  records_fn(L) is pure, so up to `ahead` launches' records are
-    drawn on `threads` host threads while earlier ones are applied."""
+    drawn on `threads` host threads while earlier ones are applied.  log(j),
+    if given, is called every `log_every` launches."""
     import concurrent.futures as cf
     if threads <= 1:
-        for L in launches:
+        for j, L in enumerate(launches):
             apply_fn(pool, L, records_fn(L))
+            if log is not None and j % log_every == log_every - 1:
+                log(j + 1)
         return
     with cf.ThreadPoolExecutor(threads) as ex:
         futs = {}
@@ -471,6 +474,8 @@ def apply_stream(pool: np.ndarray, launches, records_fn, apply_fn, threads: int 
                 futs[nxt] = ex.submit(records_fn, launches[nxt])
                 nxt += 1
             apply_fn(pool, L, futs.pop(j).result())
+            if log is not None and j % log_every == log_every - 1:
+                log(j + 1)
 
 
 def validate_launches(table: Table, pool_base: int, launches, records_fn, flags: int = V_READS | V_WRITES,
@@ -486,7 +491,7 @@ def validate_launches(table: Table, pool_base: int, launches, records_fn, flags:
 def run_stream_hashed(world, launches, pool_base: int, records_fn, apply_fn, pool: np.ndarray,
                       hash_before: Sequence[int] = (), window: Optional[Tuple[int, int]] = None,
                       flags: int = V_READS | V_WRITES, threads: int = 1,
-                      ahead: int = 16) -> StreamResult:
+                      ahead: int = 16, log=None) -> StreamResult:
     """run_stream for windows too large to snapshot twice on the host: the same
     per-launch definitions (speculation, validation, tracking, then the
     launch's writes, in launch order), with each launch's records drawn,
@@ -494,7 +499,8 @@ def run_stream_hashed(world, launches, pool_base: int, records_fn, apply_fn, poo
     of the writes, and every snapshot replaced by its page fingerprints
     (res.hashes[j], as image_hashes_from_pool).  res.last[p] is the last
     launch position in the window with a failing write inside a buffer on
-    page p (-1: none)."""
+    page p (-1: none).  log(j), if given, is called every 100 launches (a
+    long replay reports its progress)."""
     import concurrent.futures as cf
     table = Table.from_world(world, pool_base)
     npg, page = world.n_pages, world.page_bytes
@@ -532,6 +538,8 @@ def run_stream_hashed(world, launches, pool_base: int, records_fn, apply_fn, poo
                 res.victim[dv[1]] = 1
                 res.last[dv[1]] = j
             apply_fn(pool, L, rec)
+            if log is not None and j % 100 == 99:
+                log(j + 1)
     if len(launches) in hash_before:
         res.hashes[len(launches)] = image_hashes_from_pool(pool, pool_base, table, page, threads)
     return res

@@ -101,7 +101,8 @@ def test_training_step_full_size():
     res = oracle.run_stream_hashed(
         w, launches, base, lambda L: synth.records_host(hw, L),
         lambda p, L, rec: synth.apply_writes_host(p, base, w.seed, L.k, rec), host,
-        hash_before=(0, N_LAUNCH), window=(0, N_LAUNCH), threads=THREADS)
+        hash_before=(0, N_LAUNCH), window=(0, N_LAUNCH), threads=THREADS,
+        log=lambda j: print(f"[scale] oracle replay: {j} launches", flush=True))
     print("[scale] oracle replay done", flush=True)
 
     # both images, every page (Sections 4.2 and 4.3)

@@ -223,6 +223,23 @@ phos_status phos_validate(phos_ctx *ctx, phos_spec spec, const uint64_t *d_recor
                           uint32_t flags, phos_violation *out, uint64_t cap,
                           uint64_t *n_violations, hipStream_t stream);
 
+/* For callers that cannot allocate device memory: code recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same validation as phos_validate (same arguments, results, asynchrony and
+ * flags), but its workspace is a fixed array in device memory, one per GPU,
+ * held until the process ends (about 4 MiB), so the call allocates nothing.
+ * Limits, checked before any device work (PHOS_E_INVAL): cap <= 131,072
+ * violation records, and at most 4,096 validation tiles: 67,108,864 records
+ * per call untracked and 134,217,728 with PHOS_V_TRACK at the default
+ * largest tiles (16,384 and 32,768 records; PHOS_VTILE_MAX).  Every
+ * call on one GPU shares the array and leaves its last contents there;
+ * each call clears the counters it needs first.  Calls that overlap on one
+ * GPU (different streams of one context not ordered by the library, or
+ * different contexts) race on the array and must be ordered by the caller. */
+phos_status phos_validate_noalloc(phos_ctx *ctx, phos_spec spec, const uint64_t *d_records,
+                                  uint64_t n, uint32_t flags, phos_violation *out, uint64_t cap,
+                                  uint64_t *n_violations, hipStream_t stream);
+
 /* Many launches in one pass: launch i uses specs[i], records d_records[i]
  * (n[i] of them); host arrays of nlaunch entries.  Output ordered by
  * (position i in the call, record index). */

@@ -29,6 +29,17 @@ constexpr uint32_t kTrackWords = 8192;           // LDS dirty-bitmap words (32 K
 constexpr uint32_t kSeg = 1024;                  // tiles per scan segment
 constexpr uint32_t kFuseTiles = 4096;            // calls up to this many tiles use one finish kernel
 
+// The fixed workspace of phos_validate_noalloc: one array in device memory
+// per GPU, held until the process ends.  Byte offsets: the append cursor and
+// the segment sums (8 words, cleared by every call), the tile counts and
+// tile offsets of at most kFuseTiles tiles, then kNaViol violation records.
+constexpr uint64_t kNaViol = 1ull << 17;                        // 131,072 records (4 MiB)
+constexpr uint64_t kNaClearWords = 8;                           // cursor + segment sums
+constexpr uint64_t kNaOffCount = 256;
+constexpr uint64_t kNaOffTileOff = kNaOffCount + 4ull * kFuseTiles;
+constexpr uint64_t kNaOffViol = kNaOffTileOff + 8ull * kFuseTiles;
+constexpr uint64_t kNaBytes = kNaOffViol + 32ull * kNaViol;   // 4,243,712 B
+
 // Copy kernels.
 constexpr uint32_t kCThreads = 256;
 constexpr uint32_t kBgCopyThreads = 512;            // copying waves of a background block
@@ -244,6 +255,11 @@ hipError_t launch_segs_prefix(const phos_copy_seg *segs, uint64_t nseg, unsigned
                               unsigned long long *prefix, unsigned long long *cursor,
                               uint32_t *bad, hipStream_t s);
 hipError_t launch_plain_copy(const BatchQ &q, uint64_t nchunks, uint32_t threads, hipStream_t s);
+
+// Device address of this GPU's copy of the fixed validation workspace
+// (kNaBytes).  Looked up once per device, which must be current; later calls
+// return the kept address.
+hipError_t noalloc_workspace(int device, uint8_t **out);
 
 // Completion stamps of a batch's last run ([0] start, [1 + r] request r),
 // host-visible (pinned), and the GPU wall-clock rate in kHz.

@@ -12,6 +12,7 @@
 //   batch_copy        persistent copy of many requests' segments (no paper analog)
 //   twin_kernel       Section 4.1 instrumented twin of an application kernel
 #include <hip/hip_runtime.h>
+#include <mutex>
 
 #include "internal.h"
 #include "util.h"
@@ -1597,6 +1598,36 @@ hipError_t launch_twin(const TwinArgs &a, const DevSpec &spec, uint64_t blocks, 
     case 8: return launch_twin_t<true, 8>(a, spec, blocks, n_cu, s);
     default: return launch_twin_t<true, -1>(a, spec, blocks, n_cu, s);
   }
+}
+
+}  // namespace phos
+
+// ============================================== fixed validation workspace
+// The workspace of phos_validate_noalloc (layout in internal.h): every GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name denotes a host-side stand-in, not device memory, so
+// its only host use is the address lookup below; kernels get the looked-up
+// address.
+static __device__ __align__(256) uint8_t scratch[phos::kNaBytes];
+
+namespace phos {
+
+hipError_t noalloc_workspace(int device, uint8_t **out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static uint8_t *addr[kMaxDevices] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<uint8_t *>(p);
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace phos

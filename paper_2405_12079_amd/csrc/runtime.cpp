@@ -91,6 +91,9 @@ struct phos_ctx {
   // device-side batch met a malformed segment; a write out of speculation
   // landed on a page an open copy-on-write checkpoint had not copied
   uint32_t *d_err = nullptr;
+  // this GPU's fixed validation workspace (phos_validate_noalloc; kNaBytes,
+  // not owned: it lives until the process ends)
+  uint8_t *na_ws = nullptr;
 
   // device-resident segment batches (phos_copy_batch*): [hdr 4][prefix cap+1]
   // and a chunk cursor; tuned calls replay a captured graph per (segments,
@@ -405,6 +408,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
              "hipHostMalloc") ||
       !hipck(hipHostMalloc((void **)&c->h_bounce, kBounceBytes + kDmaRunBytes / 1024,
                            hipHostMallocDefault), "hipHostMalloc") ||
+      !hipck(noalloc_workspace(device, &c->na_ws), "hipGetSymbolAddress (fixed workspace)") ||
       !hipck(hipDeviceSynchronize(), "hipDeviceSynchronize")) {
     ctx_free(c);
     return PHOS_E_HIP;
@@ -798,6 +802,72 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   a.nlaunch = 1;
   a.ntiles = (uint32_t)ntiles;
   TRY(run_validation(c, a, &ds, out, cap, n_violations, stream));
+  if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
+  return PHOS_OK;
+}
+
+// phos_validate with the fixed per-GPU workspace in place of the context's
+// (which grows on demand): nothing is allocated, so the call can be captured
+// into a graph or made where allocation is not allowed.  Limits: at most
+// kFuseTiles tiles (the one-kernel ordering) and a cap of kNaViol records.
+extern "C" phos_status phos_validate_noalloc(phos_ctx *c, phos_spec spec,
+                                             const uint64_t *d_records, uint64_t n,
+                                             uint32_t flags, phos_violation *out, uint64_t cap,
+                                             uint64_t *n_violations, hipStream_t stream) {
+  HostSpec *h = get_spec(c, spec);
+  if (!h) return fail(PHOS_E_INVAL, "phos_validate_noalloc: unknown spec %u", spec);
+  if ((n && !d_records) || (cap && !out) || (((uintptr_t)out) & 15) || !n_violations ||
+      (flags & ~kFlagMask))
+    return fail(PHOS_E_INVAL, "phos_validate_noalloc: bad argument");
+  if (((uintptr_t)d_records) & 7) return fail(PHOS_E_INVAL, "records must be 8-byte aligned");
+  const uint32_t tile = pick_tile(c, n, flags);
+  const uint64_t ntiles = (n + tile - 1) / tile;
+  if (ntiles > kFuseTiles)
+    return fail(PHOS_E_INVAL, "phos_validate_noalloc: %llu records need %llu tiles of %u; the "
+                "fixed workspace holds %u tiles (at most %llu records per call)",
+                (unsigned long long)n, (unsigned long long)ntiles, tile, kFuseTiles,
+                (unsigned long long)kFuseTiles * tile);
+  if (cap > kNaViol)
+    return fail(PHOS_E_INVAL, "phos_validate_noalloc: cap %llu exceeds the fixed workspace's %llu "
+                "violation records", (unsigned long long)cap, (unsigned long long)kNaViol);
+  if (!c->na_ws) return fail(PHOS_E_STATE, "phos_validate_noalloc: no fixed workspace");
+  DeviceGuard g(c->device);
+  DevSpec ds;
+  fill_devspec(*h, &ds);
+  VArgs a = base_vargs(c, flags & kKernelFlags, tile);
+  unsigned long long *clear = reinterpret_cast<unsigned long long *>(c->na_ws);
+  a.cursor = clear;
+  a.seg_sum = clear + 1;
+  a.tile_count = reinterpret_cast<uint32_t *>(c->na_ws + kNaOffCount);
+  a.tile_off = reinterpret_cast<unsigned long long *>(c->na_ws + kNaOffTileOff);
+  a.scratch = reinterpret_cast<phos_violation *>(c->na_ws + kNaOffViol);
+  a.scratch_cap = kNaViol;
+  a.launches = nullptr;
+  a.single.rec = d_records;
+  a.single.n = n;
+  a.single.launch_id = h->launch_id;
+  a.single.tile0 = 0;
+  a.seq0 = ++c->vseq;
+  a.nlaunch = 1;
+  a.ntiles = (uint32_t)ntiles;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(stream, &cs));
+  const bool capturing = cs != hipStreamCaptureStatusNone;
+  // the context's validations run in call order, as with phos_validate
+  if (!capturing && c->v_evt_used && stream != c->v_stream)
+    HIP_TRY(hipStreamWaitEvent(stream, c->v_evt, 0));
+  // the previous call on this GPU left the cursor and sums at zero unless it
+  // failed part-way: clear them (with a kernel, which graph capture takes)
+  HIP_TRY(launch_fill_u64(clear, kNaClearWords, 0, stream));
+  HIP_TRY(launch_validate(a, &ds, (a.flags & PHOS_V_TRACK) != 0, stream));
+  if (a.flags & PHOS_V_TRACK) note_victims(c, stream);
+  HIP_TRY(launch_vfinish(a.tile_count, a.tile_off, a.ntiles, a.scratch, a.scratch_cap, out, cap,
+                         n_violations, a.cursor, a.seg_sum, c->d_err + kErrOverflow, stream));
+  if (!capturing) {
+    HIP_TRY(hipEventRecord(c->v_evt, stream));
+    c->v_evt_used = true;
+    c->v_stream = stream;
+  }
   if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
   return PHOS_OK;
 }

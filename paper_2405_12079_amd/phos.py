@@ -80,6 +80,7 @@ SIGNATURES = [
     ("phos_spec_intervals", [P, U32, P, U32, ctypes.POINTER(U32)]),
     ("phos_spec_release", [P, U32]),
     ("phos_validate", [P, U32, P, U64, U32, P, U64, P, P]),
+    ("phos_validate_noalloc", [P, U32, P, U64, U32, P, U64, P, P]),
     ("phos_twin_scale_add", [P, U32, P, P, P, U64, U32, P, U64, P, P]),
     ("phos_validate_batch", [P, P, P, P, U32, U32, P, U64, P, P]),
     ("phos_stream_status", [P, P]),
@@ -238,6 +239,12 @@ def phos_spec_release(ctx: int, spec: int) -> None:
 # ------------------------------------------------------------- validation
 def phos_validate(ctx, spec, d_records, n, flags, out, cap, n_violations, stream=None) -> None:
     _call("phos_validate", ctx, spec, _ptr(d_records), n, flags, _ptr(out), cap,
+          _ptr(n_violations), _stream(stream))
+
+
+def phos_validate_noalloc(ctx, spec, d_records, n, flags, out, cap, n_violations,
+                          stream=None) -> None:
+    _call("phos_validate_noalloc", ctx, spec, _ptr(d_records), n, flags, _ptr(out), cap,
           _ptr(n_violations), _stream(stream))
 
 

@@ -262,21 +262,23 @@ def run_training_step(args):
     app, cpy = torch.cuda.Stream(), torch.cuda.Stream()
     VFLAGS = phos.V_READS | phos.V_WRITES | phos.V_TRACK
 
-    t_bg_a, t_bg_b = Timer(torch, cpy), Timer(torch, cpy)
+    # the background passes run on the library's own stream: their GPU time
+    # comes back in the checkpoints' stats (bg_ms, HIP events on that stream)
     t_val, t_app = Timer(torch, app), Timer(torch, app)
     t_rec = Timer(torch, cpy)
     graph = None
+
+    pair = not args.separate_passes
 
     def start_copies(ca, cb):
         # the background copies start once the first validation pass is done:
         # they then share HBM with the latency-bound launches, not with it
         cpy.wait_stream(app)
-        t_bg_a.start()
+        if pair:  # one pass reads each page once for both images
+            phos.phos_ckpt_start_pair(ca, cb, None)
+            return
         phos.phos_ckpt_start(ca, None)
-        t_bg_a.stop()
-        t_bg_b.start()
         phos.phos_ckpt_start(cb, None)
-        t_bg_b.stop()
 
     final_at = {int(x) for x in args.final_at.split(",") if x.strip()}
     vstream = torch.cuda.Stream() if args.pipelined_validation else None
@@ -311,7 +313,7 @@ def run_training_step(args):
                 sl = slice(j, min(j + chunk, n_launch))
                 phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], [n_rec] * len(specs[sl]),
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
-                if j == 0 and args.copy_after_validation:
+                if j == 0 and args.copy_start == "validation":
                     start_copies(ca, cb)
             if j in final_at:  # pages no remaining launch may write
                 ahead = min((j // chunk + 1) * chunk, n_launch) - j  # validated, still to come
@@ -319,22 +321,24 @@ def run_training_step(args):
             phos.phos_ckpt_cow(ca, specs[j], app)
             if j == 0:
                 e_first.record(app)
+                if args.copy_start == "cow":
+                    start_copies(ca, cb)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
 
     warm = False
 
     def step():
         nonlocal graph, warm
-        if args.copy_after_validation:
+        if args.copy_start != "begin":
             ca = phos.phos_ckpt_begin(ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, img_a, None, cpy)
             cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, phos.CKPT_DEFER_BACKGROUND, img_b, None, cpy)
+        elif pair:
+            ca = phos.phos_ckpt_begin(ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, img_a, None, cpy)
+            cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, phos.CKPT_DEFER_BACKGROUND, img_b, None, cpy)
+            phos.phos_ckpt_start_pair(ca, cb, None)
         else:
-            t_bg_a.start()
             ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
-            t_bg_a.stop()
-            t_bg_b.start()
             cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, 0, img_b, None, cpy)
-            t_bg_b.stop()
         t_app.start()
         if args.app_graph and warm:
             if graph is None:
@@ -364,10 +368,11 @@ def run_training_step(args):
         sa, sb = step()  # ends with both checkpoints finished (synchronous)
         step_s.append(time.perf_counter() - ts0)
         stall = t_app.e0.elapsed_time(e_first) if not (args.app_graph or vstream) else float("nan")
-        rows.append(dict(bg_a=t_bg_a.ms(), bg_b=t_bg_b.ms(), app=t_app.ms(),
+        rows.append(dict(bg_a=sa.bg_ms, bg_b=sb.bg_ms if not pair else 0.0, app=t_app.ms(),
                          rec=t_rec.ms(), stall_t1=stall, bg_a_pages=sa.bg_pages,
                          cow_pages=sa.cow_pages,
-                         bg_b_pages=sb.bg_pages, recopy_pages=sb.recopy_pages,
+                         bg_b_pages=sb.bg_pages, bg_read_pages=sa.bg_read_pages + sb.bg_read_pages,
+                         recopy_pages=sb.recopy_pages,
                          precopy_pages=sb.precopy_pages))
         log(f"[bench] step {i}: " + ", ".join(f"{k}={v:.3f}" if isinstance(v, float) else f"{k}={v}"
                                              for k, v in rows[-1].items()))
@@ -394,12 +399,26 @@ def run_training_step(args):
     # launches with no checkpoint open (what the step would cost without C/R)
     ts = []
     for _ in range(3):
-        t_bg_a.start()
         ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
-        t_bg_a.stop()
-        phos.phos_ckpt_end(ca, cpy)
-        ts.append(t_bg_a.ms())
+        ts.append(phos.phos_ckpt_end(ca, cpy).bg_ms)
     bg_alone_ms = float(np.median(ts))
+    # the shared pass with nothing beside it (both images, every page)
+    ts, hbm = [], []
+    for _ in range(3):
+        ca = phos.phos_ckpt_begin(ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, img_a, None, cpy)
+        cb = phos.phos_ckpt_begin(ctx, phos.RECOPY, phos.CKPT_DEFER_BACKGROUND, img_b, None, cpy)
+        phos.phos_ckpt_start_pair(ca, cb, None)
+        sa = phos.phos_ckpt_end(ca, cpy)
+        sb = phos.phos_ckpt_end(cb, cpy)
+        ts.append(sa.bg_ms)
+        hbm.append((sa.bg_read_pages + sa.bg_pages + sb.bg_pages) * page)
+    pair_ms = float(np.median(ts))
+    pair_alone = {"bound": "hbm", "kernel": "background_pair_kernel, nothing beside it",
+                  "achieved": round(float(np.median(hbm)) / pair_ms / 1e6, 1),
+                  "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                  "frac": round(float(np.median(hbm)) / pair_ms / 1e6 / HBM_PEAK_GBPS, 4),
+                  "avg_launch_ms": round(pair_ms, 4)}
+    log(f"[bench] shared background pass alone {pair_ms:.3f} ms ({pair_alone['achieved']} GB/s)")
     ts = []
     for _ in range(2):
         t_app.start()
@@ -415,28 +434,25 @@ def run_training_step(args):
     # application stops while image A is copied (the library's background
     # copy with nothing beside it, its fastest whole-image copy), runs its
     # launches (no checkpoint open, so no validation), and stops again while
-    # image B is copied.  Each part is timed with HIP events on its stream;
-    # the sum leaves out the host's gaps between them.
+    # image B is copied.  Each part is timed with HIP events (the copies on
+    # the library's stream, the launches on the application's); the sum
+    # leaves out the host's gaps between them.
     stw = []
-    t_stw = [Timer(torch, cpy), Timer(torch, app), Timer(torch, cpy)]
+    t_launch = Timer(torch, app)
     for _ in range(3):
         torch.cuda.synchronize()
-        t_stw[0].start()
         ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, None, cpy)
-        t_stw[0].stop()
-        phos.phos_ckpt_end(ck, cpy)
+        copy_a = phos.phos_ckpt_end(ck, cpy).bg_ms
         app.wait_stream(cpy)
-        t_stw[1].start()
+        t_launch.start()
         for j, L in enumerate(launches):
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_ptrs[j], n_rec, app)
-        t_stw[1].stop()
+        t_launch.stop()
         cpy.wait_stream(app)
-        t_stw[2].start()
         ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_b, None, cpy)
-        t_stw[2].stop()
-        phos.phos_ckpt_end(ck, cpy)
+        copy_b = phos.phos_ckpt_end(ck, cpy).bg_ms
         torch.cuda.synchronize()
-        stw.append([t.ms() for t in t_stw])
+        stw.append([copy_a, t_launch.ms(), copy_b])
     stw_parts = np.median(np.array(stw), axis=0)
     stw_ms = float(np.median([sum(x) for x in stw]))
     log(f"[bench] stop-the-world step {stw_ms:.3f} ms (copy A {stw_parts[0]:.3f}, launches "
@@ -444,7 +460,7 @@ def run_training_step(args):
     # the Section 5 drain of a finished image to pinned host memory (PCIe)
     host_img = pinned_tensor(torch, nimg)
     ca = phos.phos_ckpt_begin(ctx, phos.COW, 0, img_a, host_img.data_ptr(), cpy)
-    cpy.synchronize()
+    torch.cuda.synchronize()  # the background copy (on the library's stream) has finished
     t0d = time.perf_counter()
     phos.phos_ckpt_end(ca, cpy)
     d2h_s = time.perf_counter() - t0d
@@ -465,9 +481,17 @@ def run_training_step(args):
     # with HIP events on the copy stream while the application runs beside it.
     # The recopy image's background copy is reported apart: how many pages it
     # skips depends on how far validation got, so its work varies by run.
+    # With the shared pass (default) the dominant kernel is that one pass: one
+    # read of each page it copies and one write per image it copies it into.
     bg_ms = float(np.mean([r["bg_a"] for r in rows]))
-    bg_bytes = float(np.mean([r["bg_a_pages"] for r in rows])) * page
-    bg_gbps = 2 * bg_bytes / (bg_ms / 1e3) / 1e9
+    if pair:
+        bg_kernel = "background_pair_kernel"
+        bg_hbm = float(np.mean([r["bg_read_pages"] + r["bg_a_pages"] + r["bg_b_pages"]
+                                for r in rows])) * page
+    else:
+        bg_kernel = "background_kernel"
+        bg_hbm = 2 * float(np.mean([r["bg_a_pages"] for r in rows])) * page
+    bg_gbps = bg_hbm / (bg_ms / 1e3) / 1e9
     bgb_ms = float(np.mean([r["bg_b"] for r in rows]))
     bgb_bytes = float(np.mean([r["bg_b_pages"] for r in rows])) * page
     n_addr = n_launch * n_rec
@@ -522,14 +546,17 @@ def run_training_step(args):
         "violations_per_step": nviol,
         "image_bytes_per_step": int(img_bytes),
         "bytes_copied_into_images_per_step": int(copied_bytes),
-        "background_recopy_image": {"avg_launch_ms": round(bgb_ms, 4),
-                                    "pages": int(bgb_bytes // page),
-                                    "GBps_hbm": round(2 * bgb_bytes / bgb_ms / 1e6, 1)},
-        "roofline": {"bound": "hbm", "kernel": "background_kernel (copy-on-write image)",
+        "background_passes": "shared (one pass, both images)" if pair else "one per image",
+        "background_pages": {"copy_on_write_image": int(np.mean([r["bg_a_pages"] for r in rows])),
+                             "recopy_image": int(np.mean([r["bg_b_pages"] for r in rows])),
+                             "pool_pages_read": int(np.mean([r["bg_read_pages"] for r in rows]))},
+        "roofline": {"bound": "hbm",
+                     "kernel": (f"{bg_kernel} (both images)" if pair
+                                else f"{bg_kernel} (copy-on-write image)"),
                      "achieved": round(bg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(bg_gbps / HBM_PEAK_GBPS, 4),
-                     "traffic": measured_traffic("background_kernel", "training_step"),
-                     "algorithmic_bytes_per_launch": int(2 * bg_bytes),
+                     "traffic": measured_traffic(bg_kernel, "training_step"),
+                     "algorithmic_bytes_per_launch": int(bg_hbm),
                      "avg_launch_ms": round(bg_ms, 4)},
         "roofline_background_alone": {"bound": "hbm", "kernel": "background_kernel, nothing beside it",
                                        "achieved": round(2 * nimg / bg_alone_ms / 1e6, 1),
@@ -537,6 +564,7 @@ def run_training_step(args):
                                        "frac": round(2 * nimg / bg_alone_ms / 1e6 / HBM_PEAK_GBPS, 4),
                                        "avg_launch_ms": round(bg_alone_ms, 4)},
         "application_alone_ms": round(app_alone_ms, 3),
+        "roofline_background_pair_alone": pair_alone,
         "d2h_drain_GBps": round(nimg / d2h_s / 1e9, 2),
         "roofline_validate": {"bound": "hbm", "kernel": "validate_kernel (+scan, scatter), alone",
                               "achieved": round((8 * n_addr + 32 * nviol) / alone["track"] / 1e6, 1),
@@ -553,6 +581,10 @@ def run_training_step(args):
                         "working_set_bytes": int(2 * rec_bytes),
                         "traffic": measured_traffic("gather_pages_kernel", "training_step")},
     }
+    if not pair:
+        result["background_recopy_image"] = {"avg_launch_ms": round(bgb_ms, 4),
+                                             "pages": int(bgb_bytes // page),
+                                             "GBps_hbm": round(2 * bgb_bytes / bgb_ms / 1e6, 1)}
     if graph is not None:
         graph.close()
     phos.phos_destroy(ctx)
@@ -850,7 +882,6 @@ def run_cold_start(args):
     pool.zero_()
     torch.cuda.synchronize()
     e_begin = torch.cuda.Event(enable_timing=True)
-    e_bg = torch.cuda.Event(enable_timing=True)
     e_end = torch.cuda.Event(enable_timing=True)
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(n_launch)]
@@ -862,7 +893,6 @@ def run_cold_start(args):
     h0 = time.perf_counter()
     rs = phos.phos_restore_begin_chunked(ctx, 0, pieces, cb, cpy)
     h_begin = time.perf_counter() - h0
-    e_bg.record(cpy)
     h_first = 0.0
     for j, L in enumerate(launches):
         r = recs.data_ptr() + j * n_rec * 8
@@ -878,7 +908,9 @@ def run_cold_start(args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ttfk = e_begin.elapsed_time(ev1[0])
-    full = e_begin.elapsed_time(e_bg)
+    # the background restore's GPU time (HIP events on the library's stream,
+    # which starts right after the begin call), or the pageable pieces' DMA
+    full = max(st.bg_ms, st.dma_ms)
     stream_ms = e_begin.elapsed_time(e_end)
     stalls = np.array([ev0[j].elapsed_time(ev1[j]) for j in range(n_launch)])
     h2d = w.image_bytes / (max(full, stream_ms) / 1e3) / 1e9
@@ -1321,7 +1353,7 @@ def run_drain(args):
         rates, lat = [], []
         for rep in range(max(2, args.steps)):
             ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, img.data_ptr(), host_img.data_ptr(), cpy)
-            cpy.synchronize()  # the background copy has finished: time the drain alone
+            torch.cuda.synchronize()  # the background copy has finished: time the drain alone
             box = {}
 
             def end():
@@ -1651,9 +1683,11 @@ def parse_args(argv=None):
     ap.add_argument("--small-mib", type=int, default=1024,
                     help="batched order: requests with at most this many MiB left go first")
     ap.add_argument("--twin-n", type=int, default=1 << 28, help="elements per array (config 6)")
-    ap.add_argument("--copy-after-validation", dest="copy_after_validation", action="store_true",
-                    help="config 2: open the checkpoints with deferred background copies and "
-                         "start them after the first validation pass")
+    ap.add_argument("--copy-start", dest="copy_start", default="cow",
+                    choices=("begin", "validation", "cow"),
+                    help="config 2: when the background copies start: with the checkpoints "
+                         "(begin), after the first validation pass (validation), or after launch "
+                         "0's copy-on-write, which takes the pages hit by failing writes (cow)")
     ap.add_argument("--pipelined-validation", dest="pipelined_validation", action="store_true",
                     help="config 2: validate the launch chunks on their own stream ahead of the "
                          "launches (use with --val-chunk)")
@@ -1666,6 +1700,9 @@ def parse_args(argv=None):
     ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",
                     help="config 8: staging budgets in MiB")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
+    ap.add_argument("--shared-pass", dest="separate_passes", action="store_false",
+                    help="config 2: one shared background pass for both images (one read per "
+                         "page) instead of one pass per image")
     ap.add_argument("--step-only", dest="step_only", action="store_true",
                     help="config 2: only the training step (no plain-tiny validation rate and "
                          "no batched-uneven latency beside it)")
@@ -1678,15 +1715,17 @@ def parse_args(argv=None):
 
 def main():
     args = parse_args()
-    if args.pipelined_validation and (args.app_graph or args.precopy or args.copy_after_validation):
-        sys.exit("--pipelined-validation runs alone (no --app-graph, --precopy, "
-                 "--copy-after-validation)")
+    if args.pipelined_validation:
+        if args.app_graph or args.precopy:
+            sys.exit("--pipelined-validation runs alone (no --app-graph, --precopy)")
+        args.copy_start = "begin"
     if args.final_at and (args.app_graph or args.pipelined_validation):
         # a round builds its page mask on the host at the call
         log("[bench] final-page pre-copy rounds are off with --app-graph / --pipelined-validation")
         args.final_at = ""
-    if args.copy_after_validation and args.app_graph:
-        sys.exit("--copy-after-validation starts the copies on another stream: not with --app-graph")
+    if args.app_graph and args.copy_start != "begin":
+        log("[bench] --app-graph starts the background copies with the checkpoints")
+        args.copy_start = "begin"
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the hot path is per GPU and shards by process "
               f"(one pool per GPU), so --gpus {args.gpus} is not run.", file=sys.stderr)

@@ -125,6 +125,12 @@ typedef struct {
   uint64_t image_bytes;  /* bytes of the image                                 */
   uint64_t precopy_pages; /* pages copied by pre-copy rounds                   */
   uint64_t staged_pages;  /* copy-on-write pages that went through staging      */
+  uint64_t bg_read_pages; /* pool pages its background pass read: bg_pages, or
+                             for phos_ckpt_start_pair the pages read once for
+                             both images (reported by the copy-on-write one; 0
+                             for the recopy one) */
+  double bg_ms;           /* GPU time of its background pass, from when it could
+                             start to its end (HIP events) */
 } phos_ckpt_stats;
 
 typedef struct {
@@ -136,6 +142,7 @@ typedef struct {
   double dma_first_ms;   /* ... until its first batch of pages was published */
   double dma_first_issue_ms;  /* ... until its first copy was queued        */
   double dma_first_copy_ms;   /* ... until that batch's copies had landed   */
+  double bg_ms;          /* GPU time of the background restore (HIP events) */
 } phos_rst_stats;
 
 /* ---------------------------------------------------------------- context */
@@ -321,6 +328,21 @@ phos_status phos_ckpt_staging(phos_ckpt *ck, void *staging, uint64_t bytes);
  * validation of the launches) and beside latency-bound launches instead.
  * E_STATE if the background copy has started or the recopy is done. */
 phos_status phos_ckpt_start(phos_ckpt *ck, hipStream_t after);
+
+/* Sections 4.2 and 4.3 with both checkpoints open in one window: a
+ * copy-on-write checkpoint `cow` (its image frozen at its begin) and a recopy
+ * checkpoint `recopy` (its image taken at its recopy), both begun with
+ * PHOS_CKPT_DEFER_BACKGROUND on one context, into device images.  Starts
+ * their background copies as one pass on cow's copy stream (after the work
+ * already on `after`, if not NULL): until a page is written the two images
+ * hold the same bytes, so the pass reads each pool page once and stores it
+ * to each image that still needs it (a page is claimed in each image on its
+ * own, as by phos_ckpt_start; pages already traced as written are left to
+ * the recopy).  Copy-on-write, pre-copy rounds, the recopy and the ends work
+ * as with separate passes; recopy's copy stream waits for this pass.
+ * E_INVAL: not a copy-on-write and a recopy checkpoint of one context, or a
+ * host image or staging area; E_STATE: a background copy already started. */
+phos_status phos_ckpt_start_pair(phos_ckpt *cow, phos_ckpt *recopy, hipStream_t after);
 
 /* Section 4.2: before the launch described by `spec` runs on app_stream,
  * copy every page it may write that the checkpoint has not copied yet: the

@@ -136,6 +136,14 @@ struct CopyArgs {
   // skips its page scan once [1] is set (skip_when_finished).
   unsigned long long *bg_exit = nullptr;
   uint32_t skip_when_finished = 0;
+  // Shared background pass of two checkpoints (launch_background_pair): the
+  // fields above describe the copy-on-write image (every page); these the
+  // recopy image, whose pages already traced as written (skip_dirty,
+  // skip_victim) are left to its recopy.
+  uint8_t *image2 = nullptr;
+  uint32_t *state2 = nullptr;
+  unsigned long long *stat2 = nullptr;
+  unsigned long long *stat_read = nullptr;  // pool pages the shared pass read
 };
 
 // Pages [p0, p0 + np) per range, in work units of kUnitPages.
@@ -223,6 +231,11 @@ hipError_t launch_mark_pieces(const uint32_t *img_page, uint32_t *state, uint32_
                               unsigned long long *count, hipStream_t s);
 hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
                              hipStream_t s);
+// One background pass for a copy-on-write and a recopy checkpoint open
+// together (device images): each pool page is read once and written to each
+// image whose claim this pass won.
+hipError_t launch_background_pair(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
+                                  hipStream_t s);
 // Final pages of a pre-copy round: dirty pages, and victim pages whose
 // latest failing write came from a launch numbered <= thr (those are
 // unmarked in the victim map), minus the pages of `exclude`.

@@ -876,6 +876,165 @@ __global__ void __launch_bounds__(kBgThreads)
   }
 }
 
+// Shared background pass of a copy-on-write and a recopy checkpoint open
+// together (Sections 4.2 and 4.3 in one window): the two images hold the same
+// bytes for every page not yet written, so one pass reads each pool page once
+// and stores it to both, instead of two passes reading the pool twice.  Each
+// page is still claimed in each image on its own (C.state: copy-on-write,
+// every page; C.state2: recopy, pages not yet traced as written), exactly as
+// two separate passes would claim it, so copy-on-write, pre-copy rounds and
+// the recopy interleave with it as they do with one pass per image.
+
+// Claimer wave: claim batch i's candidate pages in both images; won bit 0 =
+// the copy-on-write image, bit 1 = the recopy image.
+__device__ __forceinline__ void bg_claim_pair(const CopyArgs &C, uint64_t i, uint32_t batch,
+                                              uint32_t grab, uint32_t *s_p, uint32_t *s_ip,
+                                              uint32_t *s_m, uint32_t *s_n, uint32_t &n1,
+                                              uint32_t &n2, uint32_t &nr) {
+  const uint32_t lane = threadIdx.x - kBgCopyThreads;
+  if (lane == 0) *s_n = 0;  // same wave as every append below: ordered
+  const uint32_t nb = batch * grab;
+  for (uint32_t k = lane; k < nb; k += 64) {
+    const uint64_t g = (i * batch + k / grab) * gridDim.x + blockIdx.x;
+    const uint64_t p = g * grab + k % grab;
+    const bool in = p < C.n_pages;
+    const uint64_t q = in ? p : 0;
+    // the independent reads first, so their round trips overlap
+    const uint32_t ip = C.img_page[q];
+    uint32_t st1 = C.state[q], st2 = C.state2[q];  // plain reads only lag: "done" is final
+    const uint32_t traced = C.skip_dirty[q] | C.skip_victim[q];
+    if (!in || ip == kNone) continue;
+    uint32_t won = 0, exp;
+    if (st1 == kClaimed) st1 = ld_relaxed(&C.state[p]);
+    exp = kFree;
+    if (st1 == kFree && cas_u32(&C.state[p], exp, kClaimed)) won |= 1u;
+    if (!traced) {
+      if (st2 == kClaimed) st2 = ld_relaxed(&C.state2[p]);
+      exp = kFree;
+      if (st2 == kFree && cas_u32(&C.state2[p], exp, kClaimed)) won |= 2u;
+    }
+    if (!won) continue;
+    n1 += won & 1u;
+    n2 += won >> 1;
+    ++nr;
+    const uint32_t slot = atomicAdd(s_n, 1u);
+    s_p[slot] = (uint32_t)p;
+    s_ip[slot] = ip;
+    s_m[slot] = won;
+  }
+}
+
+// One page from the pool to one or both images (won: as above, uniform over
+// the block), U 16-byte loads in flight per thread, each stored once per image.
+template <bool NT, int U>
+__device__ __forceinline__ void copy_page_pair_t(const u32x4 *__restrict__ src,
+                                                 u32x4 *__restrict__ d1, u32x4 *__restrict__ d2,
+                                                 uint64_t n16, uint32_t tid, uint32_t nthreads) {
+  const uint64_t T = nthreads;
+  uint64_t i = tid;
+  for (; i + (U - 1) * T < n16; i += U * T) {
+    u32x4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      v[u] = NT ? __builtin_nontemporal_load(src + i + u * T) : src[i + u * T];
+    if (d1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (NT) __builtin_nontemporal_store(v[u], d1 + i + u * T);
+        else d1[i + u * T] = v[u];
+      }
+    }
+    if (d2) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (NT) __builtin_nontemporal_store(v[u], d2 + i + u * T);
+        else d2[i + u * T] = v[u];
+      }
+    }
+  }
+  for (; i < n16; i += T) {
+    const u32x4 v = src[i];
+    if (d1) d1[i] = v;
+    if (d2) d2[i] = v;
+  }
+}
+
+__device__ __forceinline__ void copy_page_pair(const CopyArgs &C, uint32_t p, uint32_t ip,
+                                               uint32_t won, uint32_t tid, uint32_t nthreads) {
+  const uint64_t pb = 1ull << C.page_shift;
+  const u32x4 *src = reinterpret_cast<const u32x4 *>(C.pool + ((uint64_t)p << C.page_shift));
+  u32x4 *d1 = (won & 1u) ? reinterpret_cast<u32x4 *>(C.image + ((uint64_t)ip << C.page_shift))
+                         : nullptr;
+  u32x4 *d2 = (won & 2u) ? reinterpret_cast<u32x4 *>(C.image2 + ((uint64_t)ip << C.page_shift))
+                         : nullptr;
+  if (C.nt) copy_page_pair_t<true, 8>(src, d1, d2, pb >> 4, tid, nthreads);
+  else copy_page_pair_t<false, 8>(src, d1, d2, pb >> 4, tid, nthreads);
+}
+
+// Same shape as background_kernel: waves 0..7 copy batch i while wave 8
+// claims batch i + 1.
+__global__ void __launch_bounds__(kBgThreads)
+    background_pair_kernel(CopyArgs C, uint32_t grab, uint32_t batch) {
+  __shared__ uint32_t s_p[2][kBgMaxBatch], s_ip[2][kBgMaxBatch], s_m[2][kBgMaxBatch], s_n[2],
+      s_arrive;
+  const uint32_t t = threadIdx.x;
+  const bool claimer = t >= kBgCopyThreads;
+  uint32_t n1 = 0, n2 = 0, nr = 0;  // pages this claimer won, per image, and in either
+  if (t == 0) s_arrive = 0;
+  if (claimer) bg_claim_pair(C, 0, batch, grab, s_p[0], s_ip[0], s_m[0], &s_n[0], n1, n2, nr);
+  __syncthreads();
+  uint32_t cur = 0;
+  for (uint64_t i = 0; bg_live(i, batch, grab, C.n_pages); ++i) {
+    if (claimer) {
+      bg_claim_pair(C, i + 1, batch, grab, s_p[cur ^ 1], s_ip[cur ^ 1], s_m[cur ^ 1],
+                    &s_n[cur ^ 1], n1, n2, nr);
+    } else {
+      const uint32_t n = s_n[cur];
+      for (uint32_t m = 0; m < n; ++m)
+        copy_page_pair(C, s_p[cur][m], s_ip[cur][m], s_m[cur][m], t, kBgCopyThreads);
+      // The recopy image's stores must be visible at device scope before its
+      // "done" (a pre-copy round may overwrite the page from another XCD
+      // right after; see background_kernel), so each wave fences before it
+      // arrives and the publisher releases; the copy-on-write image's "done"
+      // needs no ordering of stores.
+      if (n) __threadfence();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      uint32_t order = 0;
+      if ((t & 63u) == 0) order = atomicAdd(&s_arrive, 1u);
+      order = rfl(order);
+      if (order == kBgCopyThreads / 64 - 1) {
+        for (uint32_t m = t & 63u; m < n; m += 64) {
+          const uint32_t won = s_m[cur][m], pg = s_p[cur][m];
+          if (won & 1u)
+            __hip_atomic_store(&C.state[pg], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (won & 2u) st_release(&C.state2[pg], kDone);
+        }
+        if ((t & 63u) == 0) s_arrive = 0;
+      }
+    }
+    lds_barrier();  // list `cur` is free for the claim after next; s_arrive is 0
+    cur ^= 1;
+  }
+  if (claimer) {
+    for (uint32_t d = 32; d; d >>= 1) {
+      n1 += __shfl_down(n1, d, 64);
+      n2 += __shfl_down(n2, d, 64);
+      nr += __shfl_down(nr, d, 64);
+    }
+    if (t == kBgCopyThreads) {
+      if (n1) atomicAdd(C.stat, (unsigned long long)n1);
+      if (n2) atomicAdd(C.stat2, (unsigned long long)n2);
+      if (nr && C.stat_read) atomicAdd(C.stat_read, (unsigned long long)nr);
+    }
+  }
+  if (C.bg_exit && t == 0) {
+    // the copy-on-write image's completion, as background_kernel reports it
+    __threadfence();
+    if (atomicAdd(&C.bg_exit[0], 1ull) == gridDim.x - 1)
+      __hip_atomic_store(&C.bg_exit[1], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // Set the state of every pool page whose image page lies in a flagged image
 // piece (pieces the kernels cannot read, moved by DMA instead); count them.
 __global__ void __launch_bounds__(256)
@@ -1450,6 +1609,18 @@ hipError_t launch_background(const CopyArgs &c, uint32_t grab, uint32_t batch, u
     hipLaunchKernelGGL(background_kernel<true>, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
   else
     hipLaunchKernelGGL(background_kernel<false>, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_background_pair(const CopyArgs &c, uint32_t grab, uint32_t batch, uint32_t grid,
+                                  hipStream_t s) {
+  if (!c.n_pages || !grid) return hipSuccess;
+  if (grab == 0 || grab > kBgMaxBatch || !c.image || !c.image2 || !c.state || !c.state2 ||
+      !c.stat || !c.stat2 || !c.skip_dirty || !c.skip_victim || !c.to_image || c.image_chunks)
+    return hipErrorInvalidValue;
+  if (batch == 0) batch = 1;
+  if (batch * grab > kBgMaxBatch) batch = kBgMaxBatch / grab;
+  hipLaunchKernelGGL(background_pair_kernel, dim3(grid), dim3(kBgThreads), 0, s, c, grab, batch);
   return hipGetLastError();
 }
 

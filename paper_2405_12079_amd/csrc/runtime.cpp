@@ -61,6 +61,25 @@ struct HostSpec {
   std::vector<phos_interval> iv;  // sorted by (lo, hi)
 };
 
+// Events around a background copy on the context's background stream: its
+// start (after the work it follows) and its end; timed, for the stats.
+struct BgEvents {
+  hipEvent_t start = nullptr, done = nullptr;
+  void destroy() {
+    if (start) (void)hipEventDestroy(start);
+    if (done) (void)hipEventDestroy(done);
+    start = done = nullptr;
+  }
+  double ms() const {
+    float m = 0;
+    if (!start || !done || hipEventElapsedTime(&m, start, done) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    return m;
+  }
+};
+
 struct Slot {  // per-protocol reusable device state of a checkpoint / restore
   uint32_t *state = nullptr;               // per pool page
   unsigned long long *counters = nullptr;  // [0] chunk cursor, [1..3] stats
@@ -151,6 +170,15 @@ struct phos_ctx {
   phos_rst *open_rst = nullptr;
 
   hipStream_t aux = nullptr;     // private stream for synchronous reads
+  // Stream of the persistent background copies (created on first use), with
+  // a hardware queue of its own: streams created the ordinary way share a
+  // few hardware queues round robin, and an application kernel queued behind
+  // a background copy in a shared queue would wait for the whole copy (a
+  // copy-on-write, pre-copy or on-demand kernel waiting for one of its pages
+  // could then not even start).  A stream with a compute-unit mask never
+  // shares its queue; the mask here enables every unit.
+  hipStream_t bgq = nullptr;
+  hipEvent_t bgq_in = nullptr;   // work before a background copy, for bgq to wait on
   unsigned long long *h_pinned = nullptr;  // small pinned readback area
   uint32_t *h_want = nullptr;  // pageable restore: pages asked for by waiting launches (pinned)
   // pageable restore: the two pinned bounce slots the DMA thread stages
@@ -194,7 +222,8 @@ struct phos_ckpt {
   Slot *slot;
   bool recopied = false;
   bool bg_started = false;
-  hipEvent_t bg_done = nullptr;  // recorded after the background copy
+  uint32_t pair = 0;  // shared background pass: 1 copy-on-write side, 2 recopy side
+  BgEvents bg;  // around the background copy (on the context's bgq)
   bool bg_known_done = false;
   hipStream_t cow_stream = nullptr;  // the one stream CoW calls came from
   bool cow_streams_many = false;
@@ -248,8 +277,10 @@ struct phos_rst {
   std::chrono::steady_clock::time_point t_begin;
   double dma_ms = 0, dma_first_ms = -1, dma_first_issue_ms = -1, dma_first_copy_ms = -1;
   uint64_t asked_pages = 0;
+  BgEvents bg;  // around the background copy (on the context's bgq)
   ~phos_rst() {
     if (dma_thread.joinable()) dma_thread.join();
+    bg.destroy();
   }
 };
 
@@ -306,6 +337,8 @@ static phos_status ctx_free(phos_ctx *c) {
   if (c->v_evt) (void)hipEventDestroy(c->v_evt);
   if (c->vstage_evt) (void)hipEventDestroy(c->vstage_evt);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->bgq) (void)hipStreamDestroy(c->bgq);
+  if (c->bgq_in) (void)hipEventDestroy(c->bgq_in);
   for (void *p : c->retired) (void)hipFree(p);
   for (auto &e : c->vcache) (void)hipFree(e.dev);
   delete c;
@@ -1267,9 +1300,37 @@ static CopyArgs copy_args(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
 
 // over_pcie: the copy reads host memory, so a claimed-but-not-copied page
 // takes PCIe time to arrive; claim less far ahead for on-demand waiters.
+static phos_status ensure_bgq(phos_ctx *c) {
+  if (c->bgq) return PHOS_OK;
+  std::vector<uint32_t> mask((c->n_cu + 31) / 32, 0xFFFFFFFFu);
+  HIP_TRY(hipExtStreamCreateWithCUMask(&c->bgq, (uint32_t)mask.size(), mask.data()));
+  HIP_TRY(hipEventCreateWithFlags(&c->bgq_in, hipEventDisableTiming));
+  return PHOS_OK;
+}
+
+// The background stream runs after the work already enqueued on `after`;
+// `after` itself does not wait for the copy (a stream sharing a hardware
+// queue with the application would hold the application's kernels behind
+// it), so whoever needs the copy finished waits for *done.
+static phos_status bgq_after(phos_ctx *c, hipStream_t after) {
+  TRY(ensure_bgq(c));
+  HIP_TRY(hipEventRecord(c->bgq_in, after));
+  HIP_TRY(hipStreamWaitEvent(c->bgq, c->bgq_in, 0));
+  return PHOS_OK;
+}
+
+static phos_status bgq_mark(phos_ctx *c, hipEvent_t *e) {
+  if (!*e) HIP_TRY(hipEventCreate(e));
+  HIP_TRY(hipEventRecord(*e, c->bgq));
+  return PHOS_OK;
+}
+
 static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a,
-                                         hipStream_t stream, bool over_pcie = false) {
+                                         hipStream_t stream, BgEvents *ev,
+                                         bool over_pcie = false) {
   (void)s;
+  TRY(bgq_after(c, stream));
+  TRY(bgq_mark(c, &ev->start));
   // groups of 64 KiB: one page at 64 KiB pages, 16 at 4 KiB pages
   const uint32_t grab = std::max<uint32_t>(1, (64u << 10) >> c->page_shift);
   const uint32_t groups = (c->n_pages + grab - 1) / grab;
@@ -1283,12 +1344,12 @@ static phos_status start_background_args(phos_ctx *c, Slot &s, const CopyArgs &a
   const uint32_t grid = !over_pcie ? c->bg_grid
                         : a.to_image ? std::min(c->bg_grid, c->bg_grid_host)
                                      : std::min(c->bg_grid, c->n_cu);
-  HIP_TRY(launch_background(a, grab, batch, std::min(grid, groups), stream));
-  return PHOS_OK;
+  HIP_TRY(launch_background(a, grab, batch, std::min(grid, groups), c->bgq));
+  return bgq_mark(c, &ev->done);
 }
 
 static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool to_image,
-                                    hipStream_t stream, bool skip_traced = false,
+                                    hipStream_t stream, BgEvents *ev, bool skip_traced = false,
                                     bool over_pcie = false) {
   CopyArgs a = copy_args(c, s, image, to_image, &s.counters[1]);
   a.bg_exit = to_image ? &s.counters[6] : nullptr;  // [6], [7]: completion (reset at begin)
@@ -1296,7 +1357,7 @@ static phos_status start_background(phos_ctx *c, Slot &s, uint8_t *image, bool t
     a.skip_dirty = c->d_dirty;
     a.skip_victim = c->d_victim;
   }
-  return start_background_args(c, s, a, stream, over_pcie);
+  return start_background_args(c, s, a, stream, ev, over_pcie);
 }
 
 // Pages of the intervals with any of `modes`, clamped to the pool.
@@ -1381,12 +1442,10 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
     return fail(PHOS_E_INVAL, "the image must be device or pinned host memory");
   }
   if (!(flags & PHOS_CKPT_DEFER_BACKGROUND)) {
-    phos_status st = start_background(c, s, k->image, true, copy, protocol == PHOS_RECOPY, k->host);
-    if (st == PHOS_OK && (hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming) != hipSuccess ||
-                          hipEventRecord(k->bg_done, copy) != hipSuccess))
-      st = fail(PHOS_E_HIP, "background completion event");
+    phos_status st = start_background(c, s, k->image, true, copy, &k->bg,
+                                      protocol == PHOS_RECOPY, k->host);
     if (st != PHOS_OK) {
-      if (k->bg_done) (void)hipEventDestroy(k->bg_done);
+      k->bg.destroy();
       delete k;
       return st;
     }
@@ -1411,10 +1470,46 @@ extern "C" phos_status phos_ckpt_start(phos_ckpt *k, hipStream_t after) {
     (void)hipEventDestroy(e);
     if (he != hipSuccess) return fail(PHOS_E_HIP, "phos_ckpt_start: %s", hipGetErrorString(he));
   }
-  TRY(start_background(c, *k->slot, k->image, true, k->copy, k->protocol == PHOS_RECOPY, k->host));
+  TRY(start_background(c, *k->slot, k->image, true, k->copy, &k->bg,
+                       k->protocol == PHOS_RECOPY, k->host));
   k->bg_started = true;
-  if (!k->bg_done) HIP_TRY(hipEventCreateWithFlags(&k->bg_done, hipEventDisableTiming));
-  HIP_TRY(hipEventRecord(k->bg_done, k->copy));
+  return PHOS_OK;
+}
+
+extern "C" phos_status phos_ckpt_start_pair(phos_ckpt *a, phos_ckpt *b, hipStream_t after) {
+  if (!a || !b) return fail(PHOS_E_INVAL, "phos_ckpt_start_pair: NULL checkpoint");
+  if (a->protocol != PHOS_COW || b->protocol != PHOS_RECOPY || a->ctx != b->ctx)
+    return fail(PHOS_E_INVAL, "phos_ckpt_start_pair takes a copy-on-write and a recopy checkpoint "
+                "of one context");
+  if (a->bg_started || b->bg_started) return fail(PHOS_E_STATE, "a background copy has started");
+  if (b->recopied) return fail(PHOS_E_STATE, "recopy already done");
+  if (a->host || b->host || a->stage)
+    return fail(PHOS_E_INVAL, "the shared background pass copies into device images only");
+  phos_ctx *c = a->ctx;
+  DeviceGuard g(c->device);
+  if (after) TRY(bgq_after(c, after));
+  TRY(bgq_after(c, a->copy));
+  if (b->copy != a->copy) TRY(bgq_after(c, b->copy));
+  TRY(bgq_mark(c, &a->bg.start));
+  TRY(bgq_mark(c, &b->bg.start));
+  Slot &sa = *a->slot, &sb = *b->slot;
+  CopyArgs x = copy_args(c, sa, a->image, true, &sa.counters[1]);
+  x.bg_exit = &sa.counters[6];
+  x.image2 = b->image;
+  x.state2 = sb.state;
+  x.stat2 = &sb.counters[1];
+  x.stat_read = &sa.counters[4];
+  x.skip_dirty = c->d_dirty;
+  x.skip_victim = c->d_victim;
+  const uint32_t grab = std::max<uint32_t>(1, (64u << 10) >> c->page_shift);
+  const uint32_t groups = (c->n_pages + grab - 1) / grab;
+  HIP_TRY(launch_background_pair(x, grab, std::max<uint32_t>(1, c->bg_batch),
+                                 std::min(c->bg_grid, groups), c->bgq));
+  a->bg_started = b->bg_started = true;
+  a->pair = 1;
+  b->pair = 2;
+  TRY(bgq_mark(c, &a->bg.done));
+  TRY(bgq_mark(c, &b->bg.done));
   return PHOS_OK;
 }
 
@@ -1462,9 +1557,9 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   k->cow_stream = app;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(app, &cs));
-  if (cs == hipStreamCaptureStatusNone && k->bg_done && !k->cow_streams_many) {
+  if (cs == hipStreamCaptureStatusNone && k->bg.done && !k->cow_streams_many) {
     if (!k->bg_known_done) {
-      const hipError_t q = hipEventQuery(k->bg_done);
+      const hipError_t q = hipEventQuery(k->bg.done);
       if (q == hipSuccess) k->bg_known_done = true;
       else if (q != hipErrorNotReady) return fail(PHOS_E_HIP, "hipEventQuery: %s", hipGetErrorString(q));
     }
@@ -1522,9 +1617,11 @@ extern "C" phos_status phos_ckpt_recopy(phos_ckpt *k, hipStream_t app) {
   HIP_TRY(hipEventRecord(e, app));
   HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
   if (!k->bg_started) {
-    TRY(start_background(c, s, k->image, true, k->copy, true, k->host));
+    TRY(start_background(c, s, k->image, true, k->copy, &k->bg, true, k->host));
     k->bg_started = true;
   }
+  // the recopy follows the background copy, which left it the traced pages
+  HIP_TRY(hipStreamWaitEvent(k->copy, k->bg.done, 0));
   HIP_TRY(launch_fill_u32(s.list_count, 1, 0, k->copy));
   HIP_TRY(launch_pagelist(c->d_dirty, c->d_victim, c->nwords, c->n_pages, s.list, s.list_count,
                           k->copy));
@@ -1678,9 +1775,10 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
   HIP_TRY(hipStreamWaitEvent(k->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!k->bg_started) {
-    TRY(start_background(c, s, k->image, true, k->copy, false, k->host));
+    TRY(start_background(c, s, k->image, true, k->copy, &k->bg, false, k->host));
     k->bg_started = true;
   }
+  HIP_TRY(hipStreamWaitEvent(k->copy, k->bg.done, 0));
   if (k->stage) {  // staged copy-on-write pages to their places in the host image
     CopyArgs a = copy_args(c, s, k->image, true, nullptr);
     a.stage = k->stage;
@@ -1700,12 +1798,14 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     stats->recopy_pages = c->h_pinned[3];
     stats->precopy_pages = c->h_pinned[5];
     stats->staged_pages = k->stage ? std::min<uint64_t>(c->h_pinned[6], k->stage_cap) : 0;
+    stats->bg_read_pages = k->pair == 1 ? c->h_pinned[4] : k->pair == 2 ? 0 : c->h_pinned[1];
+    stats->bg_ms = k->bg.ms();
     stats->image_bytes = c->image_bytes;
   }
   bool timeout = false, misspec = false;
   TRY(read_err(c, k->copy, &timeout, k->protocol == PHOS_COW ? &misspec : nullptr));
   c->open_ckpt[k->protocol] = nullptr;
-  if (k->bg_done) (void)hipEventDestroy(k->bg_done);
+  k->bg.destroy();
   if (k->d_stage_page) (void)hipFree(k->d_stage_page);
   if (k->d_stage_head) (void)hipFree(k->d_stage_head);
   delete k;
@@ -2050,7 +2150,8 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
     }
   }
   if (!(flags & PHOS_RST_DEFER_BACKGROUND)) {
-    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), copy, r->host_image);
+    phos_status st = start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), copy,
+                                           &r->bg, r->host_image);
     if (st != PHOS_OK) {
       delete r;
       return st;
@@ -2100,9 +2201,11 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
   HIP_TRY(hipStreamWaitEvent(r->copy, e, 0));
   HIP_TRY(hipEventDestroy(e));
   if (!r->bg_started) {
-    TRY(start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), r->copy, r->host_image));
+    TRY(start_background_args(c, s, rst_args(r, &s.counters[1], c->rst_deep_bg), r->copy,
+                              &r->bg, r->host_image));
     r->bg_started = true;
   }
+  HIP_TRY(hipStreamWaitEvent(r->copy, r->bg.done, 0));
   if (r->dma_thread.joinable()) r->dma_thread.join();
   HIP_TRY(hipMemcpyAsync(c->h_pinned, s.counters, 4 * 8, hipMemcpyDeviceToHost, r->copy));
   HIP_TRY(hipStreamSynchronize(r->copy));
@@ -2116,6 +2219,7 @@ extern "C" phos_status phos_restore_end(phos_rst *r, hipStream_t app, phos_rst_s
     stats->dma_first_ms = r->dma_first_ms;
     stats->dma_first_issue_ms = r->dma_first_issue_ms;
     stats->dma_first_copy_ms = r->dma_first_copy_ms;
+    stats->bg_ms = r->bg.ms();
   }
   bool timeout = false;
   TRY(read_err(c, r->copy, &timeout));

@@ -52,14 +52,16 @@ class phos_arg(ctypes.Structure):
 class phos_ckpt_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("cow_pages", ctypes.c_uint64),
                 ("recopy_pages", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
-                ("precopy_pages", ctypes.c_uint64), ("staged_pages", ctypes.c_uint64)]
+                ("precopy_pages", ctypes.c_uint64), ("staged_pages", ctypes.c_uint64),
+                ("bg_read_pages", ctypes.c_uint64), ("bg_ms", ctypes.c_double)]
 
 
 class phos_rst_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("demand_pages", ctypes.c_uint64),
                 ("dma_pages", ctypes.c_uint64), ("asked_pages", ctypes.c_uint64),
                 ("dma_ms", ctypes.c_double), ("dma_first_ms", ctypes.c_double),
-                ("dma_first_issue_ms", ctypes.c_double), ("dma_first_copy_ms", ctypes.c_double)]
+                ("dma_first_issue_ms", ctypes.c_double), ("dma_first_copy_ms", ctypes.c_double),
+                ("bg_ms", ctypes.c_double)]
 
 
 class phos_batch_cfg(ctypes.Structure):
@@ -93,6 +95,7 @@ SIGNATURES = [
     ("phos_ckpt_precopy_final", [P, P, U32, U32, P]),
     ("phos_ckpt_staging", [P, P, U64]),
     ("phos_ckpt_start", [P, P]),
+    ("phos_ckpt_start_pair", [P, P, P]),
     ("phos_ckpt_end", [P, P, P]),
     ("phos_ckpt_copied", [P, P, U64]),
     ("phos_restore_begin", [P, U32, P, P, PP]),
@@ -297,6 +300,10 @@ def phos_ckpt_recopy(ck, app_stream) -> None:
 
 def phos_ckpt_start(ck, after=None) -> None:
     _call("phos_ckpt_start", ck, _stream(after))
+
+
+def phos_ckpt_start_pair(cow, recopy, after=None) -> None:
+    _call("phos_ckpt_start_pair", cow, recopy, _stream(after))
 
 
 def phos_ckpt_staging(ck, staging, nbytes) -> None:

@@ -422,8 +422,16 @@ def test_precopy_final_degenerate(env, window):
     assert np.array_equal(image.cpu().numpy(), res.snapshots[t2 - T1]), "image != snapshot at t2"
 
 
-def test_both_protocols_open_together(env):
-    """A CoW checkpoint (t1 image) and a recopy checkpoint (t2 image) over one window."""
+@pytest.mark.parametrize("mode", ["separate", "pair", "pair_precopy"])
+def test_both_protocols_open_together(env, mode):
+    """A CoW checkpoint (t1 image) and a recopy checkpoint (t2 image) over one
+    window.  separate: each with its own background pass; pair: one shared
+    pass (phos_ckpt_start_pair) that reads each page once for both images,
+    with the recopy checkpoint on another copy stream; pair_precopy: the
+    same, with two pre-copy rounds of the recopy image in the window.  Either
+    way the copy-on-write image is the snapshot at t1 and the recopy image
+    the snapshot at t2, and every image page is copied once per image by
+    exactly one path of its checkpoint."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)[:40]
     st = Stream(env, launches)
@@ -434,12 +442,25 @@ def test_both_protocols_open_together(env):
     img_a = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
     img_b = T.empty(env.image_bytes, dtype=T.uint8, device="cuda")
     copy2 = T.cuda.Stream()
-    ca = phos.phos_ckpt_begin(env.ctx, phos.COW, 0, img_a, None, env.copy)
-    cb = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, 0, img_b, None, copy2)
+    pair = mode != "separate"
+    flags = phos.CKPT_DEFER_BACKGROUND if pair else 0
+    ca = phos.phos_ckpt_begin(env.ctx, phos.COW, flags, img_a, None, env.copy)
+    cb = phos.phos_ckpt_begin(env.ctx, phos.RECOPY, flags, img_b, None, copy2)
     with pytest.raises(phos.PhosError):
         phos.phos_ckpt_begin(env.ctx, phos.COW, 0, img_a, None, env.copy)
+    if pair:
+        with pytest.raises(phos.PhosError) as e:  # a copy-on-write, then a recopy checkpoint
+            phos.phos_ckpt_start_pair(cb, ca, None)
+        assert e.value.status == phos.E_INVAL
+        phos.phos_ckpt_start_pair(ca, cb, env.app)
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_ckpt_start(cb, None)
+        assert e.value.status == phos.E_STATE
+    rounds = (13, 27) if mode == "pair_precopy" else ()
     out, cnt = env.violations_buffers(N)
     for j, L in enumerate(launches):
+        if j in rounds:
+            phos.phos_ckpt_precopy(cb, env.app)
         s = env.spec(L)
         r = st.records(j)
         _validate(env, s, r, out, cnt)
@@ -447,10 +468,20 @@ def test_both_protocols_open_together(env):
         env.mutate(L, r.data_ptr(), N)
         phos.phos_spec_release(env.ctx, s)
     phos.phos_ckpt_recopy(cb, env.app)
-    phos.phos_ckpt_end(ca, env.app)
-    phos.phos_ckpt_end(cb, env.app)
-    assert np.array_equal(img_a.cpu().numpy(), res.snapshots[0])
-    assert np.array_equal(img_b.cpu().numpy(), res.snapshots[40])
+    sa = phos.phos_ckpt_end(ca, env.app)
+    sb = phos.phos_ckpt_end(cb, env.app)
+    assert np.array_equal(img_a.cpu().numpy(), res.snapshots[0]), "copy-on-write image != t1"
+    assert np.array_equal(img_b.cpu().numpy(), res.snapshots[40]), "recopy image != t2"
+    n_img_pages = env.image_bytes // w.page_bytes
+    assert sa.bg_pages + sa.cow_pages == n_img_pages
+    assert n_img_pages - sb.recopy_pages - sb.precopy_pages <= sb.bg_pages <= n_img_pages
+    if rounds:
+        assert sb.precopy_pages > 0
+    if pair:  # one read per page for both images
+        assert max(sa.bg_pages, sb.bg_pages) <= sa.bg_read_pages <= sa.bg_pages + sb.bg_pages
+        assert sb.bg_read_pages == 0
+    else:
+        assert (sa.bg_read_pages, sb.bg_read_pages) == (sa.bg_pages, sb.bg_pages)
 
 
 def test_cow_straight_to_pinned_host(env):

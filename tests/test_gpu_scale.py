@@ -1,9 +1,9 @@
 """Full-size parity in the launch configuration bench.py times: the training
 step (16 GiB pool of 2,000 buffers, 64 KiB pages, 1,000 launches x 10^6
 accesses validated with tracking in one batched call, copy-on-write before
-every launch, a copy-on-write and a recopy checkpoint open together with one
-shared background pass for both images started after launch 0's
-copy-on-write, pre-copy rounds of the pages whose last write has been issued
+every launch, a copy-on-write and a recopy checkpoint open together with
+their background copies started after launch 0's copy-on-write, pre-copy
+rounds of the pages whose last write has been issued
 before launches 400, 650, 850, 950 and 990, recopy at the end).
 
 Compared against what the oracle computes at this size, on host threads,
@@ -75,8 +75,9 @@ def test_training_step_full_size():
             if j in FINAL_AT:  # every launch was validated up front
                 phos.phos_ckpt_precopy_final(cb, specs[j:], N_LAUNCH - j, app)
             phos.phos_ckpt_cow(ca, specs[j], app)
-            if j == 0:  # one shared background pass for both images, from here on
-                phos.phos_ckpt_start_pair(ca, cb, app)
+            if j == 0:  # the background copies of both images, from here on
+                phos.phos_ckpt_start(ca, app)
+                phos.phos_ckpt_start(cb, app)
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, ptrs[j], N_REC, app)
         phos.phos_ckpt_recopy(cb, app)
         dirty_gpu = phos.phos_track_read(ctx, 0, w.n_pages)

@@ -58,6 +58,7 @@ extern "C" const char *phos_last_error(void) { return g_err.c_str(); }
 struct HostSpec {
   bool used = false;
   uint32_t launch_id = 0;
+  uint64_t gen = 0;               // registration number: a reused handle is a new spec
   std::vector<phos_interval> iv;  // sorted by (lo, hi)
 };
 
@@ -146,12 +147,17 @@ struct phos_ctx {
 
   // batch descriptors ([VLaunch x n][DevIv x m]) cached on the device by
   // content, uploaded once through pinned staging
+  // Uploaded batch descriptors, keyed by what determines them: the tile
+  // size and, per launch, the spec (handle and registration number), the
+  // record pointer and count.  A repeated call finds its descriptors without
+  // building them again.
   struct VBatch {
     uint64_t hash;
-    std::vector<uint8_t> blob;
+    std::vector<uint64_t> key;
     uint8_t *dev;
     uint64_t last_use;
   };
+  uint64_t spec_gen = 0;
   std::vector<VBatch> vcache;
   uint64_t vclock = 0;
   void *h_vstage = nullptr;
@@ -574,6 +580,7 @@ extern "C" phos_status phos_spec_register(phos_ctx *c, uint32_t launch_id, const
   }
   c->specs[h].used = true;
   c->specs[h].launch_id = launch_id;
+  c->specs[h].gen = ++c->spec_gen;
   c->specs[h].iv = std::move(merged);
   *out = h;
   return PHOS_OK;
@@ -927,28 +934,18 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   uint64_t tiles = 0;
   for (uint32_t i = 0; i < nlaunch; ++i) tiles += (n[i] + tile - 1) / tile;
   if (tiles >= 0xFFFFFFF0ull) return fail(PHOS_E_INVAL, "too many records");
-  // host image of the descriptor table, the flat interval table and the
-  // launch of every tile
   const size_t head = nlaunch * sizeof(VLaunch) + total_iv * sizeof(DevIv);
-  std::vector<uint8_t> blob(head + 4 * tiles);
-  VLaunch *L = reinterpret_cast<VLaunch *>(blob.data());
-  DevIv *IV = reinterpret_cast<DevIv *>(blob.data() + nlaunch * sizeof(VLaunch));
-  uint32_t *TL = reinterpret_cast<uint32_t *>(blob.data() + head);
-  uint64_t ivo = 0;
-  tiles = 0;
+  // the cache key, and its hash (64-bit words, FNV-1a style mixing)
+  std::vector<uint64_t> key(2 + 3ull * nlaunch);
+  key[0] = tile;
+  key[1] = nlaunch;
   for (uint32_t i = 0; i < nlaunch; ++i) {
-    const HostSpec &h = c->specs[specs[i]];
-    L[i].rec = d_records[i];
-    L[i].n = n[i];
-    L[i].iv_off = (uint32_t)ivo;
-    L[i].niv = (uint32_t)h.iv.size();
-    L[i].launch_id = h.launch_id;
-    L[i].tile0 = (uint32_t)tiles;
-    for (const phos_interval &x : h.iv) IV[ivo++] = to_dev(x);
-    const uint64_t nt = (n[i] + tile - 1) / tile;
-    for (uint64_t t = 0; t < nt; ++t) TL[tiles + t] = i;
-    tiles += nt;
+    key[2 + 3 * i] = ((uint64_t)specs[i] << 32) ^ c->specs[specs[i]].gen;
+    key[3 + 3 * i] = (uint64_t)(uintptr_t)d_records[i];
+    key[4 + 3 * i] = n[i];
   }
+  uint64_t hsh = 1469598103934665603ull;
+  for (uint64_t w : key) hsh = (hsh ^ w) * 1099511628211ull, hsh ^= hsh >> 29;
   DeviceGuard g(c->device);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(stream, &cs));
@@ -956,13 +953,31 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   if (!capturing) TRY(ensure_workspace(c, tiles, cap));
   else if (tiles > c->tile_cap || cap > c->scratch_cap)
     return fail(PHOS_E_STATE, "workspace must be grown by an uncaptured call first");
-  uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the descriptors (the tile map follows)
-  for (size_t i = 0; i < head; ++i) hsh = (hsh ^ blob[i]) * 1099511628211ull;
   phos_ctx::VBatch *hit = nullptr;
   for (auto &e : c->vcache)
-    if (e.hash == hsh && e.blob == blob) hit = &e;
+    if (e.hash == hsh && e.key == key) hit = &e;
   if (!hit) {
     if (capturing) return fail(PHOS_E_STATE, "batch descriptors must be uploaded before capture");
+    // host image of the descriptor table, the flat interval table and the
+    // launch of every tile
+    std::vector<uint8_t> blob(head + 4 * tiles);
+    VLaunch *L = reinterpret_cast<VLaunch *>(blob.data());
+    DevIv *IV = reinterpret_cast<DevIv *>(blob.data() + nlaunch * sizeof(VLaunch));
+    uint32_t *TL = reinterpret_cast<uint32_t *>(blob.data() + head);
+    uint64_t ivo = 0, t0 = 0;
+    for (uint32_t i = 0; i < nlaunch; ++i) {
+      const HostSpec &h = c->specs[specs[i]];
+      L[i].rec = d_records[i];
+      L[i].n = n[i];
+      L[i].iv_off = (uint32_t)ivo;
+      L[i].niv = (uint32_t)h.iv.size();
+      L[i].launch_id = h.launch_id;
+      L[i].tile0 = (uint32_t)t0;
+      for (const phos_interval &x : h.iv) IV[ivo++] = to_dev(x);
+      const uint64_t nt = (n[i] + tile - 1) / tile;
+      for (uint64_t t = 0; t < nt; ++t) TL[t0 + t] = i;
+      t0 += nt;
+    }
     if (c->vcache.size() >= 256) {  // evict the least recently used
       auto lru = std::min_element(c->vcache.begin(), c->vcache.end(),
                                   [](const phos_ctx::VBatch &x, const phos_ctx::VBatch &y) {
@@ -989,7 +1004,7 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
     HIP_TRY(hipMemcpyAsync(dev, c->h_vstage, blob.size(), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventRecord(c->vstage_evt, stream));
     c->vstage_used = true;
-    c->vcache.push_back({hsh, std::move(blob), dev, 0});
+    c->vcache.push_back({hsh, std::move(key), dev, 0});
     hit = &c->vcache.back();
   }
   hit->last_use = ++c->vclock;

@@ -251,14 +251,28 @@ def phos_validate_noalloc(ctx, spec, d_records, n, flags, out, cap, n_violations
           _ptr(n_violations), _stream(stream))
 
 
+def _array(vals, dtype):
+    """A contiguous numpy array of `vals` (kept alive by the caller)."""
+    if isinstance(vals, np.ndarray) and vals.dtype == dtype and vals.flags.c_contiguous:
+        return vals
+    return np.ascontiguousarray(vals, dtype=dtype)
+
+
 def phos_validate_batch(ctx, specs, d_records, n, flags, out, cap, n_violations,
                         stream=None) -> None:
+    """specs, d_records (integer addresses or tensors) and n: sequences or
+    numpy arrays (uint32, uint64, uint64) of one entry per launch."""
     k = len(specs)
-    sp = (U32 * max(1, k))(*specs)
-    rp = (ctypes.c_void_p * max(1, k))(*[_ptr(r) for r in d_records])
-    nn = (U64 * max(1, k))(*n)
-    _call("phos_validate_batch", ctx, sp, rp, nn, k, flags, _ptr(out), cap, _ptr(n_violations),
-          _stream(stream))
+    sp = _array(specs, np.uint32)
+    if isinstance(d_records, np.ndarray):
+        rp = _array(d_records, np.uint64)
+    else:
+        rp = np.fromiter((_ptr(r) or 0 for r in d_records), dtype=np.uint64, count=k)
+    nn = _array(n, np.uint64)
+    if k == 0:
+        sp, rp, nn = np.zeros(1, np.uint32), np.zeros(1, np.uint64), np.zeros(1, np.uint64)
+    _call("phos_validate_batch", ctx, sp.ctypes.data, rp.ctypes.data, nn.ctypes.data, k, flags,
+          _ptr(out), cap, _ptr(n_violations), _stream(stream))
 
 
 def phos_twin_scale_add(ctx, spec, x, y, idx, n, flags, out=None, cap=0, n_violations=None,
@@ -316,8 +330,9 @@ def phos_ckpt_precopy(ck, app_stream) -> None:
 
 def phos_ckpt_precopy_final(ck, upcoming, n_validated_ahead, app_stream) -> None:
     k = len(upcoming)
-    sp = (U32 * max(1, k))(*upcoming)
-    _call("phos_ckpt_precopy_final", ck, sp, k, n_validated_ahead, _stream(app_stream))
+    sp = _array(upcoming, np.uint32) if k else np.zeros(1, np.uint32)
+    _call("phos_ckpt_precopy_final", ck, sp.ctypes.data, k, n_validated_ahead,
+          _stream(app_stream))
 
 
 def phos_ckpt_end(ck, app_stream) -> phos_ckpt_stats:

@@ -63,7 +63,7 @@ HOST_THREADS, HOST_CPU_DETAIL = host_cpu_share()
 KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic(kernel, workload, key="traffic_bytes_per_launch"):
+def measured_traffic(kernel, workload, key="traffic_bytes_per_launch", cast=int):
     """HBM bytes per launch (or the summary's `key`) of `kernel` on `workload`
     from the committed rocprofv3 counter summary
     (profiles/<kernel>_<workload>_pmc.txt), or None when there is none or the
@@ -80,7 +80,7 @@ def measured_traffic(kernel, workload, key="traffic_bytes_per_launch"):
     sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
     if fields.get("kernels_hip_sha256") != sha or key not in fields:
         return None
-    return int(float(fields[key]))
+    return cast(float(fields[key]))
 
 
 def log(*a):
@@ -572,6 +572,10 @@ def run_training_step(args):
                      "achieved": round(bg_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(bg_gbps / HBM_PEAK_GBPS, 4),
                      "traffic": measured_traffic(bg_kernel, "training_step"),
+                     # the counted launch copies a few hundred pages more or
+                     # fewer than the mean here (the copy-on-write race)
+                     "traffic_over_algorithmic": measured_traffic(
+                         bg_kernel, "training_step", "traffic_over_algorithmic", float),
                      "algorithmic_bytes_per_launch": int(bg_hbm),
                      "avg_launch_ms": round(bg_ms, 4)},
         "roofline_background_alone": {"bound": "hbm", "kernel": "background_kernel, nothing beside it",

@@ -1475,13 +1475,17 @@ def run_staging(args):
     rng = np.random.default_rng(8)
     img_off = np.concatenate([[0], np.cumsum(w.alloc_bytes.astype(np.int64))])
     samples = rng.integers(0, nimg // page, 2048)
-    rows = {}
-    for mib in [int(x) for x in args.budgets.split(",")]:
+    rows, rows_block = {}, {}
+    policies = [x for x in args.stage_policies.split(",") if x]
+    cases = [(pol, int(mib)) for mib in args.budgets.split(",") for pol in policies
+             if pol == "host_direct" or int(mib) > 0]
+    for pol, mib in cases:
         fresh()
         snap.copy_(pool)
         torch.cuda.synchronize()
         ck = phos.phos_ckpt_begin(ctx, phos.COW, 0, himg.data_ptr(), None, cpy)
-        phos.phos_ckpt_staging(ck, staging, min(mib << 20, nimg))
+        phos.phos_ckpt_staging_policy(ck, staging, min(mib << 20, nimg),
+                                      phos.STAGE_BLOCK if pol == "block" else phos.STAGE_HOST_DIRECT)
         t.start()
         loop(ck)
         t.stop()
@@ -1495,12 +1499,17 @@ def run_staging(args):
             src = int(w.alloc_off[b]) + p * page - int(img_off[b])
             ok &= bool(torch.equal(himg[p * page:(p + 1) * page],
                                    snap[src:src + page].cpu()))
-        assert ok, f"host image differs from the pool at t1 (budget {mib} MiB)"
-        rows[mib] = {"loop_ms": round(loop_ms, 2), "stall_ms": round(loop_ms - alone_ms, 2),
-                     "cow_pages": int(st.cow_pages), "staged_pages": int(st.staged_pages),
-                     "background_pages": int(st.bg_pages), "end_s": round(end_s, 3)}
-        log(f"[bench] budget {mib} MiB: {rows[mib]}")
+        assert ok, f"host image differs from the pool at t1 ({pol}, budget {mib} MiB)"
+        row = {"loop_ms": round(loop_ms, 2), "stall_ms": round(loop_ms - alone_ms, 2),
+               "cow_pages": int(st.cow_pages), "staged_pages": int(st.staged_pages),
+               "background_pages": int(st.bg_pages), "end_s": round(end_s, 3)}
+        if pol == "block":
+            row["drain_batches"] = int(st.stage_batches)
+        (rows_block if pol == "block" else rows)[mib] = row
+        log(f"[bench] {pol}, budget {mib} MiB: {row}")
     phos.phos_destroy(ctx)
+    if not rows:
+        rows = rows_block
     first = rows[min(rows)]
     return {
         "metric": "copy-on-write stall of the launches (ms per step) vs the device staging budget",
@@ -1511,8 +1520,11 @@ def run_staging(args):
         "config": {"workload": "CoW staging: training-step layout, 1000 launches x 1e6 accesses, "
                                "16 GiB pinned host image, budgets " + args.budgets + " MiB"},
         "launches_without_checkpoint_ms": round(alone_ms, 2),
-        "by_budget_mib": rows, "stall_ms_without_staging": first["stall_ms"],
-        "parity": "2048 sampled image pages equal the pool at t1 for every budget",
+        # a full area: copies go straight to the host image (host_direct), or
+        # wait for a slot the host's copy-engine drain frees (block)
+        "by_budget_mib": rows, "by_budget_mib_block": rows_block,
+        "stall_ms_without_staging": first["stall_ms"],
+        "parity": "2048 sampled image pages equal the pool at t1 for every budget and policy",
     }
 
 
@@ -1719,6 +1731,8 @@ def parse_args(argv=None):
                          "dirty pages no remaining launch may write ('' for none)")
     ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",
                     help="config 8: staging budgets in MiB")
+    ap.add_argument("--stage-policies", default="host_direct,block",
+                    help="config 8: policies for a full staging area (host_direct, block)")
     ap.add_argument("--no-parity", dest="parity", action="store_false")
     ap.add_argument("--shared-pass", dest="separate_passes", action="store_false",
                     help="config 2: one shared background pass for both images (one read per "

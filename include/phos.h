@@ -131,6 +131,8 @@ typedef struct {
                              for the recopy one) */
   double bg_ms;           /* GPU time of its background pass, from when it could
                              start to its end (HIP events) */
+  uint64_t stage_batches; /* blocking staging: batches the drain moved (one
+                             engine copy each); 0 otherwise */
 } phos_ckpt_stats;
 
 typedef struct {
@@ -180,7 +182,11 @@ typedef struct {
  *                        background [0] copies
  *   PHOS_TWIN_BLOCKS_PER_CU  twin kernel blocks per CU [4; 5 with PHOS_V_TRACK]
  *   PHOS_DRAIN_CHUNK_KB  image drain to a host image: chunk size [16384; 0 =
- *                        one copy]; PHOS_DRAIN_WINDOW chunks in flight [2] */
+ *                        one copy]; PHOS_DRAIN_WINDOW chunks in flight [2]
+ *   PHOS_STAGE_THREADS   blocking CoW staging: host threads moving drained
+ *                        pages into the image [4]
+ *   PHOS_STAGE_HIGH_PCT  ... the ring's fill (percent) that starts its drain
+ *                        during the checkpoint [50]; the rest drains at the end */
 phos_status phos_create(int device, uint64_t pool_base, uint64_t pool_bytes, uint32_t page_bytes,
                         phos_ctx **out);
 /* Synchronizes the device, frees everything the context owns. */
@@ -320,6 +326,32 @@ phos_status phos_ckpt_begin(phos_ctx *ctx, uint32_t protocol, uint32_t flags, vo
  * a device image or staging that is not 16-byte aligned device memory.
  * The staging memory must stay allocated until phos_ckpt_end returns. */
 phos_status phos_ckpt_staging(phos_ckpt *ck, void *staging, uint64_t bytes);
+
+/* Policies of phos_ckpt_staging_policy. */
+enum {
+  PHOS_STAGE_HOST_DIRECT = 0, /* a full area: copies go straight to the host image */
+  PHOS_STAGE_BLOCK = 1        /* a full area: copies wait for a slot the drain frees */
+};
+
+/* Section 4.2, CoW staging with a policy for a full area.
+ * PHOS_STAGE_HOST_DIRECT is phos_ckpt_staging.  PHOS_STAGE_BLOCK makes the
+ * area a ring of bytes / page_bytes slots that the host drains into the host
+ * image while the checkpoint runs: a host thread the call starts moves
+ * batches of consecutive slots (up to 16 MiB) with the copy engines into
+ * pinned bounce buffers, no compute queue taking part, and PHOS_STAGE_THREADS
+ * (default 4) more host threads move the pages to their places in the
+ * image.  Every copy-on-write page takes the next slot; when the ring is full
+ * the copy waits until the drain has freed the slot it needs (a bounded
+ * wait: if it gives up the page goes straight to the image and phos_ckpt_end
+ * reports PHOS_E_TIMEOUT).  phos_ckpt_end waits for the drain of the last
+ * slot; stats.staged_pages counts the pages that went through the ring.
+ * Pinned host memory: 12 bytes per slot of control words and 8 bounce
+ * buffers of min(slots, 16 MiB / page_bytes) pages.  Same preconditions and
+ * errors as phos_ckpt_staging, plus E_INVAL for an unknown policy and
+ * E_HIP when the copy engines cannot be reached.  The staging memory must
+ * stay allocated until phos_ckpt_end returns. */
+phos_status phos_ckpt_staging_policy(phos_ckpt *ck, void *staging, uint64_t bytes,
+                                     uint32_t policy);
 
 /* Start the background copy of a checkpoint opened with
  * PHOS_CKPT_DEFER_BACKGROUND now, on its copy_stream, after the work already

@@ -127,6 +127,18 @@ struct CopyArgs {
   uint32_t *stage_page = nullptr;
   unsigned long long *stage_head = nullptr;
   uint32_t stage_cap = 0;
+  // Blocking policy (stage_block = 1): the area is a ring, slot s at position
+  // s % stage_cap, drained to the image by the host's copy engines while the
+  // checkpoint runs.  A page needing slot s >= stage_cap waits until the
+  // drain of slot s - stage_cap has been published (free_seq[pos] reaches
+  // s - stage_cap + 1; device memory, written by the copy engine).  A filled
+  // slot is published to the host as fill[pos] = (s + 1) << 32 | pool page
+  // (pinned host memory, a system-scope store).  A page whose wait gave up
+  // goes straight to the image and its slot stays unpublished (the error
+  // word records the expiry; the drain then stops there).
+  uint32_t stage_block = 0;
+  uint64_t *fill = nullptr;
+  uint32_t *free_seq = nullptr;
   // Restore: blocks copying pages a launch needs now (on demand) count
   // themselves here while they copy; the background copy claims no new
   // pages while it is nonzero, so on-demand copies get the link first.

@@ -572,6 +572,49 @@ __device__ __forceinline__ bool wait_expired(const CopyArgs &C, uint32_t it) {
   return false;
 }
 
+// Blocking staging: slot `slot` (ring position pos) may be written once the
+// drain of its previous occupant, slot - stage_cap, is published.  With
+// WAIT, one thread of the block waits (bounded; false: the wait gave up);
+// without, it only looks once.
+template <bool WAIT>
+__device__ __forceinline__ bool stage_room(const CopyArgs &C, unsigned long long slot, uint32_t pos) {
+  if (slot < C.stage_cap) return true;
+  const uint32_t need = (uint32_t)(slot - C.stage_cap + 1);
+  uint32_t it = 0;
+  // the copy engine writes free_seq in memory: read it at system scope
+  while ((int32_t)(__hip_atomic_load(&C.free_seq[pos], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) -
+                   need) < 0) {
+    if (!WAIT) return false;
+    __builtin_amdgcn_s_sleep(8);
+    if (wait_expired(C, ++it)) return false;
+  }
+  return true;
+}
+
+// Blocking staging, block-collective: publish the slots of won pages
+// [j0, j1) to the host's drain (all but those marked kNone in won_ip, whose
+// wait gave up).  Each slot's word packs its sequence number + 1 (high half)
+// with its pool page (low half), so one store publishes both.  Every wave's slot
+// stores have completed into the L2 before the barrier, and one
+// system-scope release then writes the L2 back, so the copy engine that
+// drains a published slot reads the page, not what the slot held before.
+__device__ __forceinline__ void stage_publish(const CopyArgs &C, unsigned long long slot0,
+                                              uint32_t j0, uint32_t j1, const uint32_t *won,
+                                              const uint32_t *won_ip) {
+  if (j0 >= j1) return;  // block-uniform
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    for (uint32_t j = j0; j < j1; ++j) {
+      if (won_ip[j] == kNone) continue;  // not staged (its wait gave up)
+      const unsigned long long slot = slot0 + j;
+      const uint64_t v = ((uint64_t)(uint32_t)(slot + 1) << 32) | won[j];
+      __hip_atomic_store(&C.fill[slot % C.stage_cap], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
+}
+
 // Block-collective: every thread offers at most one candidate page.  Pages
 // still free are claimed (one winner per page across the whole GPU), copied
 // by this block, then published as done; with WAIT, a thread whose page is
@@ -627,21 +670,53 @@ __device__ void claim_copy(uint32_t cand, const CopyArgs &C, unsigned long long 
   if (C.stage && C.to_image) {
     // copy-on-write into a host image: the first pages go to the device
     // staging area at HBM speed (moved to the image when the checkpoint
-    // ends), the rest straight to the host once the area is full
+    // ends), the rest straight to the host once the area is full; under the
+    // blocking policy every page takes a slot of the ring, waiting for one
+    // the host's drain has freed
     __shared__ unsigned long long s_slot0;
+    __shared__ uint32_t s_room;
     if (threadIdx.x == 0) s_slot0 = nwon ? atomicAdd(C.stage_head, (unsigned long long)nwon) : 0;
     __syncthreads();
     const unsigned long long slot0 = s_slot0;
     const uint64_t pb = 1ull << C.page_shift;
+    uint32_t pend = 0;  // blocking policy: won pages [pend, i) are staged, not yet published
     for (uint32_t i = 0; i < nwon; ++i) {
       const unsigned long long slot = slot0 + i;
-      if (slot < C.stage_cap) {
+      if (C.stage_block) {
+        const uint32_t pos = (uint32_t)(slot % C.stage_cap);
+        if (threadIdx.x == 0) s_room = stage_room<false>(C, slot, pos);
+        __syncthreads();
+        if (!s_room) {
+          // about to wait: what this block has staged goes to the drain
+          // first (with a short ring the slot waited for may be behind it)
+          stage_publish(C, slot0, pend, i, s_won, s_won_ip);
+          pend = i;
+          __syncthreads();
+          if (threadIdx.x == 0) s_room = stage_room<true>(C, slot, pos);
+          __syncthreads();
+        }
+        const bool room = s_room != 0;
+        if (room)
+          block_copy16(reinterpret_cast<const uint4 *>(C.pool + ((uint64_t)s_won[i] << C.page_shift)),
+                       reinterpret_cast<uint4 *>(C.stage + (uint64_t)pos * pb), pb >> 4, C.nt != 0);
+        else
+          copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
+        __syncthreads();  // every wave has read s_room and s_won_ip[i]
+        // a page whose wait gave up went straight to the image; its slot
+        // still holds an undrained page and is not published (the
+        // checkpoint reports the timeout)
+        if (threadIdx.x == 0 && !room) s_won_ip[i] = kNone;
+      } else if (slot < C.stage_cap) {
         block_copy16(reinterpret_cast<const uint4 *>(C.pool + ((uint64_t)s_won[i] << C.page_shift)),
                      reinterpret_cast<uint4 *>(C.stage + slot * pb), pb >> 4, C.nt != 0);
         if (threadIdx.x == 0) C.stage_page[slot] = s_won[i];
       } else {
         copy_page<DEEP>(C, s_won[i], s_won_ip[i]);
       }
+    }
+    if (C.stage_block) {
+      __syncthreads();  // the last hole mark is visible
+      stage_publish(C, slot0, pend, nwon, s_won, s_won_ip);
     }
   } else {
     for (uint32_t i = 0; i < nwon; ++i) copy_page<DEEP>(C, s_won[i], s_won_ip[i]);

@@ -7,6 +7,7 @@
 #include <hsa/hsa_ext_amd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -81,9 +82,11 @@ struct BgEvents {
   }
 };
 
+constexpr uint32_t kSlotCounters = 8;
 struct Slot {  // per-protocol reusable device state of a checkpoint / restore
   uint32_t *state = nullptr;               // per pool page
-  unsigned long long *counters = nullptr;  // [0] chunk cursor, [1..3] stats
+  unsigned long long *counters = nullptr;  // [0] chunk cursor, [1..5] stats, [6..7] background
+                                           // completion (a restore: [4] on-demand copies)
   uint32_t *list = nullptr;                // recopy page list
   unsigned int *list_count = nullptr;
 };
@@ -202,6 +205,8 @@ struct phos_ctx {
   // for the on-demand / background copies of an image in host memory
   uint32_t rst_pause = 64, rst_deep_demand = 1, rst_deep_bg = 0;
   uint32_t rst_hold_ms = 200;  // restore: hold only this long after the background starts (0: always)
+  uint32_t stage_threads = 4;  // blocking staging: host threads moving drained pages into the image
+  uint32_t stage_high_pct = 50;  // ... and the ring's fill (percent) that starts its drain
   uint32_t cow_deep = 1;  // copy-on-write copies keep 16 loads in flight per thread
   uint64_t drain_chunk = 16u << 20;  // image drain to host: chunk bytes (0: one copy)
   uint32_t drain_window = 2;        // ... and chunks in flight
@@ -242,12 +247,34 @@ struct phos_ckpt {
   uint32_t *d_stage_page = nullptr;
   unsigned long long *d_stage_head = nullptr;
   uint32_t stage_cap = 0;
+  // blocking policy: the area is a ring the host drains during the checkpoint
+  bool stage_block = false;
+  uint64_t *h_fill = nullptr;      // pinned: per slot (sequence number + 1) << 32 | pool page
+  uint32_t *h_free_src = nullptr;  // pinned: the sequence numbers the drain publishes
+  uint32_t *d_free_seq = nullptr;  // device: per slot, sequence number + 1 of its last drained occupant
+  std::thread drainer;
+  std::atomic<bool> drain_stop{false}, drain_abort{false};
+  std::atomic<uint64_t> drain_final{0};  // slots taken in all (set with drain_stop)
+  phos_status drain_status = PHOS_OK;
+  std::string drain_error;
+  uint64_t drained_pages = 0, drain_copies = 0;
+  uint8_t *h_bounce = nullptr;     // pinned: the drain's bounce buffers
+  uint32_t drain_batch_slots = 0, drain_threads = 0, drain_high_pct = 50;
   // final-page pre-copy rounds: the pages the remaining launches may write,
   // one bit per pool page (pinned host copy, device copy, upload event)
   uint32_t *h_mask = nullptr, *d_mask = nullptr;
   hipEvent_t mask_evt = nullptr;
   bool mask_used = false;
   ~phos_ckpt() {
+    if (drainer.joinable()) {  // not ended: let the kernels finish, then stop the drain
+      (void)hipDeviceSynchronize();
+      drain_abort.store(true, std::memory_order_release);
+      drainer.join();
+    }
+    if (h_fill) (void)hipHostFree(h_fill);
+    if (h_free_src) (void)hipHostFree(h_free_src);
+    if (h_bounce) (void)hipHostFree(h_bounce);
+    if (d_free_seq) (void)hipFree(d_free_seq);
     if (mask_used) (void)hipEventSynchronize(mask_evt);
     if (mask_evt) (void)hipEventDestroy(mask_evt);
     if (h_mask) (void)hipHostFree(h_mask);
@@ -391,6 +418,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->spin_limit = env_u32("PHOS_SPIN_LIMIT", 1u << 22);
   c->rst_pause = env_u32("PHOS_RST_PAUSE", 64);
   c->rst_hold_ms = std::min<uint32_t>(env_u32("PHOS_RST_HOLD_MS", 200), 40000);
+  c->stage_threads = env_u32("PHOS_STAGE_THREADS", 4);
+  c->stage_high_pct = env_u32("PHOS_STAGE_HIGH_PCT", 50);
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);
   c->rst_deep_demand = env_u32("PHOS_RST_DEEP_DEMAND", 1);
@@ -1273,7 +1302,7 @@ extern "C" phos_status phos_track_read(phos_ctx *c, uint32_t which, uint32_t *ho
 // ---------------------------------------------------------------- protocols
 static phos_status ensure_slot(phos_ctx *c, Slot &s, bool with_list) {
   if (!s.state) TRY(dalloc(&s.state, c->n_pages));
-  if (!s.counters) TRY(dalloc(&s.counters, 8));
+  if (!s.counters) TRY(dalloc(&s.counters, kSlotCounters));
   if (with_list && !s.list) {
     TRY(dalloc(&s.list, c->n_pages));
     TRY(dalloc(&s.list_count, 1));
@@ -1432,7 +1461,7 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
   // (On the private stream, synchronized here, so that a second checkpoint
   // opened beside this one does not wait for this one's background copy.)
   HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, c->aux));
-  HIP_TRY(launch_fill_u64(s.counters, 8, 0, c->aux));
+  HIP_TRY(launch_fill_u64(s.counters, kSlotCounters, 0, c->aux));
   if (s.list_count) HIP_TRY(launch_fill_u32(s.list_count, 1, 0, c->aux));
   if (!c->open_ckpt[PHOS_COW] && !c->open_ckpt[PHOS_RECOPY]) {
     HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(c->d_dirty), 8ull * c->nwords, 0, c->aux));
@@ -1528,8 +1557,22 @@ extern "C" phos_status phos_ckpt_start_pair(phos_ckpt *a, phos_ckpt *b, hipStrea
   return PHOS_OK;
 }
 
+static phos_status dma_engines_ready(phos_ctx *c);
+static void stage_drain_main(phos_ckpt *k);
+namespace {
+constexpr uint32_t kDrainBounces = 8;            // drain batches in flight
+constexpr uint64_t kDrainBatchBytes = 16u << 20;  // largest drain batch (one bounce buffer)
+}  // namespace
+
 extern "C" phos_status phos_ckpt_staging(phos_ckpt *k, void *staging, uint64_t bytes) {
+  return phos_ckpt_staging_policy(k, staging, bytes, PHOS_STAGE_HOST_DIRECT);
+}
+
+extern "C" phos_status phos_ckpt_staging_policy(phos_ckpt *k, void *staging, uint64_t bytes,
+                                                uint32_t policy) {
   if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_staging: NULL checkpoint");
+  if (policy != PHOS_STAGE_HOST_DIRECT && policy != PHOS_STAGE_BLOCK)
+    return fail(PHOS_E_INVAL, "unknown staging policy %u", policy);
   if (k->protocol != PHOS_COW) return fail(PHOS_E_STATE, "staging needs a CoW checkpoint");
   if (k->stage || k->cow_stream) return fail(PHOS_E_STATE, "staging set twice or after a CoW call");
   phos_ctx *c = k->ctx;
@@ -1554,6 +1597,34 @@ extern "C" phos_status phos_ckpt_staging(phos_ckpt *k, void *staging, uint64_t b
   }
   k->stage = static_cast<uint8_t *>(staging);
   k->stage_cap = (uint32_t)cap;
+  if (policy == PHOS_STAGE_BLOCK) {
+    // the ring's control words, then the host's drain
+    st = dma_engines_ready(c);
+    k->drain_batch_slots =
+        (uint32_t)std::min<uint64_t>(cap, std::max<uint64_t>(1, kDrainBatchBytes >> c->page_shift));
+    k->drain_threads = std::min<uint32_t>(64, std::max<uint32_t>(1, c->stage_threads));
+    k->drain_high_pct = std::min<uint32_t>(100, c->stage_high_pct);
+    if (st == PHOS_OK &&
+        (hipHostMalloc((void **)&k->h_fill, 8ull * cap, hipHostMallocDefault) != hipSuccess ||
+         hipHostMalloc((void **)&k->h_free_src, 4ull * cap, hipHostMallocDefault) != hipSuccess ||
+         hipHostMalloc((void **)&k->h_bounce,
+                       (uint64_t)kDrainBounces * k->drain_batch_slots * c->page_bytes,
+                       hipHostMallocDefault) != hipSuccess))
+      st = fail(PHOS_E_NOMEM, "pinned staging control words and bounce buffers (%llu slots)",
+                (unsigned long long)cap);
+    if (st == PHOS_OK) st = dalloc(&k->d_free_seq, cap);
+    if (st == PHOS_OK && (launch_fill_u32(k->d_free_seq, cap, 0, c->aux) != hipSuccess ||
+                          hipStreamSynchronize(c->aux) != hipSuccess))
+      st = fail(PHOS_E_HIP, "staging set-up");
+    if (st != PHOS_OK) {
+      k->stage = nullptr;  // the checkpoint goes on without staging
+      k->stage_cap = 0;
+      return st;
+    }
+    memset(k->h_fill, 0, 8ull * cap);
+    k->stage_block = true;
+    k->drainer = std::thread(stage_drain_main, k);
+  }
   return PHOS_OK;
 }
 
@@ -1606,6 +1677,11 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
     a.stage_page = k->d_stage_page;
     a.stage_head = k->d_stage_head;
     a.stage_cap = k->stage_cap;
+    if (k->stage_block) {
+      a.stage_block = 1;
+      a.fill = k->h_fill;
+      a.free_seq = k->d_free_seq;
+    }
   }
   // with tracking calls on other streams the list may be appended to while
   // this launch reads it: the victim map (marks only ever added, complete
@@ -1776,6 +1852,30 @@ static phos_status drain_image(phos_ctx *c, phos_ckpt *k) {
   return st;
 }
 
+// Blocking staging at the end: once every copy-on-write call has completed,
+// every slot taken is published; the drain ends after the last of them.
+static phos_status stage_drain_finish(phos_ckpt *k, hipStream_t app) {
+  phos_ctx *c = k->ctx;
+  if (!k->drainer.joinable()) return PHOS_OK;
+  HIP_TRY(hipStreamSynchronize(app));
+  if (k->cow_stream && k->cow_stream != app) HIP_TRY(hipStreamSynchronize(k->cow_stream));
+  if (k->cow_streams_many) HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 7, k->d_stage_head, 8, hipMemcpyDeviceToHost, c->aux));
+  HIP_TRY(hipMemcpyAsync(c->h_pinned + 20, c->d_err, 4, hipMemcpyDeviceToHost, c->aux));
+  HIP_TRY(hipStreamSynchronize(c->aux));
+  k->drain_final.store(c->h_pinned[7], std::memory_order_release);
+  // A copy whose wait for a slot gave up went straight to the image and left
+  // its slot unpublished; the checkpoint has failed (PHOS_E_TIMEOUT), so the
+  // drain stops at that slot instead of waiting for it.
+  if (reinterpret_cast<const uint32_t *>(c->h_pinned + 20)[0] & 1u)
+    k->drain_abort.store(true, std::memory_order_release);
+  k->drain_stop.store(true, std::memory_order_release);
+  k->drainer.join();
+  if (k->drain_status != PHOS_OK)
+    return fail(k->drain_status, "copy-on-write staging drain: %s", k->drain_error.c_str());
+  return PHOS_OK;
+}
+
 extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_stats *stats) {
   if (!k) return fail(PHOS_E_INVAL, "phos_ckpt_end: NULL checkpoint");
   phos_ctx *c = k->ctx;
@@ -1794,7 +1894,9 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     k->bg_started = true;
   }
   HIP_TRY(hipStreamWaitEvent(k->copy, k->bg.done, 0));
-  if (k->stage) {  // staged copy-on-write pages to their places in the host image
+  if (k->stage_block) {
+    TRY(stage_drain_finish(k, app));
+  } else if (k->stage) {  // staged copy-on-write pages to their places in the host image
     CopyArgs a = copy_args(c, s, k->image, true, nullptr);
     a.stage = k->stage;
     a.stage_page = k->d_stage_page;
@@ -1812,10 +1914,13 @@ extern "C" phos_status phos_ckpt_end(phos_ckpt *k, hipStream_t app, phos_ckpt_st
     stats->cow_pages = c->h_pinned[2];
     stats->recopy_pages = c->h_pinned[3];
     stats->precopy_pages = c->h_pinned[5];
-    stats->staged_pages = k->stage ? std::min<uint64_t>(c->h_pinned[6], k->stage_cap) : 0;
+    stats->staged_pages = k->stage_block ? k->drained_pages
+                          : k->stage   ? std::min<uint64_t>(c->h_pinned[6], k->stage_cap)
+                                       : 0;
     stats->bg_read_pages = k->pair == 1 ? c->h_pinned[4] : k->pair == 2 ? 0 : c->h_pinned[1];
     stats->bg_ms = k->bg.ms();
     stats->image_bytes = c->image_bytes;
+    stats->stage_batches = k->stage_block ? k->drain_copies : 0;
   }
   bool timeout = false, misspec = false;
   TRY(read_err(c, k->copy, &timeout, k->protocol == PHOS_COW ? &misspec : nullptr));
@@ -1982,6 +2087,179 @@ static phos_status dma_engines_ready(phos_ctx *c) {
   return PHOS_OK;
 }
 
+// Section 4.2, blocking copy-on-write staging: the host drains the ring of
+// staged pages into their places in the host image while the checkpoint runs.
+// It takes slots in order as the kernels publish them (fill) and moves
+// each batch of consecutive slots with one copy-engine copy into a pinned
+// bounce buffer; a second copy, which starts when the first has completed,
+// publishes the batch's slots as free (free_seq in device memory, where the
+// waiting kernels poll).  Host threads then move the bounce's pages to their
+// places in the image (staged pages are rarely consecutive in the image, and
+// one engine copy per page costs far more than the page).  No compute queue
+// or kernel takes part, so the drain cannot queue behind the kernels that
+// wait for it.
+namespace {
+struct DrainShared {
+  phos_ckpt *k;
+  uint32_t batch_slots = 0;
+  hsa_signal_t data[kDrainBounces]{}, freed[kDrainBounces]{};
+  std::vector<uint32_t> pages[kDrainBounces];     // per bounce: pool page of each slot (kNone: hole)
+  std::atomic<uint64_t> issued{0};                // batches handed to the copy engines
+  std::atomic<uint64_t> scattered[kDrainBounces];  // per bounce: 1 + the last batch moved out of it
+  std::atomic<bool> finished{false}, failed{false};
+  std::string error;
+  std::atomic<uint64_t> drained_pages{0};
+  void fail_with(const std::string &why) {
+    bool expect = false;
+    if (failed.compare_exchange_strong(expect, true)) error = why;
+  }
+};
+
+// Scatter worker w of nw: batches u = w, w + nw, ... (bounce u % kDrainBounces).
+void drain_scatter_main(DrainShared *d, uint32_t w, uint32_t nw) {
+  phos_ctx *c = d->k->ctx;
+  const uint64_t pb = c->page_bytes;
+  for (uint64_t u = w;; u += nw) {
+    // wait until batch u is issued, or no more will be
+    while (d->issued.load(std::memory_order_acquire) <= u) {
+      if (d->finished.load(std::memory_order_acquire) &&
+          d->issued.load(std::memory_order_acquire) <= u)
+        return;
+      if (d->failed.load(std::memory_order_relaxed)) return;
+      std::this_thread::yield();
+    }
+    const uint32_t b = (uint32_t)(u % kDrainBounces);
+    std::string why;
+    if (!wait_copy(d->data[b], &why)) {
+      d->fail_with(why);
+      return;
+    }
+    const uint8_t *src = d->k->h_bounce + (uint64_t)b * d->batch_slots * pb;
+    uint64_t n = 0;
+    for (size_t i = 0; i < d->pages[b].size(); ++i) {
+      const uint32_t p = d->pages[b][i];
+      const uint32_t ip = p < c->n_pages ? c->h_img_page[p] : kNone;
+      if (ip == kNone) continue;
+      memcpy(d->k->image + (uint64_t)ip * pb, src + i * pb, pb);
+      ++n;
+    }
+    d->drained_pages.fetch_add(n, std::memory_order_relaxed);
+    d->scattered[b].store(u + 1, std::memory_order_release);
+  }
+}
+}  // namespace
+
+static void stage_drain_main(phos_ckpt *k) {
+  phos_ctx *c = k->ctx;
+  const uint32_t cap = k->stage_cap;
+  const uint64_t *fill = k->h_fill;
+  const uint64_t pb = c->page_bytes;
+  DrainShared d;
+  d.k = k;
+  d.batch_slots = k->drain_batch_slots;
+  for (uint32_t b = 0; b < kDrainBounces; ++b) {
+    d.scattered[b].store(0);
+    d.pages[b].reserve(d.batch_slots);
+    if (hsa_signal_create(0, 0, nullptr, &d.data[b]) != HSA_STATUS_SUCCESS ||
+        hsa_signal_create(0, 0, nullptr, &d.freed[b]) != HSA_STATUS_SUCCESS)
+      d.fail_with("hsa_signal_create failed");
+  }
+  std::vector<std::thread> workers;
+  const uint32_t nw = k->drain_threads;
+  if (!d.failed.load())
+    for (uint32_t w = 0; w < nw; ++w) workers.emplace_back(drain_scatter_main, &d, w, nw);
+  uint64_t next = 0, u = 0;  // the next slot to drain, the next batch
+  bool stopping = false;
+  std::chrono::steady_clock::time_point t_stop{};
+  // The ring is drained once it is about half full (the slot half a ring
+  // ahead of the oldest one is published), and everything at the end: while
+  // the area holds every page the launches copy, the link stays free for the
+  // background copy, whose claimed pages the launches may be waiting for.
+  const uint64_t high = std::max<uint64_t>(1, (uint64_t)cap * k->drain_high_pct / 100);
+  while (!d.failed.load(std::memory_order_relaxed)) {
+    const uint32_t pos0 = (uint32_t)(next % cap);
+    const uint32_t lim = std::min<uint32_t>(d.batch_slots, cap - pos0);
+    uint32_t n = 0;
+    const bool stop = k->drain_stop.load(std::memory_order_acquire);
+    if (stop || (uint32_t)(__atomic_load_n(&fill[(next + high - 1) % cap], __ATOMIC_ACQUIRE) >> 32) ==
+                    (uint32_t)(next + high))
+      while (n < lim && (uint32_t)(__atomic_load_n(&fill[pos0 + n], __ATOMIC_ACQUIRE) >> 32) ==
+                            (uint32_t)(next + n + 1))
+        ++n;
+    if (!n) {
+      if (k->drain_abort.load(std::memory_order_acquire)) break;
+      if (stop) {
+        if (next >= k->drain_final.load(std::memory_order_acquire)) break;
+        // every kernel has ended, so every slot taken is published already
+        if (!stopping) {
+          stopping = true;
+          t_stop = std::chrono::steady_clock::now();
+        } else if (std::chrono::steady_clock::now() - t_stop > std::chrono::seconds(10)) {
+          d.fail_with("a staging slot was taken but never published");
+          break;
+        }
+      }
+      __builtin_ia32_pause();
+      continue;
+    }
+    const uint32_t b = (uint32_t)(u % kDrainBounces);
+    // the bounce's previous batch has been moved out, and its free copy is done
+    const auto t0 = std::chrono::steady_clock::now();
+    while (u >= kDrainBounces && d.scattered[b].load(std::memory_order_acquire) < u - kDrainBounces + 1) {
+      if (d.failed.load(std::memory_order_relaxed)) break;
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) {
+        d.fail_with("moving a staged batch into the image took over 60 s");
+        break;
+      }
+      std::this_thread::yield();
+    }
+    std::string why;
+    if (d.failed.load() || (u >= kDrainBounces && !wait_copy(d.freed[b], &why))) {
+      if (!why.empty()) d.fail_with(why);
+      break;
+    }
+    d.pages[b].resize(n);
+    for (uint32_t i = 0; i < n; ++i) d.pages[b][i] = (uint32_t)fill[pos0 + i];
+    hsa_signal_store_relaxed(d.data[b], 1);
+    uint8_t *dst = k->h_bounce + (uint64_t)b * d.batch_slots * pb;
+    const uint8_t *src = k->stage + (uint64_t)pos0 * pb;
+    if (hsa_amd_memory_async_copy(dst, c->cpu_agent, src, c->gpu_agent, n * pb, 0, nullptr,
+                                  d.data[b]) != HSA_STATUS_SUCCESS) {
+      hsa_signal_store_relaxed(d.data[b], 0);
+      d.fail_with("hsa_amd_memory_async_copy failed");
+      break;
+    }
+    for (uint32_t i = 0; i < n; ++i) k->h_free_src[pos0 + i] = (uint32_t)(next + i + 1);
+    hsa_signal_store_relaxed(d.freed[b], 1);
+    if (hsa_amd_memory_async_copy(k->d_free_seq + pos0, c->gpu_agent, k->h_free_src + pos0,
+                                  c->cpu_agent, 4ull * n, 1, &d.data[b],
+                                  d.freed[b]) != HSA_STATUS_SUCCESS) {
+      hsa_signal_store_relaxed(d.freed[b], 0);
+      d.issued.store(u + 1, std::memory_order_release);  // the data copy still gets moved
+      d.fail_with("hsa_amd_memory_async_copy failed");
+      break;
+    }
+    ++k->drain_copies;
+    d.issued.store(++u, std::memory_order_release);
+    next += n;
+  }
+  d.finished.store(true, std::memory_order_release);
+  for (std::thread &t : workers) t.join();
+  for (uint32_t b = 0; b < kDrainBounces; ++b) {
+    std::string why;
+    if (u > b && !wait_copy(d.freed[b], &why)) d.fail_with(why);
+  }
+  for (uint32_t b = 0; b < kDrainBounces; ++b) {
+    if (d.data[b].handle) (void)hsa_signal_destroy(d.data[b]);
+    if (d.freed[b].handle) (void)hsa_signal_destroy(d.freed[b]);
+  }
+  k->drained_pages = d.drained_pages.load();
+  if (d.failed.load()) {
+    k->drain_status = PHOS_E_HIP;
+    k->drain_error = d.error;
+  }
+}
+
 static void restore_dma_main(phos_rst *r, std::vector<const uint8_t *> src, std::vector<uint8_t> pg,
                              uint64_t chunk_bytes) {
   phos_ctx *c = r->ctx;
@@ -2104,7 +2382,7 @@ static phos_status restore_open(phos_ctx *c, uint32_t flags, const void *image,
   Slot &s = c->slots[0];
   TRY(ensure_slot(c, s, false));
   HIP_TRY(launch_fill_u32(s.state, c->n_pages, kFree, c->aux));
-  HIP_TRY(launch_fill_u64(s.counters, 8, 0, c->aux));
+  HIP_TRY(launch_fill_u64(s.counters, kSlotCounters, 0, c->aux));
   HIP_TRY(hipStreamSynchronize(c->aux));
   phos_rst *r = new phos_rst;
   r->ctx = c;

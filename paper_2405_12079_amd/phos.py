@@ -21,6 +21,7 @@ ARG_SCALAR, ARG_PTR_CONST, ARG_PTR_MUT, ARG_STRUCT, ARG_RANGE = 0, 1, 2, 3, 4
 V_READS, V_WRITES, V_TRACK, V_SYNC = 1, 2, 4, 8
 COW, RECOPY = 1, 2
 CKPT_DEFER_BACKGROUND = 1
+STAGE_HOST_DIRECT, STAGE_BLOCK = 0, 1
 RST_DEFER_BACKGROUND, RST_PREFETCH_SPEC = 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_STATE", 5: "E_OVERFLOW",
@@ -53,7 +54,8 @@ class phos_ckpt_stats(ctypes.Structure):
     _fields_ = [("bg_pages", ctypes.c_uint64), ("cow_pages", ctypes.c_uint64),
                 ("recopy_pages", ctypes.c_uint64), ("image_bytes", ctypes.c_uint64),
                 ("precopy_pages", ctypes.c_uint64), ("staged_pages", ctypes.c_uint64),
-                ("bg_read_pages", ctypes.c_uint64), ("bg_ms", ctypes.c_double)]
+                ("bg_read_pages", ctypes.c_uint64), ("bg_ms", ctypes.c_double),
+                ("stage_batches", ctypes.c_uint64)]
 
 
 class phos_rst_stats(ctypes.Structure):
@@ -94,6 +96,7 @@ SIGNATURES = [
     ("phos_ckpt_precopy", [P, P]),
     ("phos_ckpt_precopy_final", [P, P, U32, U32, P]),
     ("phos_ckpt_staging", [P, P, U64]),
+    ("phos_ckpt_staging_policy", [P, P, U64, U32]),
     ("phos_ckpt_start", [P, P]),
     ("phos_ckpt_start_pair", [P, P, P]),
     ("phos_ckpt_end", [P, P, P]),
@@ -322,6 +325,10 @@ def phos_ckpt_start_pair(cow, recopy, after=None) -> None:
 
 def phos_ckpt_staging(ck, staging, nbytes) -> None:
     _call("phos_ckpt_staging", ck, _ptr(staging), nbytes)
+
+
+def phos_ckpt_staging_policy(ck, staging, nbytes, policy) -> None:
+    _call("phos_ckpt_staging_policy", ck, _ptr(staging), nbytes, policy)
 
 
 def phos_ckpt_precopy(ck, app_stream) -> None:

@@ -179,12 +179,18 @@ def test_soft_cow_chunked_validation(env, vstream):
     assert np.array_equal(env.pool_host(), host)
 
 
-@pytest.mark.parametrize("defer,budget", [(True, 0), (True, 10), (True, None), (False, 64)])
-def test_cow_staging_host_image(env, defer, budget):
+@pytest.mark.parametrize("policy,defer,budget", [
+    ("host_direct", True, 0), ("host_direct", True, 10), ("host_direct", True, None),
+    ("host_direct", False, 64),
+    ("block", True, 1), ("block", True, 7), ("block", False, 64), ("block", True, None)])
+def test_cow_staging_host_image(env, policy, defer, budget):
     """Copy-on-write into a pinned host image through a device staging area of
-    `budget` pages (None: room for every page): staged pages reach the image
-    at the end, the overflow goes straight to the host; the image is the t1
-    snapshot either way."""
+    `budget` pages (None: room for every page).  host_direct: staged pages
+    reach the image at the end, the overflow goes straight to the host.
+    block: the area is a ring the host drains during the checkpoint, every
+    copy-on-write page goes through it and waits for a free slot when it is
+    full (1 and 7 slots: the ring wraps thousands of times).  The image is the
+    t1 snapshot either way."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -199,7 +205,8 @@ def test_cow_staging_host_image(env, defer, budget):
     T.cuda.synchronize()
     ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND if defer else 0,
                               himg, None, env.copy)
-    phos.phos_ckpt_staging(ck, staging, pages * w.page_bytes)
+    phos.phos_ckpt_staging_policy(ck, staging, pages * w.page_bytes,
+                                  phos.STAGE_BLOCK if policy == "block" else phos.STAGE_HOST_DIRECT)
     out, cnt = env.violations_buffers(N)
     for j in range(T1, T2):
         L = launches[j]
@@ -213,10 +220,61 @@ def test_cow_staging_host_image(env, defer, budget):
     assert np.array_equal(himg.numpy(), res.snapshots[0]), "CoW host image != snapshot at t1"
     n_img_pages = env.image_bytes // w.page_bytes
     assert stats.bg_pages + stats.cow_pages == n_img_pages
-    assert stats.staged_pages == min(stats.cow_pages, pages)
+    if policy == "block":
+        assert stats.staged_pages == stats.cow_pages
+    else:
+        assert stats.staged_pages == min(stats.cow_pages, pages)
     if defer:
         assert stats.cow_pages == sum(len(c) for c in res.cow_sets)
     assert np.array_equal(env.pool_host(), host)
+
+
+def test_blocking_staging_wait_timeout():
+    """Section 4.2 blocking policy, failure handling forced from the host: a
+    one-slot ring under a device wait budget of one poll.  Copies that wait
+    for a slot give up and go straight to the image, every kernel exits
+    normally, the checkpoint reports PHOS_E_TIMEOUT within seconds (the drain
+    stops at the first slot left unpublished), and the device keeps working."""
+    import os
+    import time
+    from paper_2405_12079_amd import phos
+    w = synth.config1_world()
+    old = os.environ.get("PHOS_SPIN_LIMIT")
+    os.environ["PHOS_SPIN_LIMIT"] = "1"  # read when the context is created
+    try:
+        env = Env(w)
+    finally:
+        if old is None:
+            del os.environ["PHOS_SPIN_LIMIT"]
+        else:
+            os.environ["PHOS_SPIN_LIMIT"] = old
+    T = env.T
+    try:
+        launches = synth.config1_launches(w)[:6]
+        st = Stream(env, launches)
+        himg = T.zeros(env.image_bytes, dtype=T.uint8, pin_memory=True)
+        staging = T.empty(w.page_bytes, dtype=T.uint8, device="cuda")
+        T.cuda.synchronize()
+        t0 = time.perf_counter()
+        ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, himg, None, env.copy)
+        phos.phos_ckpt_staging_policy(ck, staging, w.page_bytes, phos.STAGE_BLOCK)
+        out, cnt = env.violations_buffers(N)
+        for j, L in enumerate(launches):
+            s = env.spec(L)
+            r = st.records(j)
+            _validate(env, s, r, out, cnt)
+            phos.phos_ckpt_cow(ck, s, env.app)
+            env.mutate(L, r.data_ptr(), N)
+            phos.phos_spec_release(env.ctx, s)
+        with pytest.raises(phos.PhosError) as e:
+            phos.phos_ckpt_end(ck, env.app)
+        assert e.value.status == phos.E_TIMEOUT
+        assert time.perf_counter() - t0 < 30
+        T.cuda.synchronize()
+        x = T.arange(1 << 20, device="cuda", dtype=T.int64)
+        assert int(x.sum().item()) == (1 << 20) * ((1 << 20) - 1) // 2
+    finally:
+        env.close()
 
 
 def test_staging_rejects_bad_use(env):
@@ -232,6 +290,9 @@ def test_staging_rejects_bad_use(env):
     ck = phos.phos_ckpt_begin(env.ctx, phos.COW, phos.CKPT_DEFER_BACKGROUND, himg, None, env.copy)
     with pytest.raises(phos.PhosError) as e:  # staging in host memory
         phos.phos_ckpt_staging(ck, himg, 1 << 20)
+    assert e.value.status == phos.E_INVAL
+    with pytest.raises(phos.PhosError) as e:  # no such policy
+        phos.phos_ckpt_staging_policy(ck, staging, 1 << 20, 7)
     assert e.value.status == phos.E_INVAL
     phos.phos_ckpt_end(ck, env.app)
     pageable = T.empty(env.image_bytes, dtype=T.uint8)

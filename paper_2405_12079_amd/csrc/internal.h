@@ -25,6 +25,7 @@ constexpr uint32_t kVStep = 128;                 // records per wave step
 constexpr uint32_t kVUnroll = 4;                 // steps in flight
 constexpr uint32_t kVQuantum = kVWaves * kVStep * kVUnroll;  // tile_recs multiple (2048)
 constexpr uint32_t kWcap = 256;                  // per-wave violation list in LDS
+constexpr uint32_t kVPend = 64;                  // per-wave failing writes kept for the tile's end
 constexpr uint32_t kTrackWords = 8192;           // LDS dirty-bitmap words (32 KiB)
 constexpr uint32_t kSeg = 1024;                  // tiles per scan segment
 constexpr uint32_t kFuseTiles = 4096;            // calls up to this many tiles use one finish kernel

@@ -149,6 +149,7 @@ __device__ __forceinline__ uint32_t classify_lds(const DevSpec &S, uint32_t niv,
 struct VShared {
   DevSpec spec;
   uint32_t list[kVWaves][kWcap];
+  uint32_t vpend[kVWaves][kVPend];  // pool pages of failing writes, marked at the tile's end
   uint32_t wcnt[kVWaves];
   uint32_t win_fw;   // first global dirty-map word of the LDS window
   uint32_t win_nw;   // window words in use, or kNone (write pages straight to the map)
@@ -157,32 +158,76 @@ struct VShared {
   unsigned long long off;
 };
 
-// Tracking for one record (Section 4.3): a validated write marks its page in
-// the LDS window (or straight in the dirty map); a failing write inside a
-// buffer marks the victim map and is appended to the victim list.
-template <bool TRACK>
-__device__ __forceinline__ void track_record(const VArgs &A, const VShared &S, uint32_t *s_track,
-                                             uint64_t a, uint32_t reason) {
-  if (!TRACK) return;
-  const uint64_t off = a - A.pool_base;
-  if (off >= A.pool_bytes) return;
-  const uint32_t page = (uint32_t)(off >> A.page_shift);
-  if (reason == 0) {
-    if (S.win_nw != kNone) {
-      atomicOr(&s_track[(page >> 5) - S.win_fw], 1u << (page & 31));  // result unused: no return
-    } else {
-      A.dirty[page] = 1;
+// The block's LDS dirty window in the form the scan uses: a validated write
+// at a marks bit ((a - lo) >> page_shift) & 31 of word (a - lo) >> word_shift
+// when a - lo < bytes (the window lies inside the pool).  direct: no window
+// (the write intervals span too much of the pool): marks go straight to the
+// dirty map.
+struct TrackWin {
+  uint64_t lo, bytes;
+  uint32_t word_shift;
+  bool direct;
+};
+
+// Section 4.3 tracking of one record, without branches: a validated write
+// marks its page in the LDS window; every other lane ORs 0 into a pad word of
+// its own (kTrackWords + lane), so the wave issues one LDS atomic and no
+// divergent code.  Without a window (DIRECT) the page goes straight to the
+// dirty map.
+template <bool DIRECT>
+__device__ __forceinline__ void track_write(const VArgs &A, const TrackWin &W, uint32_t *s_track,
+                                            uint64_t a, bool marks, uint32_t lane) {
+  if (DIRECT) {
+    const uint64_t off = a - A.pool_base;
+    if (marks && off < A.pool_bytes) A.dirty[off >> A.page_shift] = 1;
+    return;
+  }
+  const uint64_t d = a - W.lo;
+  const bool in = marks && d < W.bytes;
+  const uint32_t word = in ? (uint32_t)(d >> W.word_shift) : kTrackWords + lane;
+  const uint32_t bit = in ? 1u << ((uint32_t)(d >> A.page_shift) & 31u) : 0u;
+  atomicOr(&s_track[word], bit);  // result unused: no return
+}
+
+// A failing write at pool page `page` of launch number `seq`: inside a
+// buffer, the page is a victim (Section 4.3).
+__device__ __forceinline__ void track_victim(const VArgs &A, uint32_t seq, uint32_t page) {
+  if (A.page_buf[page] == kNone) return;
+  // the latest launch that writes here out of its speculation
+  atomicMax(&A.victim_seq[page], seq);
+  if (A.victim[page] == 0) {
+    // newly marked victim page (a stale read only adds a duplicate)
+    A.victim[page] = 1;
+    const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
+    if (i < A.vlist_cap) A.vlist[i] = page;
+    else A.vmeta[3] = 1;
+  }
+}
+
+// Keep the step's failing writes inside the pool (two records per lane,
+// their pool pages) in the wave's LDS list; past its end they are marked at
+// once.
+__device__ __forceinline__ void rank_victims(const VArgs &A, VShared &S, uint32_t wave,
+                                             uint64_t lt, bool f0, uint64_t a0, bool f1,
+                                             uint64_t a1, uint32_t &vcnt) {
+  const uint64_t m0 = __ballot(f0), m1 = __ballot(f1);
+  if (__builtin_expect((m0 | m1) != 0, 0)) {
+    const uint64_t o0 = a0 - A.pool_base, o1 = a1 - A.pool_base;
+    f0 = f0 && o0 < A.pool_bytes;
+    f1 = f1 && o1 < A.pool_bytes;
+    const uint64_t n0 = __ballot(f0), n1 = __ballot(f1);
+    const uint32_t rk = vcnt + __popcll(n0 & lt) + __popcll(n1 & lt);
+    const uint32_t p0 = (uint32_t)(o0 >> A.page_shift), p1 = (uint32_t)(o1 >> A.page_shift);
+    if (f0) {
+      if (rk < kVPend) S.vpend[wave][rk] = p0;
+      else track_victim(A, S.seq, p0);
     }
-  } else if (A.page_buf[page] != kNone) {
-    // the latest launch that writes here out of its speculation
-    atomicMax(&A.victim_seq[page], S.seq);
-    if (A.victim[page] == 0) {
-      // newly marked victim page (a stale read only adds a duplicate)
-      A.victim[page] = 1;
-      const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
-      if (i < A.vlist_cap) A.vlist[i] = page;
-      else A.vmeta[3] = 1;
+    const uint32_t rk1 = rk + (f0 ? 1u : 0u);
+    if (f1) {
+      if (rk1 < kVPend) S.vpend[wave][rk1] = p1;
+      else track_victim(A, S.seq, p1);
     }
+    vcnt += __popcll(n0) + __popcll(n1);
   }
 }
 
@@ -201,12 +246,13 @@ __device__ __forceinline__ void rank_violations(VShared &S, uint32_t wave, uint6
 }
 
 // One wave's range [wbase, wend) of records; NIV < 0: intervals from LDS.
-template <int NIV, bool TRACK>
+// TRACK: 0 none, 1 the LDS window, 2 straight to the dirty map.
+template <int NIV, int TRACK>
 __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint32_t *s_track,
-                                               uint32_t niv,
+                                               const TrackWin &TW, uint32_t niv,
                                                const GLOBAL_AS uint64_t *rec8, bool al16,
                                                uint64_t wbase, uint64_t wend, uint32_t wave,
-                                               uint32_t lane) {
+                                               uint32_t lane, uint32_t &vcnt) {
   // this specialization's bounds, from LDS into registers (uniform values;
   // kept in VGPRs: scalar registers are needed for the comparison masks)
   IvRegs R;
@@ -220,48 +266,60 @@ __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint3
   const uint64_t lt = (1ull << lane) - 1ull;
   uint32_t wcnt = 0;
   uint64_t c = wbase;
-  auto one = [&](uint64_t r, bool valid) -> bool {
+  // fw: a failing write (its victim marks are taken by rank_victims)
+  auto one = [&](uint64_t r, bool valid, bool &fw) -> bool {
     const uint64_t a = r & ~7ull;
     const uint32_t w = (uint32_t)(r & 1u);
     const uint32_t reason = NIV >= 0 ? classify_n<(NIV >= 0 ? NIV : 0)>(R, a, w)
                                      : classify_lds(S.spec, niv, a, w);
-    if (TRACK && valid && w) track_record<TRACK>(A, S, s_track, a, reason);
+    fw = false;
+    if (TRACK) {
+      track_write<TRACK == 2>(A, TW, s_track, a, valid && w && reason == 0, lane);
+      fw = valid && w && reason != 0;
+    }
     return valid && reason != 0 && ((A.flags >> w) & 1u);
   };
   // main body: whole steps only, software pipelined: the next step's four
   // 16-byte loads are in flight while this step is classified (the last
   // step reloads itself instead of branching)
+  constexpr uint32_t U = kVUnroll;
   constexpr uint64_t kS = (uint64_t)kVStep * kVUnroll;
   if (al16 && c + kS <= wend) {
     const GLOBAL_AS u32x4 *__restrict__ rec4 = (const GLOBAL_AS u32x4 *)rec8;
-    u32x4 q[kVUnroll];
+    u32x4 q[U];
 #pragma unroll
-    for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
+    for (uint32_t u = 0; u < U; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
     for (;;) {
       const bool more = c + 2 * kS <= wend;
       const uint64_t cn = more ? c + kS : c;
-      u32x4 nq[kVUnroll];
+      u32x4 nq[U];
 #pragma unroll
-      for (uint32_t u = 0; u < kVUnroll; ++u) nq[u] = rec4[((cn + u * kVStep) >> 1) + lane];
+      for (uint32_t u = 0; u < U; ++u) nq[u] = rec4[((cn + u * kVStep) >> 1) + lane];
 #pragma unroll
-      for (uint32_t u = 0; u < kVUnroll; ++u) {
-        const bool b0 = one(((uint64_t)q[u].y << 32) | q[u].x, true);
-        const bool b1 = one(((uint64_t)q[u].w << 32) | q[u].z, true);
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint64_t r0 = ((uint64_t)q[u].y << 32) | q[u].x, r1 = ((uint64_t)q[u].w << 32) | q[u].z;
+        bool f0, f1;
+        const bool b0 = one(r0, true, f0);
+        const bool b1 = one(r1, true, f1);
         rank_violations(S, wave, lt, b0, b1, (uint32_t)(c - wbase) + u * kVStep + 2 * lane, wcnt);
+        if (TRACK) rank_victims(A, S, wave, lt, f0, r0 & ~7ull, f1, r1 & ~7ull, vcnt);
       }
       c += kS;
       if (!more) break;
 #pragma unroll
-      for (uint32_t u = 0; u < kVUnroll; ++u) q[u] = nq[u];
+      for (uint32_t u = 0; u < U; ++u) q[u] = nq[u];
     }
   }
   // tail (and 8-byte-aligned arrays): 128 records per step, guarded loads
   for (; c < wend; c += kVStep) {
     const uint64_t i0 = c + 2 * lane;
     const bool v0 = i0 < wend, v1 = i0 + 1 < wend;
-    const bool b0 = one(v0 ? rec8[i0] : 0, v0);
-    const bool b1 = one(v1 ? rec8[i0 + 1] : 0, v1);
+    const uint64_t r0 = v0 ? rec8[i0] : 0, r1 = v1 ? rec8[i0 + 1] : 0;
+    bool f0, f1;
+    const bool b0 = one(r0, v0, f0);
+    const bool b1 = one(r1, v1, f1);
     rank_violations(S, wave, lt, b0, b1, (uint32_t)(i0 - wbase), wcnt);
+    if (TRACK) rank_victims(A, S, wave, lt, f0, r0 & ~7ull, f1, r1 & ~7ull, vcnt);
   }
   return wcnt;
 }
@@ -288,7 +346,7 @@ __device__ __forceinline__ void emit_violation(const VArgs &A, const VShared &S,
 template <bool BATCH, bool TRACK>
 __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec single) {
   __shared__ VShared S;
-  __shared__ uint32_t s_track[TRACK ? kTrackWords : 1];
+  __shared__ uint32_t s_track[TRACK ? kTrackWords + 64 : 1];  // the window, then 64 pad words
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t tile = blockIdx.x;
 
@@ -338,10 +396,22 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   const uint64_t wbase = (uint64_t)(tile - S.L.tile0) * A.tile_recs + (uint64_t)wave * Q;
   const uint64_t wend = wbase + Q < n ? wbase + Q : n;
   const bool al16 = (((uintptr_t)rec) & 15u) == 0;
-  uint32_t wcnt = 0;
+  uint32_t wcnt = 0, vcnt = 0;
+  // the window, read once into (wave-uniform) registers
+  TrackWin TW{0, 0, 0, true};
+  if (TRACK) {
+    const uint32_t wfw = rfl(S.win_fw), wnw = rfl(S.win_nw);
+    TW.direct = wnw == kNone;
+    TW.word_shift = A.page_shift + 5;
+    TW.lo = A.pool_base + (TW.direct || wnw == 0 ? 0ull : (uint64_t)wfw << TW.word_shift);
+    TW.bytes = TW.direct ? 0ull : (uint64_t)wnw << TW.word_shift;
+  }
 #define PHOS_SCAN(N)                                                                          \
-  wcnt = scan_range<N, TRACK>(A, S, s_track, niv, rec8, al16, wbase, wend, wave, lane)
-  switch (niv) {
+  wcnt = scan_range<N, TRACK ? 1 : 0>(A, S, s_track, TW, niv, rec8, al16, wbase, wend, wave, lane, \
+                                      vcnt)
+  if (TRACK && TW.direct)
+    wcnt = scan_range<-1, 2>(A, S, s_track, TW, niv, rec8, al16, wbase, wend, wave, lane, vcnt);
+  else switch (niv) {
     case 0: PHOS_SCAN(0); break;
     case 1: PHOS_SCAN(1); break;
     case 2: PHOS_SCAN(2); break;
@@ -358,6 +428,10 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   if (lane == 0) S.wcnt[wave] = wcnt;
   __syncthreads();
 
+  if (TRACK) {  // the failing writes this wave kept
+    const uint32_t nv = vcnt < kVPend ? vcnt : kVPend;
+    for (uint32_t j = lane; j < nv; j += 64) track_victim(A, S.seq, S.vpend[wave][j]);
+  }
   if (TRACK && S.win_nw != kNone && S.win_nw) {
     // Flush the window, one word (32 pages) per thread: a plain byte store
     // per page not yet marked (the page maps need no atomics, and byte

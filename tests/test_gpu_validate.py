@@ -258,3 +258,66 @@ def test_track_bitmaps_config1_window(env1):
     assert np.array_equal(v, oracle.pages_to_bitmap(vic, w.n_pages))
     assert dirty.sum() > 0 and vic.sum() > 0
     assert np.array_equal(bits_to_pages(d, w.n_pages), dirty)
+
+
+def _edge_records(bounds, seed):
+    """Records on and around every bound (8-byte slots from 24 bytes below to
+    24 bytes above), as reads and as writes, plus random records over the
+    same span, shuffled."""
+    rng = np.random.default_rng(seed)
+    addrs = []
+    for b in bounds:
+        for d in range(-24, 32, 8):
+            addrs.append(((b + d) & ~7) & ((1 << 64) - 1))
+    lo, hi = min(bounds) - 4096, max(bounds) + 4096
+    addrs += list(rng.integers(lo // 8, hi // 8, 60_000, dtype=np.int64).astype(np.uint64) * 8)
+    a = np.array(addrs, dtype=np.uint64)
+    rec = np.concatenate([a, a | np.uint64(1)])
+    rng.shuffle(rec)
+    return rec
+
+
+@pytest.mark.parametrize("case", ["inside", "past_end"])
+def test_validate_range_bounds(env1, case):
+    """Section 4.1 ranges with bounds off 8-byte slots.  "inside": every
+    interval inside the pool and holding a slot (the 32-bit offset test);
+    "past_end": adds ranges of 1, 7 and 8 bytes that hold no slot, one that
+    reaches past the pool's end and one beyond it (the 64-bit test).  Violations bit-exact and dirty / victim pages
+    equal to the oracle's, on records at and around every bound."""
+    from paper_2405_12079_amd import phos
+    T = env1.T
+    w, base = env1.world, env1.base
+    R, W_ = 1, 2
+    b0, b1 = int(w.alloc_off[3]), int(w.alloc_off[40])
+    # each holds at least one 8-byte slot (the 32-bit test needs that)
+    ranges = [(base + b0 + 1003, 1008, R | W_), (base + b0 + 5 * 4096 + 5, 61, W_),
+              (base + b1 + 3 * 4096 + 7, 9, R | W_)]
+    if case == "past_end":
+        # ranges shorter than a slot, or holding none, and two past the pool
+        ranges += [(base + b1 + 13, 1, R), (base + b1 + 4096 + 1, 7, W_),
+                   (base + b1 + 8192 + 3, 8, R | W_),
+                   (base + w.pool_bytes - 100, 300, R | W_), (base + w.pool_bytes + 4096, 64, R | W_)]
+    args = [(synth.ARG_RANGE, m, lo, n) for lo, n, m in ranges]
+    bounds = [lo for lo, _, _ in ranges] + [lo + n for lo, n, _ in ranges]
+    rec_h = _edge_records(bounds, 7 if case == "inside" else 8)
+    n = len(rec_h)
+    rec_d = T.from_numpy(rec_h.view(np.int64)).cuda()
+    phos.phos_track_reset(env1.ctx, env1.app)
+    s = phos.phos_spec_register(env1.ctx, 900, args)
+    out, cnt = env1.violations_buffers(n)
+    phos.phos_validate(env1.ctx, s, rec_d, n, FLAGS | phos.V_TRACK, out, n, cnt, env1.app)
+    env1.app.synchronize()
+    got_n, got = Env.read_violations(out, cnt, n)
+    phos.phos_spec_release(env1.ctx, s)
+    iv = oracle.spec_build(env1.table, args)
+    want = oracle.validate(iv, rec_h, env1.table, 900)
+    assert got_n == len(want) and np.array_equal(got, want)
+    assert 0 < len(want) < n
+    dirty = np.zeros(w.n_pages, np.uint8)
+    vic = np.zeros(w.n_pages, np.uint8)
+    oracle.track(iv, rec_h, env1.table, base, w.page_bytes, w.n_pages, dirty, vic)
+    assert np.array_equal(phos.phos_track_read(env1.ctx, 0, w.n_pages),
+                          oracle.pages_to_bitmap(dirty, w.n_pages))
+    assert np.array_equal(phos.phos_track_read(env1.ctx, 1, w.n_pages),
+                          oracle.pages_to_bitmap(vic, w.n_pages))
+    assert dirty.sum() > 0

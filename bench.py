@@ -60,15 +60,24 @@ def host_cpu_share():
 
 # Host threads for the oracle's parity replays and the CPU baseline.
 HOST_THREADS, HOST_CPU_DETAIL = host_cpu_share()
-KERNELS_SRC = os.path.join(ROOT, "paper_2405_12079_amd", "csrc", "kernels.hip")
+# the device code's sources: a counter summary is valid for these bytes only
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2405_12079_amd", "csrc", f)
+                  for f in ("kernels.hip", "internal.h")]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, workload, key="traffic_bytes_per_launch", cast=int):
     """HBM bytes per launch (or the summary's `key`) of `kernel` on `workload`
     from the committed rocprofv3 counter summary
     (profiles/<kernel>_<workload>_pmc.txt), or None when there is none or the
-    kernel source changed since it was taken."""
-    import hashlib
+    kernel sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
@@ -77,8 +86,7 @@ def measured_traffic(kernel, workload, key="traffic_bytes_per_launch", cast=int)
         if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
-    if fields.get("kernels_hip_sha256") != sha or key not in fields:
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256() or key not in fields:
         return None
     return cast(float(fields[key]))
 

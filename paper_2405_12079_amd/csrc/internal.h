@@ -46,7 +46,7 @@ constexpr uint32_t kCThreads = 256;
 constexpr uint32_t kBgCopyThreads = 512;            // copying waves of a background block
 constexpr uint32_t kBgThreads = kBgCopyThreads + 64; // plus one claiming wave
 constexpr uint32_t kUnitPages = 4;  // pages per copy-on-write work unit
-constexpr uint32_t kVictimUnit = 16;  // victim-list entries per copy-on-write work unit
+constexpr uint32_t kVictimUnit = 64;  // victim-list entries per copy-on-write work unit
 
 // Interval in the form the kernel tests: an access at a is inside iff
 // (a - lo) <= span (unsigned), span = hi - lo - 8.  Empty-for-8-byte

@@ -170,6 +170,8 @@ typedef struct {
  *   PHOS_COPY_NT         streaming (non-temporal) device copies [1]
  *   PHOS_COW_DEEP        copy-on-write copies keep 16 loads in flight per
  *                        thread instead of 8 [1]
+ *   PHOS_COW_VICTIM_WINDOW  launches whose victim pages one copy-on-write
+ *                        call takes [128]
  *   PHOS_VTILE_MAX       largest validation tile, records [16384 / 32768 tracked]
  *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles order in one kernel [4096]
  *   PHOS_RST_PAUSE       restore: polls (about 0.5 us each) the background
@@ -387,7 +389,13 @@ phos_status phos_ckpt_start_pair(phos_ckpt *cow, phos_ckpt *recopy, hipStream_t 
  * validation went to that same stream, the host skips a call whose write
  * pages earlier calls already asked for when no validation has run since
  * (those pages are done before the launch, in stream order); with tracking
- * validations on other streams each call scans the whole victim map. */
+ * validations on other streams each call scans the whole victim map.
+ * Victim pages by launch: in that one-stream case, for a spec validated once
+ * (with tracking) since the checkpoint opened, the victim pages are sorted by
+ * the launch that writes them first, and a call copies those of a window of
+ * launches (from the first not yet taken through at least this one,
+ * PHOS_COW_VICTIM_WINDOW of them, never past the end of the validation call
+ * that numbered them) instead of every victim page marked so far. */
 phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream);
 
 /* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every

@@ -80,6 +80,7 @@ struct VArgs {
   const uint32_t *page_buf;  // per pool page: buffer index or kNone
   uint8_t *dirty, *victim;   // page maps: one byte per pool page (padded to 32)
   uint32_t *victim_seq;      // per pool page: the latest launch with a failing write there
+  uint32_t *victim_first;    // per pool page: the earliest such launch (~0: none)
   uint32_t seq0;             // sequence number of the call's first launch (then +1 per launch)
   uint32_t *vlist;           // victim pages newly marked (appended)
   uint32_t *vmeta;           // [0] appended, [1] CoW cursor, [2] CoW exit ticket, [3] overflow
@@ -178,6 +179,11 @@ struct VictimList {
   // 1: scan the whole map and leave the list and its cursor alone (the
   // caller cannot order the list's appends before this launch)
   uint32_t scan_map;
+  // Non-null: the launch's own bucket of victim pages, bucket[*bstart ..
+  // *bend) (the pages whose earliest failing write is this launch's), in
+  // place of the appended list; the list's cursor is left alone.
+  const uint32_t *bucket = nullptr;
+  const uint32_t *bstart = nullptr, *bend = nullptr;
 };
 
 // Batched-copy work queue: segments, exclusive byte prefix, a chunk cursor.
@@ -256,6 +262,16 @@ hipError_t launch_finallist(const uint8_t *dirty, uint8_t *victim, const uint32_
                             uint32_t thr, const uint32_t *exclude, uint32_t nwords,
                             uint32_t n_pages, uint32_t *list, unsigned int *count, hipStream_t s);
 // exclude: optional word mask (32 pages a word) of pages left out of the list
+// Victim buckets of the launches numbered s0 .. s0 + n - 1 (their pages
+// appended to the victim list since *seg0), after the list's end at *cursor.
+// bse: the n buckets' bounds, interleaved (start, end).  The snapshot, taken
+// before the validation, also clears the n counts.
+hipError_t launch_vb_snap(const uint32_t *vmeta, uint32_t cap, uint32_t *seg0, uint32_t *bse,
+                          uint32_t n, hipStream_t s);
+hipError_t launch_vb_build(const uint32_t *vlist, const uint32_t *vmeta, uint32_t cap,
+                           const uint32_t *seg0, const uint32_t *victim_first, uint32_t n_pages,
+                           uint32_t s0, uint32_t n, uint32_t *bse, uint32_t *cursor,
+                           uint32_t *bucket, uint32_t bucket_cap, hipStream_t s);
 hipError_t launch_pagelist(const uint8_t *a, const uint8_t *b, uint32_t nwords, uint32_t n_pages,
                            uint32_t *list, unsigned int *count, hipStream_t s,
                            const uint32_t *exclude = nullptr);

@@ -193,8 +193,10 @@ __device__ __forceinline__ void track_write(const VArgs &A, const TrackWin &W, u
 // buffer, the page is a victim (Section 4.3).
 __device__ __forceinline__ void track_victim(const VArgs &A, uint32_t seq, uint32_t page) {
   if (A.page_buf[page] == kNone) return;
-  // the latest launch that writes here out of its speculation
+  // the latest launch that writes here out of its speculation, and the
+  // earliest (its copy-on-write copies the page)
   atomicMax(&A.victim_seq[page], seq);
+  atomicMin(&A.victim_first[page], seq);
   if (A.victim[page] == 0) {
     // newly marked victim page (a stale read only adds a duplicate)
     A.victim[page] = 1;
@@ -842,9 +844,15 @@ __global__ void __launch_bounds__(kCThreads)
   const uint32_t range_units = R.units_prefix[R.n];
   // victim pages marked since the previous call: entries [start, end)
   uint32_t start = 0, end = 0, map_units = 0;
+  const uint32_t *vlist = V.list;
   const uint32_t all_map_units = (V.map_words + kCThreads / 4 - 1) / (kCThreads / 4);
   if (V.meta && V.scan_map) {
     map_units = all_map_units;
+  } else if (V.meta && V.bucket) {
+    vlist = V.bucket;
+    start = *V.bstart;
+    end = *V.bend;
+    if (V.meta[3]) map_units = all_map_units;  // the list overflowed
   } else if (V.meta) {
     start = V.meta[1];
     end = V.meta[0] < V.cap ? V.meta[0] : V.cap;
@@ -875,7 +883,7 @@ __global__ void __launch_bounds__(kCThreads)
     }
     if (unit < range_units + list_units) {
       const uint32_t e = start + (unit - range_units) * kVictimUnit + t;
-      uint32_t cand = (t < kVictimUnit && e < end) ? V.list[e] : kNone;
+      uint32_t cand = (t < kVictimUnit && e < end) ? vlist[e] : kNone;
       if (cand >= C.n_pages) cand = kNone;
       if (!unit_needed(C, cand)) continue;
       if (wait) claim_copy<true, DEEP>(cand, C, nullptr);
@@ -900,7 +908,7 @@ __global__ void __launch_bounds__(kCThreads)
     }
   }
   // the last block out moves the list cursor past the entries handled here
-  if (V.meta && !V.scan_map) {
+  if (V.meta && !V.scan_map && !V.bucket) {
     __syncthreads();
     if (t == 0 && atomicAdd(&V.meta[2], 1u) == gridDim.x - 1) {
       V.meta[1] = end;
@@ -1261,6 +1269,125 @@ __global__ void __launch_bounds__(kBgCopyThreads) unstage_kernel(CopyArgs C) {
                  reinterpret_cast<uint4 *>(C.image + ((uint64_t)ip << C.page_shift)), pb >> 4,
                  false);
   }
+}
+
+// Section 4.2, victim pages by launch.  A validation call numbers its
+// launches s0 .. s0 + n - 1; every page it newly marks as a victim is
+// appended to the victim list once, and its earliest failing write belongs to
+// one of these launches.  The appended pages are sorted into one bucket per
+// launch (counting sort: count, exclusive scan, scatter), so that launch's
+// copy-on-write copies exactly the victim pages it is the first to write.
+// Bucket k's bounds are interleaved: bse[2k] its start, bse[2k + 1] its end
+// (during the sort: its count, then its fill pointer).
+__global__ void __launch_bounds__(256)
+    vb_snap_kernel(const uint32_t *vmeta, uint32_t cap, uint32_t *seg0, uint32_t *bse, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) bse[2 * i + 1] = 0;
+  if (i == 0) *seg0 = vmeta[0] < cap ? vmeta[0] : cap;
+}
+
+constexpr uint32_t kVbLdsBuckets = 8192;  // block histograms in LDS up to this many launches
+
+__device__ __forceinline__ uint32_t vb_bucket_of(const uint32_t *vlist, const uint32_t *victim_first,
+                                                 uint32_t e, uint32_t b, uint32_t n_pages,
+                                                 uint32_t s0, uint32_t n, uint32_t &p) {
+  p = kNone;
+  if (e >= b) return n;
+  p = vlist[e];
+  // a page first marked by an earlier call (a repeated append) has its
+  // bucket already
+  return p < n_pages ? victim_first[p] - s0 : n;
+}
+
+// COUNT: bucket sizes into the ends; otherwise place each page at its
+// bucket's fill pointer (the end, advanced from the bucket's start).  With
+// few launches each block sums its entries per bucket in LDS first and adds
+// one total per bucket it saw; otherwise each wave adds once per distinct
+// bucket among its 64 entries (neighbouring entries mostly share one).
+template <bool COUNT>
+__global__ void __launch_bounds__(256)
+    vb_pass_kernel(const uint32_t *vlist, const uint32_t *vmeta, uint32_t cap, const uint32_t *seg0,
+                   const uint32_t *victim_first, uint32_t n_pages, uint32_t s0, uint32_t n,
+                   uint32_t *bse, uint32_t *bucket, uint32_t bucket_cap) {
+  extern __shared__ uint32_t s_hist[];  // n counters when n <= kVbLdsBuckets
+  const uint32_t a = *seg0, b = vmeta[0] < cap ? vmeta[0] : cap;
+  const uint32_t t = threadIdx.x, stride = gridDim.x * blockDim.x;
+  if (n <= kVbLdsBuckets) {
+    for (uint32_t k = t; k < n; k += blockDim.x) s_hist[k] = 0;
+    __syncthreads();
+    for (uint32_t e = a + blockIdx.x * blockDim.x + t; e < b; e += stride) {
+      uint32_t p;
+      const uint32_t k = vb_bucket_of(vlist, victim_first, e, b, n_pages, s0, n, p);
+      if (k < n) atomicAdd(&s_hist[k], 1u);
+    }
+    __syncthreads();
+    for (uint32_t k = t; k < n; k += blockDim.x) {
+      const uint32_t c = s_hist[k];
+      if (!c) continue;
+      const uint32_t base = atomicAdd(&bse[2 * k + 1], c);
+      if (!COUNT) s_hist[k] = base;  // this block's slots start here
+    }
+    if (COUNT) return;
+    __syncthreads();
+    for (uint32_t e = a + blockIdx.x * blockDim.x + t; e < b; e += stride) {
+      uint32_t p;
+      const uint32_t k = vb_bucket_of(vlist, victim_first, e, b, n_pages, s0, n, p);
+      if (k < n) {
+        const uint32_t pos = atomicAdd(&s_hist[k], 1u);
+        if (pos < bucket_cap) bucket[pos] = p;
+      }
+    }
+    return;
+  }
+  const uint32_t lane = t & 63;
+  const uint64_t below = (1ull << lane) - 1;
+  // wave-uniform loop: every lane takes part in the ballots
+  for (uint32_t e0 = a + blockIdx.x * blockDim.x + (t & ~63u); e0 < b; e0 += stride) {
+    uint32_t p;
+    const uint32_t k = vb_bucket_of(vlist, victim_first, e0 + lane, b, n_pages, s0, n, p);
+    uint64_t pending = __ballot(k < n);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const uint32_t lk = __shfl(k, leader);
+      const uint64_t same = __ballot(k == lk) & pending;
+      uint32_t base = 0;
+      if ((int)lane == leader) base = atomicAdd(&bse[2 * lk + 1], (uint32_t)__popcll(same));
+      base = __shfl(base, leader);
+      if (!COUNT && ((same >> lane) & 1)) {
+        const uint32_t pos = base + (uint32_t)__popcll(same & below);
+        if (pos < bucket_cap) bucket[pos] = p;
+      }
+      pending &= ~same;
+    }
+  }
+}
+
+// One workgroup: start[k] = *cursor + (sizes of buckets before k), end[k] =
+// start[k] (the scatter's fill pointer); the cursor moves past them all.
+__global__ void __launch_bounds__(1024) vb_scan_kernel(uint32_t *bse, uint32_t n, uint32_t *cursor) {
+  __shared__ uint32_t s_part[1024];
+  const uint32_t t = threadIdx.x, per = (n + 1023) / 1024;
+  const uint32_t k0 = t * per, k1 = k0 + per < n ? k0 + per : n;
+  uint32_t sum = 0;
+  for (uint32_t k = k0; k < k1; ++k) sum += bse[2 * k + 1];
+  s_part[t] = sum;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {  // inclusive scan of the parts
+    const uint32_t v = t >= off ? s_part[t - off] : 0u;
+    __syncthreads();
+    s_part[t] += v;
+    __syncthreads();
+  }
+  const uint32_t base = *cursor;
+  uint32_t run = base + s_part[t] - sum;
+  for (uint32_t k = k0; k < k1; ++k) {
+    const uint32_t c = bse[2 * k + 1];
+    bse[2 * k] = run;
+    bse[2 * k + 1] = run;
+    run += c;
+  }
+  __syncthreads();
+  if (t == 1023) *cursor = base + s_part[1023];
 }
 
 // Section 4.3: (dirty | victim) page maps -> page list, wave64 prefix-sum compaction.
@@ -1788,6 +1915,28 @@ hipError_t launch_finallist(const uint8_t *dirty, uint8_t *victim, const uint32_
   if (!nwords) return hipSuccess;
   hipLaunchKernelGGL(finallist_kernel, dim3((nwords + 255) / 256), dim3(256), 0, s, dirty, victim,
                      victim_seq, thr, exclude, nwords, n_pages, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_vb_snap(const uint32_t *vmeta, uint32_t cap, uint32_t *seg0, uint32_t *bse,
+                          uint32_t n, hipStream_t s) {
+  const uint32_t blocks = n ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(vb_snap_kernel, dim3(blocks), dim3(256), 0, s, vmeta, cap, seg0, bse, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vb_build(const uint32_t *vlist, const uint32_t *vmeta, uint32_t cap,
+                           const uint32_t *seg0, const uint32_t *victim_first, uint32_t n_pages,
+                           uint32_t s0, uint32_t n, uint32_t *bse, uint32_t *cursor,
+                           uint32_t *bucket, uint32_t bucket_cap, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const dim3 grid(256), block(256);
+  const size_t lds = n <= kVbLdsBuckets ? 4ull * n : 0;
+  hipLaunchKernelGGL(vb_pass_kernel<true>, grid, block, lds, s, vlist, vmeta, cap, seg0,
+                     victim_first, n_pages, s0, n, bse, bucket, bucket_cap);
+  hipLaunchKernelGGL(vb_scan_kernel, dim3(1), dim3(1024), 0, s, bse, n, cursor);
+  hipLaunchKernelGGL(vb_pass_kernel<false>, grid, block, lds, s, vlist, vmeta, cap, seg0,
+                     victim_first, n_pages, s0, n, bse, bucket, bucket_cap);
   return hipGetLastError();
 }
 

@@ -61,7 +61,13 @@ struct HostSpec {
   uint32_t launch_id = 0;
   uint64_t gen = 0;               // registration number: a reused handle is a new spec
   std::vector<phos_interval> iv;  // sorted by (lo, hi)
+  // victim buckets: validated vb_n times (with tracking) since the buckets'
+  // generation vb_gen started, the last time as launch number vb_seq
+  uint64_t vb_gen = 0;
+  uint32_t vb_n = 0, vb_seq = 0;
 };
+
+constexpr uint32_t kVBuckets = 1u << 16;  // launches numbered per tracking window with buckets
 
 // Events around a background copy on the context's background stream: its
 // start (after the work it follows) and its end; timed, for the stats.
@@ -108,6 +114,23 @@ struct phos_ctx {
   // validation order since the maps were last cleared
   uint32_t *d_victim_seq = nullptr;
   uint32_t vseq = 0;
+  // Section 4.2, victim pages by launch: the earliest failing launch of each
+  // page, and per launch number a bucket of the victim pages it writes first
+  // (vbucket[vbse[2 (s - 1)] .. vbse[2 (s - 1) + 1]), start and end
+  // interleaved), built after each tracking validation on the device, with
+  // the bounds read back to h_vbse (pinned, same layout) behind vb_evt.  vb_broken: some victim marks since the
+  // window opened have no buckets (copy-on-write takes the appended list).
+  uint32_t *d_vfirst = nullptr, *d_vbse = nullptr, *d_vbucket = nullptr;
+  uint32_t *d_vbseg0 = nullptr, *d_vbcursor = nullptr;
+  uint32_t *h_vbse = nullptr;
+  hipEvent_t vb_evt = nullptr;
+  bool vb_evt_used = false, vb_broken = false;
+  uint64_t vb_gen = 1;
+  uint32_t vb_hi = 0;  // the highest launch number whose bounds have been read back
+  // per launch number: the last launch number of the validation call that
+  // built its bucket (0: no bucket)
+  std::vector<uint32_t> vb_last = std::vector<uint32_t>(kVBuckets + 1, 0);
+  uint32_t cow_victim_window = 128;  // buckets a copy-on-write call takes at once
   uint32_t vlist_cap = 0;
   // status words the kernels raise (device memory, kErr* entries): a bounded
   // wait expired; a validation found more violations than its cap; a
@@ -242,6 +265,10 @@ struct phos_ckpt {
   // (one bit per pool page; empty until the first call)
   std::vector<uint64_t> requested;
   bool host = false;  // the image is in host memory (copies cross PCIe)
+  // victim buckets of launch numbers 1 .. vb_covered (of bucket generation
+  // vb_cov_gen) have been handed to copy-on-write calls
+  uint64_t vb_cov_gen = 0;
+  uint32_t vb_covered = 0;
   // copy-on-write staging area (device memory, the caller's) for a host image
   uint8_t *stage = nullptr;
   uint32_t *d_stage_page = nullptr;
@@ -345,7 +372,8 @@ static bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
 static phos_status ctx_free(phos_ctx *c) {
   (void)hipDeviceSynchronize();
   void *ptrs[] = {c->d_page_buf, c->d_img_page, c->d_dirty, c->d_victim, c->d_err, c->d_vlist,
-                  c->d_vmeta, c->d_victim_seq, c->d_scratch,
+                  c->d_vmeta, c->d_victim_seq, c->d_vfirst, c->d_vbse,
+                  c->d_vbucket, c->d_vbseg0, c->d_vbcursor, c->d_scratch,
                   c->d_cursor, c->d_tile_count, c->d_tile_off, c->d_seg_sum, c->d_seg_prefix};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -357,6 +385,8 @@ static phos_status ctx_free(phos_ctx *c) {
   }
   if (c->h_vstage) (void)hipHostFree(c->h_vstage);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  if (c->h_vbse) (void)hipHostFree(c->h_vbse);
+  if (c->vb_evt) (void)hipEventDestroy(c->vb_evt);
   if (c->h_want) (void)hipHostFree(c->h_want);
   if (c->h_bounce) (void)hipHostFree(c->h_bounce);
   if (c->hsa_inited) (void)hsa_shut_down();
@@ -419,6 +449,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->rst_pause = env_u32("PHOS_RST_PAUSE", 64);
   c->rst_hold_ms = std::min<uint32_t>(env_u32("PHOS_RST_HOLD_MS", 200), 40000);
   c->stage_threads = env_u32("PHOS_STAGE_THREADS", 4);
+  c->cow_victim_window = std::max<uint32_t>(1, env_u32("PHOS_COW_VICTIM_WINDOW", 128));
   c->stage_high_pct = env_u32("PHOS_STAGE_HIGH_PCT", 50);
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);
@@ -443,6 +474,11 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->vlist_cap = 2 * c->n_pages + 4096;
   CK(dalloc(&c->d_vlist, c->vlist_cap));
   CK(dalloc(&c->d_vmeta, 4));
+  CK(dalloc(&c->d_vfirst, 32ull * c->nwords));
+  CK(dalloc(&c->d_vbse, 2ull * kVBuckets));
+  CK(dalloc(&c->d_vbucket, c->vlist_cap));
+  CK(dalloc(&c->d_vbseg0, 1));
+  CK(dalloc(&c->d_vbcursor, 1));
   c->scratch_cap = 1u << 20;
   CK(dalloc(&c->d_scratch, c->scratch_cap));
   CK(dalloc(&c->d_cursor, 1));
@@ -464,6 +500,11 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
       !hipck(hipMemset(c->d_dirty, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_victim, 0, c->nwords * 32ull), "hipMemset") ||
       !hipck(hipMemset(c->d_victim_seq, 0, c->nwords * 128ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_vfirst, 0xFF, c->nwords * 128ull), "hipMemset") ||
+      !hipck(hipMemset(c->d_vbcursor, 0, 4), "hipMemset") ||
+      !hipck(hipHostMalloc((void **)&c->h_vbse, 8ull * kVBuckets, hipHostMallocDefault),
+             "hipHostMalloc") ||
+      !hipck(hipEventCreateWithFlags(&c->vb_evt, hipEventDisableTiming), "hipEventCreate") ||
       !hipck(hipMemset(c->d_err, 0, 4 * kErrWords), "hipMemset") ||
       !hipck(hipMemset(c->d_vmeta, 0, 16), "hipMemset") ||
       !hipck(hipMemset(c->d_cursor, 0, 8), "hipMemset") ||
@@ -610,6 +651,7 @@ extern "C" phos_status phos_spec_register(phos_ctx *c, uint32_t launch_id, const
   c->specs[h].used = true;
   c->specs[h].launch_id = launch_id;
   c->specs[h].gen = ++c->spec_gen;
+  c->specs[h].vb_gen = 0;
   c->specs[h].iv = std::move(merged);
   *out = h;
   return PHOS_OK;
@@ -716,6 +758,7 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   a.dirty = c->d_dirty;
   a.victim = c->d_victim;
   a.victim_seq = c->d_victim_seq;
+  a.victim_first = c->d_vfirst;
   a.vlist = c->d_vlist;
   a.vmeta = c->d_vmeta;
   a.vlist_cap = c->vlist_cap;
@@ -726,6 +769,29 @@ static VArgs base_vargs(phos_ctx *c, uint32_t flags, uint32_t tile_recs) {
   a.tile_off = c->d_tile_off;
   a.seg_sum = c->d_seg_sum;
   return a;
+}
+
+// A new tracking window: no page has a failing write yet, no bucket exists.
+static phos_status vb_reset(phos_ctx *c, hipStream_t s) {
+  // the last window's bucket bounds have landed before the new window's do
+  if (c->vb_evt_used) HIP_TRY(hipEventSynchronize(c->vb_evt));
+  HIP_TRY(launch_fill_u32(c->d_vfirst, 32ull * c->nwords, ~0u, s));
+  HIP_TRY(launch_fill_u32(c->d_vbcursor, 1, 0, s));
+  ++c->vb_gen;
+  c->vb_broken = false;
+  std::fill(c->vb_last.begin(), c->vb_last.begin() + c->vb_hi + 1, 0u);
+  c->vb_hi = 0;
+  return PHOS_OK;
+}
+
+// A tracking validation numbered spec h's launch `seq`.
+static void note_vb(phos_ctx *c, HostSpec *h, uint32_t seq) {
+  if (h->vb_gen != c->vb_gen) {
+    h->vb_gen = c->vb_gen;
+    h->vb_n = 0;
+  }
+  ++h->vb_n;
+  h->vb_seq = seq;
 }
 
 static void note_victims(phos_ctx *c, hipStream_t s) {
@@ -749,8 +815,28 @@ static phos_status run_validation(phos_ctx *c, const VArgs &a, const DevSpec *si
   HIP_TRY(hipStreamIsCapturing(s, &cs));
   const bool capturing = cs != hipStreamCaptureStatusNone;
   if (!capturing && c->v_evt_used && s != c->v_stream) HIP_TRY(hipStreamWaitEvent(s, c->v_evt, 0));
-  HIP_TRY(launch_validate(a, single, (a.flags & PHOS_V_TRACK) != 0, s));
-  if (a.flags & PHOS_V_TRACK) note_victims(c, s);
+  const bool track = (a.flags & PHOS_V_TRACK) != 0;
+  // victim buckets for this call's launches (not under capture: a replay
+  // would number its launches anew)
+  if (track && (capturing || a.seq0 + a.nlaunch - 1 > kVBuckets)) c->vb_broken = true;
+  const bool buckets = track && !c->vb_broken && a.nlaunch;
+  if (buckets)
+    HIP_TRY(launch_vb_snap(c->d_vmeta, c->vlist_cap, c->d_vbseg0, c->d_vbse + 2ull * (a.seq0 - 1),
+                           a.nlaunch, s));
+  HIP_TRY(launch_validate(a, single, track, s));
+  if (track) note_victims(c, s);
+  if (buckets) {
+    const uint32_t k0 = a.seq0 - 1, n = a.nlaunch;
+    HIP_TRY(launch_vb_build(c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_vbseg0, c->d_vfirst,
+                            c->n_pages, a.seq0, n, c->d_vbse + 2ull * k0, c->d_vbcursor,
+                            c->d_vbucket, c->vlist_cap, s));
+    HIP_TRY(hipMemcpyAsync(c->h_vbse + 2ull * k0, c->d_vbse + 2ull * k0, 8ull * n,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->vb_evt, s));
+    c->vb_evt_used = true;
+    c->vb_hi = a.seq0 + n - 1;
+    for (uint32_t q = a.seq0; q <= c->vb_hi; ++q) c->vb_last[q] = c->vb_hi;
+  }
   uint32_t *overflow = c->d_err + kErrOverflow;
   if (a.ntiles <= c->finish_tiles) {
     HIP_TRY(launch_vfinish(a.tile_count, a.tile_off, a.ntiles, a.scratch, a.scratch_cap, out, cap,
@@ -822,6 +908,7 @@ extern "C" phos_status phos_twin_scale_add(phos_ctx *c, phos_spec spec, const ui
   a.victim = c->d_victim;
   a.victim_seq = c->d_victim_seq;
   a.seq = ++c->vseq;
+  if (flags & PHOS_V_TRACK) c->vb_broken = true;  // the twin's victims have no buckets
   a.vlist = c->d_vlist;
   a.vmeta = c->d_vmeta;
   a.vlist_cap = c->vlist_cap;
@@ -871,6 +958,7 @@ extern "C" phos_status phos_validate(phos_ctx *c, phos_spec spec, const uint64_t
   a.nlaunch = 1;
   a.ntiles = (uint32_t)ntiles;
   TRY(run_validation(c, a, &ds, out, cap, n_violations, stream));
+  if (flags & PHOS_V_TRACK) note_vb(c, h, a.seq0);
   if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
   return PHOS_OK;
 }
@@ -929,7 +1017,10 @@ extern "C" phos_status phos_validate_noalloc(phos_ctx *c, phos_spec spec,
   // failed part-way: clear them (with a kernel, which graph capture takes)
   HIP_TRY(launch_fill_u64(clear, kNaClearWords, 0, stream));
   HIP_TRY(launch_validate(a, &ds, (a.flags & PHOS_V_TRACK) != 0, stream));
-  if (a.flags & PHOS_V_TRACK) note_victims(c, stream);
+  if (a.flags & PHOS_V_TRACK) {
+    note_victims(c, stream);
+    c->vb_broken = true;  // no victim buckets without the context's workspace
+  }
   HIP_TRY(launch_vfinish(a.tile_count, a.tile_off, a.ntiles, a.scratch, a.scratch_cap, out, cap,
                          n_violations, a.cursor, a.seg_sum, c->d_err + kErrOverflow, stream));
   if (!capturing) {
@@ -1047,6 +1138,8 @@ extern "C" phos_status phos_validate_batch(phos_ctx *c, const phos_spec *specs,
   c->vseq += nlaunch;
   static DevSpec unused;  // kernel parameter of the single-launch path
   TRY(run_validation(c, a, &unused, out, cap, n_violations, stream));
+  if (flags & PHOS_V_TRACK)
+    for (uint32_t i = 0; i < nlaunch; ++i) note_vb(c, &c->specs[specs[i]], a.seq0 + i);
   if (flags & PHOS_V_SYNC) return sync_count(c, n_violations, cap, stream);
   return PHOS_OK;
 }
@@ -1279,6 +1372,7 @@ extern "C" phos_status phos_track_reset(phos_ctx *c, hipStream_t s) {
   HIP_TRY(launch_fill_u32(c->d_victim_seq, 32ull * c->nwords, 0, s));
   c->vseq = 0;
   HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, s));
+  TRY(vb_reset(c, s));
   c->victims_pending = false;  // the list is empty again
   c->victim_stream_set = c->victim_streams_many = false;
   return PHOS_OK;
@@ -1469,6 +1563,7 @@ extern "C" phos_status phos_ckpt_begin(phos_ctx *c, uint32_t protocol, uint32_t 
     HIP_TRY(launch_fill_u32(c->d_victim_seq, 32ull * c->nwords, 0, c->aux));
     c->vseq = 0;
     HIP_TRY(launch_fill_u32(c->d_vmeta, 4, 0, c->aux));
+    TRY(vb_reset(c, c->aux));
     c->victims_pending = false;
     c->victim_stream_set = c->victim_streams_many = false;
   }
@@ -1662,9 +1757,49 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // this launch runs (stream order): with all of this launch's write pages
   // asked for and no victim page possibly new, there is nothing to do.
   const bool exact = !capturing && !k->cow_streams_many && !victims_unsure;
+  // Victim pages by launch: a spec validated once (with tracking) in this
+  // window is launch number h->vb_seq, and its copy-on-write takes its own
+  // bucket, the victim pages it is the first to write; the others wait for
+  // the launches that write them first, or for the background copy.  Its
+  // size is known once the bucket bounds have reached the host.
+  // Calls take the buckets of a window of launch numbers at once (from the
+  // first not yet taken to at least this launch's, cow_victim_window of
+  // them), so most calls have none to take: one kernel for many launches.
+  // Consecutive buckets lie consecutively in the bucket array, so a window
+  // is one range.  A window stops at the end of the validation call that
+  // built it; a launch number without a bucket sends the call to the list.
+  bool bucketed = exact && !c->vb_broken && h->vb_gen == c->vb_gen && h->vb_n == 1 &&
+                  h->vb_seq >= 1 && h->vb_seq <= c->vb_hi;
+  uint32_t win_lo = 0, win_hi = 0;  // launch numbers of the buckets this call takes (0: none)
+  int64_t bucket_size = -1;          // their pages, -1: unknown
+  if (bucketed) {
+    if (k->vb_cov_gen != c->vb_gen) {
+      k->vb_cov_gen = c->vb_gen;
+      k->vb_covered = 0;
+    }
+    if (h->vb_seq > k->vb_covered) {
+      win_lo = k->vb_covered + 1;
+      for (uint32_t q = win_lo; q <= h->vb_seq && bucketed; ++q) bucketed = c->vb_last[q] != 0;
+      if (bucketed)
+        win_hi = std::max(h->vb_seq, std::min(c->vb_last[h->vb_seq],
+                                              win_lo + c->cow_victim_window - 1));
+    }
+  }
+  if (bucketed) {
+    if (!win_lo) {
+      bucket_size = 0;
+    } else {
+      const hipError_t q = hipEventQuery(c->vb_evt);
+      if (q == hipSuccess)
+        bucket_size = (int64_t)c->h_vbse[2ull * (win_hi - 1) + 1] - c->h_vbse[2ull * (win_lo - 1)];
+      else if (q != hipErrorNotReady)
+        return fail(PHOS_E_HIP, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+  }
   if (exact) {
     if (k->requested.empty()) k->requested.assign((c->n_pages + 63) / 64, 0);
-    if (!victims_new && ranges_all_set(k->requested, r)) return PHOS_OK;
+    if ((bucketed ? bucket_size == 0 : !victims_new) && ranges_all_set(k->requested, r))
+      return PHOS_OK;
   }
   CopyArgs a = copy_args(c, *k->slot, k->image, true, &k->slot->counters[2]);
   // once the background copy has finished every page is done, provided the
@@ -1686,11 +1821,33 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // with tracking calls on other streams the list may be appended to while
   // this launch reads it: the victim map (marks only ever added, complete
   // for every call this stream has waited for) is scanned instead
-  const VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords,
-                     victims_unsure ? 1u : 0u};
+  VictimList v{c->d_vlist, c->d_vmeta, c->vlist_cap, c->d_victim, c->nwords,
+               victims_unsure ? 1u : 0u};
+  uint32_t victim_blocks = victims_new ? c->cow_grid : 8u;
+  if (bucketed) {
+    if (win_lo) {
+      v.bucket = c->d_vbucket;
+      v.bstart = c->d_vbse + 2ull * (win_lo - 1);
+      v.bend = c->d_vbse + 2ull * (win_hi - 1) + 1;
+      victim_blocks = bucket_size < 0 ? c->cow_grid
+                      : (uint32_t)std::min<int64_t>(c->cow_grid,
+                                                    (bucket_size + kVictimUnit - 1) / kVictimUnit);
+    } else {
+      v.meta = nullptr;  // no victim work in this call
+      victim_blocks = 0;
+    }
+  }
   // (a captured call may be replayed after any validation)
-  HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, victims_new ? c->cow_grid : 8u, app));
-  if (!capturing) c->victims_pending = false;
+  HIP_TRY(launch_cow(a, r, v, true, c->cow_grid, victim_blocks, app));
+  if (bucketed && win_lo) k->vb_covered = win_hi;
+  if (!capturing && !bucketed) {
+    c->victims_pending = false;
+    // the list's pages are all taken: so are the buckets read back so far
+    if (exact && !c->vb_broken) {
+      k->vb_cov_gen = c->vb_gen;
+      k->vb_covered = std::max(k->vb_covered, c->vb_hi);
+    }
+  }
   if (exact) ranges_set(k->requested, r);
   return PHOS_OK;
 }

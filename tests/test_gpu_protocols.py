@@ -124,7 +124,8 @@ def test_soft_cow_chunked_validation(env, vstream):
     by chunk, every chunk issued up front ("other": the host cannot order the
     victim pages, so every call looks at them).  With the background copy
     deferred, copy-on-write copies exactly the union of the oracle's copy
-    sets, and the image is the snapshot at t1."""
+    sets ("same": each launch's set before that launch and nothing the
+    launches not yet validated alone write), and the image is the snapshot at t1."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -160,6 +161,7 @@ def test_soft_cow_chunked_validation(env, vstream):
             validate(g)
             done[g] = T.cuda.Event()
             done[g].record(vs)
+    so_far = np.zeros(w.n_pages, np.uint8)
     for j in range(T1, T2):
         g = j // 20
         if j % 20 == 0:
@@ -168,6 +170,20 @@ def test_soft_cow_chunked_validation(env, vstream):
             else:
                 validate(g)
         phos.phos_ckpt_cow(ck, specs[j], env.app)
+        if vstream == "same":
+            # before each launch its oracle copy set (the pages of its write
+            # intervals and the victim pages it is the first to write) has
+            # been copied, and nothing beyond the copy sets of the launches
+            # validated so far (victim pages are taken by launch, a window of
+            # launches at a time, never past the end of a validation call)
+            so_far[res.cow_sets[j - T1].astype(np.int64)] = 1
+            upto = np.zeros(w.n_pages, np.uint8)
+            for cs in res.cow_sets[:(g + 1) * 20 - T1]:
+                upto[cs.astype(np.int64)] = 1
+            env.app.synchronize()
+            got = bits_to_pages(phos.phos_ckpt_copied(ck, w.n_pages), w.n_pages)
+            assert not np.any(so_far & ~got), f"pages missing before launch {j}"
+            assert not np.any(got & ~upto), f"pages copied ahead of validation before launch {j}"
         env.mutate(launches[j], groups[g].data_ptr() + (j % 20) * N * 8, N)
     stats = phos.phos_ckpt_end(ck, env.app)
     T.cuda.synchronize()

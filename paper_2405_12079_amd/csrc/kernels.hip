@@ -12,6 +12,7 @@
 //   batch_copy        persistent copy of many requests' segments (no paper analog)
 //   twin_kernel       Section 4.1 instrumented twin of an application kernel
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <mutex>
 
 #include "internal.h"
@@ -153,6 +154,11 @@ struct VShared {
   uint32_t wcnt[kVWaves];
   uint32_t win_fw;   // first global dirty-map word of the LDS window
   uint32_t win_nw;   // window words in use, or kNone (write pages straight to the map)
+  // the window words holding write-interval pages (window-relative, repeats
+  // allowed) and each one's write-interval bits, or niw = kNone (more than 64)
+  uint32_t niw;
+  uint32_t iw[64];
+  uint32_t imask[64];
   VLaunch L;
   uint32_t seq;  // sequence number of the tile's launch
   unsigned long long off;
@@ -189,15 +195,45 @@ __device__ __forceinline__ void track_write(const VArgs &A, const TrackWin &W, u
   atomicOr(&s_track[word], bit);  // result unused: no return
 }
 
+// The bits of global dirty-map word gw (pages 32 gw .. 32 gw + 31) that
+// lie in one of the spec's write intervals: the only pages a validated write
+// can mark.
+__device__ __forceinline__ uint32_t win_imask(const VArgs &A, const DevSpec &sp, uint32_t niv,
+                                              uint32_t gw) {
+  const uint64_t pool_end = A.pool_base + A.pool_bytes;
+  const uint32_t base = gw * 32u;
+  uint32_t m = 0;
+  for (uint32_t j = 0; j < niv; ++j) {
+    const DevIv iv = sp.iv[j];
+    if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
+    const uint64_t hi = iv.lo + iv.span + 8;
+    const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
+    const uint64_t hi_c = hi < pool_end ? hi : pool_end;
+    if (hi_c <= lo_c) continue;
+    const uint32_t p0 = (uint32_t)((lo_c - A.pool_base) >> A.page_shift);
+    const uint32_t p1 = (uint32_t)((hi_c - 1 - A.pool_base) >> A.page_shift);
+    if (p1 < base || p0 > base + 31u) continue;
+    const uint32_t a = p0 > base ? p0 - base : 0u, b = p1 < base + 31u ? p1 - base : 31u;
+    m |= (b == 31u ? ~0u : (2u << b) - 1u) & ~((1u << a) - 1u);
+  }
+  return m;
+}
+
 // A failing write at pool page `page` of launch number `seq`: inside a
 // buffer, the page is a victim (Section 4.3).
 __device__ __forceinline__ void track_victim(const VArgs &A, uint32_t seq, uint32_t page) {
-  if (A.page_buf[page] == kNone) return;
+  // the page's buffer, its victim mark and launch numbers, looked up together
+  const uint32_t buf = A.page_buf[page];
+  const uint8_t marked = A.victim[page];
+  const uint32_t last = A.victim_seq[page], first = A.victim_first[page];
+  if (buf == kNone) return;
   // the latest launch that writes here out of its speculation, and the
-  // earliest (its copy-on-write copies the page)
-  atomicMax(&A.victim_seq[page], seq);
-  atomicMin(&A.victim_first[page], seq);
-  if (A.victim[page] == 0) {
+  // earliest (its copy-on-write copies the page).  Both only ever move one
+  // way, so a value read that already covers seq (even a stale one) makes
+  // the atomic unnecessary.
+  if (last < seq) atomicMax(&A.victim_seq[page], seq);
+  if (first > seq) atomicMin(&A.victim_first[page], seq);
+  if (marked == 0) {
     // newly marked victim page (a stale read only adds a duplicate)
     A.victim[page] = 1;
     const uint32_t i = atomicAdd(&A.vmeta[0], 1u);
@@ -248,13 +284,18 @@ __device__ __forceinline__ void rank_violations(VShared &S, uint32_t wave, uint6
 }
 
 // One wave's range [wbase, wend) of records; NIV < 0: intervals from LDS.
-// TRACK: 0 none, 1 the LDS window, 2 straight to the dirty map.
+// TRACK: 0 none, 1 the LDS window, 2 straight to the dirty map.  With TRACK
+// 1 and `check`, every other step the wave looks at the window words that
+// hold write-interval pages (lane i: word iw_lane); once all those pages are
+// marked, the rest of the range only looks for failing writes (the same
+// software pipeline, a second copy of the step without the marks).
 template <int NIV, int TRACK>
 __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint32_t *s_track,
                                                const TrackWin &TW, uint32_t niv,
                                                const GLOBAL_AS uint64_t *rec8, bool al16,
                                                uint64_t wbase, uint64_t wend, uint32_t wave,
-                                               uint32_t lane, uint32_t &vcnt) {
+                                               uint32_t lane, uint32_t &vcnt, uint32_t iw_lane,
+                                               bool check) {
   // this specialization's bounds, from LDS into registers (uniform values;
   // kept in VGPRs: scalar registers are needed for the comparison masks)
   IvRegs R;
@@ -268,15 +309,17 @@ __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint3
   const uint64_t lt = (1ull << lane) - 1ull;
   uint32_t wcnt = 0;
   uint64_t c = wbase;
-  // fw: a failing write (its victim marks are taken by rank_victims)
-  auto one = [&](uint64_t r, bool valid, bool &fw) -> bool {
+  // MARK: validated writes mark their pages (fw: a failing write, its victim
+  // marks taken by rank_victims)
+  auto one = [&](auto MARK, uint64_t r, bool valid, bool &fw) -> bool {
     const uint64_t a = r & ~7ull;
     const uint32_t w = (uint32_t)(r & 1u);
     const uint32_t reason = NIV >= 0 ? classify_n<(NIV >= 0 ? NIV : 0)>(R, a, w)
                                      : classify_lds(S.spec, niv, a, w);
     fw = false;
     if (TRACK) {
-      track_write<TRACK == 2>(A, TW, s_track, a, valid && w && reason == 0, lane);
+      if constexpr (decltype(MARK)::value)
+        track_write<TRACK == 2>(A, TW, s_track, a, valid && w && reason == 0, lane);
       fw = valid && w && reason != 0;
     }
     return valid && reason != 0 && ((A.flags >> w) & 1u);
@@ -286,28 +329,38 @@ __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint3
   // step reloads itself instead of branching)
   constexpr uint32_t U = kVUnroll;
   constexpr uint64_t kS = (uint64_t)kVStep * kVUnroll;
+  bool full = false;  // wave-uniform
   if (al16 && c + kS <= wend) {
     const GLOBAL_AS u32x4 *__restrict__ rec4 = (const GLOBAL_AS u32x4 *)rec8;
     u32x4 q[U];
 #pragma unroll
     for (uint32_t u = 0; u < U; ++u) q[u] = rec4[((c + u * kVStep) >> 1) + lane];
+    auto step = [&](auto MARK) {
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint64_t r0 = ((uint64_t)q[u].y << 32) | q[u].x, r1 = ((uint64_t)q[u].w << 32) | q[u].z;
+        bool f0, f1;
+        const bool b0 = one(MARK, r0, true, f0);
+        const bool b1 = one(MARK, r1, true, f1);
+        rank_violations(S, wave, lt, b0, b1, (uint32_t)(c - wbase) + u * kVStep + 2 * lane, wcnt);
+        if (TRACK) rank_victims(A, S, wave, lt, f0, r0 & ~7ull, f1, r1 & ~7ull, vcnt);
+      }
+    };
+    uint32_t it = 0;
     for (;;) {
       const bool more = c + 2 * kS <= wend;
       const uint64_t cn = more ? c + kS : c;
       u32x4 nq[U];
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) nq[u] = rec4[((cn + u * kVStep) >> 1) + lane];
-#pragma unroll
-      for (uint32_t u = 0; u < U; ++u) {
-        const uint64_t r0 = ((uint64_t)q[u].y << 32) | q[u].x, r1 = ((uint64_t)q[u].w << 32) | q[u].z;
-        bool f0, f1;
-        const bool b0 = one(r0, true, f0);
-        const bool b1 = one(r1, true, f1);
-        rank_violations(S, wave, lt, b0, b1, (uint32_t)(c - wbase) + u * kVStep + 2 * lane, wcnt);
-        if (TRACK) rank_victims(A, S, wave, lt, f0, r0 & ~7ull, f1, r1 & ~7ull, vcnt);
-      }
+      if (TRACK == 1 && full) step(std::false_type{});
+      else step(std::true_type{});
       c += kS;
       if (!more) break;
+      if (TRACK == 1 && check && !full && (++it & 1u) == 0) {
+        const uint32_t v = iw_lane != kNone ? s_track[iw_lane] : ~0u;
+        full = __ballot(v != ~0u) == 0;
+      }
 #pragma unroll
       for (uint32_t u = 0; u < U; ++u) q[u] = nq[u];
     }
@@ -318,8 +371,8 @@ __device__ __forceinline__ uint32_t scan_range(const VArgs &A, VShared &S, uint3
     const bool v0 = i0 < wend, v1 = i0 + 1 < wend;
     const uint64_t r0 = v0 ? rec8[i0] : 0, r1 = v1 ? rec8[i0 + 1] : 0;
     bool f0, f1;
-    const bool b0 = one(r0, v0, f0);
-    const bool b1 = one(r1, v1, f1);
+    const bool b0 = one(std::true_type{}, r0, v0, f0);
+    const bool b1 = one(std::true_type{}, r1, v1, f1);
     rank_violations(S, wave, lt, b0, b1, (uint32_t)(i0 - wbase), wcnt);
     if (TRACK) rank_victims(A, S, wave, lt, f0, r0 & ~7ull, f1, r1 & ~7ull, vcnt);
   }
@@ -382,10 +435,40 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
       }
       S.win_fw = fw;
       S.win_nw = (fw != kNone && lw - fw + 1 <= kTrackWords) ? lw - fw + 1 : (fw == kNone ? 0u : kNone);
+      // the window words holding write-interval pages, if at most 64
+      uint32_t niw = (S.win_nw == kNone || S.win_nw == 0) ? kNone : 0u;
+      for (uint32_t j = 0; j < niv && niw != kNone; ++j) {
+        const DevIv iv = S.spec.iv[j];
+        if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
+        const uint64_t hi = iv.lo + iv.span + 8;
+        const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
+        const uint64_t hi_c = hi < pool_end ? hi : pool_end;
+        if (hi_c <= lo_c) continue;
+        const uint32_t f = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
+        const uint32_t l = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
+        if (l - f + 1 > 64u - niw) {
+          niw = kNone;
+          break;
+        }
+        for (uint32_t w = f; w <= l; ++w) S.iw[niw++] = w - fw;
+      }
+      S.niw = niw;
     }
     __syncthreads();
-    if (S.win_nw != kNone)
+    // With the word list only its words are ever marked, read or flushed;
+    // their pages outside the write intervals start marked, so the words are
+    // all ones once every write-interval page is (the flush masks those
+    // pages off again).  Otherwise the whole window starts clear.
+    const uint32_t niw = S.niw;
+    if (niw != kNone) {
+      if (tid < niw) {
+        const uint32_t m = win_imask(A, S.spec, niv, S.win_fw + S.iw[tid]);
+        S.imask[tid] = m;
+        s_track[S.iw[tid]] = ~m;  // a repeated word stores the same value
+      }
+    } else if (S.win_nw != kNone) {
       for (uint32_t j = tid; j < S.win_nw; j += kVThreads) s_track[j] = 0;
+    }
     __syncthreads();
   }
 
@@ -408,11 +491,20 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
     TW.lo = A.pool_base + (TW.direct || wnw == 0 ? 0ull : (uint64_t)wfw << TW.word_shift);
     TW.bytes = TW.direct ? 0ull : (uint64_t)wnw << TW.word_shift;
   }
+  // the window words this lane watches for the early stop
+  uint32_t iw_lane = kNone;
+  bool check = false;
+  if (TRACK && !TW.direct) {
+    const uint32_t niw = rfl(S.niw);
+    check = niw != kNone && niw != 0;
+    if (check && lane < niw) iw_lane = S.iw[lane];
+  }
 #define PHOS_SCAN(N)                                                                          \
   wcnt = scan_range<N, TRACK ? 1 : 0>(A, S, s_track, TW, niv, rec8, al16, wbase, wend, wave, lane, \
-                                      vcnt)
+                                      vcnt, iw_lane, check)
   if (TRACK && TW.direct)
-    wcnt = scan_range<-1, 2>(A, S, s_track, TW, niv, rec8, al16, wbase, wend, wave, lane, vcnt);
+    wcnt = scan_range<-1, 2>(A, S, s_track, TW, niv, rec8, al16, wbase, wend, wave, lane, vcnt,
+                             kNone, false);
   else switch (niv) {
     case 0: PHOS_SCAN(0); break;
     case 1: PHOS_SCAN(1); break;
@@ -436,15 +528,25 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   }
   if (TRACK && S.win_nw != kNone && S.win_nw) {
     // Flush the window, one word (32 pages) per thread: a plain byte store
-    // per page not yet marked (the page maps need no atomics, and byte
-    // stores from different L2s never clobber each other).  The map only
-    // gains marks between quiesces, so a stale read can only cause a
-    // redundant store, never a missing one.
-    for (uint32_t lw = tid; lw < S.win_nw; lw += kVThreads) {
-      const uint32_t bits = s_track[lw];
+    // per marked page, without reading the map first (the page maps need no
+    // atomics, byte stores from different L2s never clobber each other, and
+    // storing a mark again changes nothing).
+    // With the word list only its words can hold marks (and their pages
+    // outside the write intervals were set at the start).
+    const uint32_t niw = S.niw;
+    const uint32_t nf = niw != kNone ? niw : S.win_nw;
+    for (uint32_t i = tid; i < nf; i += kVThreads) {
+      const uint32_t lw = niw != kNone ? S.iw[i] : i;
+      const uint32_t bits = s_track[lw] & (niw != kNone ? S.imask[i] : ~0u);
       if (!bits) continue;
       uint8_t *d = A.dirty + 32ull * (S.win_fw + lw);
-      for (uint32_t m = bits & ~bytes_to_mask(d); m; m &= m - 1) d[__ffs(m) - 1] = 1;
+      if (bits == ~0u) {
+        const uint4 ones = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+        reinterpret_cast<uint4 *>(d)[0] = ones;
+        reinterpret_cast<uint4 *>(d)[1] = ones;
+      } else {
+        for (uint32_t m = bits; m; m &= m - 1) d[__ffs(m) - 1] = 1;
+      }
     }
   }
 

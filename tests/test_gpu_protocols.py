@@ -114,8 +114,29 @@ def test_soft_cow_config1(env, defer):
     assert np.array_equal(env.pool_host(), host)
 
 
+@pytest.fixture()
+def env_w3(monkeypatch):
+    """The plain-tiny world with copy-on-write taking victim pages 3 launches
+    at a time (read when the context is created)."""
+    monkeypatch.setenv("PHOS_COW_VICTIM_WINDOW", "3")
+    e = Env(synth.config1_world())
+    monkeypatch.delenv("PHOS_COW_VICTIM_WINDOW")
+    yield e
+    e.close()
+
+
+def test_soft_cow_chunked_validation_small_window(env_w3):
+    """As below ("same"), with victim windows of 3 launches: several windows
+    per validation call, the last one cut short at the call's end."""
+    _chunked_validation(env_w3, "same", 3)
+
+
 @pytest.mark.parametrize("vstream", ["same", "other"])
 def test_soft_cow_chunked_validation(env, vstream):
+    _chunked_validation(env, vstream, 128)
+
+
+def _chunked_validation(env, vstream, window):
     """The training step's order on the plain-tiny workload: each chunk of 20
     launches is validated in one batched call ahead of its launches, on the
     application's stream ("same": a copy-on-write call whose write pages
@@ -124,8 +145,9 @@ def test_soft_cow_chunked_validation(env, vstream):
     by chunk, every chunk issued up front ("other": the host cannot order the
     victim pages, so every call looks at them).  With the background copy
     deferred, copy-on-write copies exactly the union of the oracle's copy
-    sets ("same": each launch's set before that launch and nothing the
-    launches not yet validated alone write), and the image is the snapshot at t1."""
+    sets ("same": each launch's set before that launch, and nothing beyond the
+    sets of the launches its victim window reaches), and the image is the
+    snapshot at t1."""
     phos, w, T = env.phos, env.world, env.T
     launches = synth.config1_launches(w)
     st = Stream(env, launches)
@@ -162,6 +184,7 @@ def test_soft_cow_chunked_validation(env, vstream):
             done[g] = T.cuda.Event()
             done[g].record(vs)
     so_far = np.zeros(w.n_pages, np.uint8)
+    covered = 0
     for j in range(T1, T2):
         g = j // 20
         if j % 20 == 0:
@@ -174,11 +197,16 @@ def test_soft_cow_chunked_validation(env, vstream):
             # before each launch its oracle copy set (the pages of its write
             # intervals and the victim pages it is the first to write) has
             # been copied, and nothing beyond the copy sets of the launches
-            # validated so far (victim pages are taken by launch, a window of
-            # launches at a time, never past the end of a validation call)
+            # its victim window reaches
             so_far[res.cow_sets[j - T1].astype(np.int64)] = 1
+            # launch numbers count from 1 at the checkpoint's open; a call
+            # takes the window from the first launch not yet taken, at least
+            # through its own, `window` launches, cut at its validation call's end
+            q, last = j - T1 + 1, (g + 1) * 20 - T1
+            if q > covered:
+                covered = max(q, min(last, covered + window))
             upto = np.zeros(w.n_pages, np.uint8)
-            for cs in res.cow_sets[:(g + 1) * 20 - T1]:
+            for cs in res.cow_sets[:covered]:
                 upto[cs.astype(np.int64)] = 1
             env.app.synchronize()
             got = bits_to_pages(phos.phos_ckpt_copied(ck, w.n_pages), w.n_pages)

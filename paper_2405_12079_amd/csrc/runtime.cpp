@@ -449,7 +449,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->rst_pause = env_u32("PHOS_RST_PAUSE", 64);
   c->rst_hold_ms = std::min<uint32_t>(env_u32("PHOS_RST_HOLD_MS", 200), 40000);
   c->stage_threads = env_u32("PHOS_STAGE_THREADS", 4);
-  c->cow_victim_window = std::max<uint32_t>(1, env_u32("PHOS_COW_VICTIM_WINDOW", 128));
+  c->cow_victim_window =
+      std::min<uint32_t>(kVBuckets, std::max<uint32_t>(1, env_u32("PHOS_COW_VICTIM_WINDOW", 128)));
   c->stage_high_pct = env_u32("PHOS_STAGE_HIGH_PCT", 50);
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);

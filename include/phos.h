@@ -173,7 +173,8 @@ typedef struct {
  *   PHOS_COW_VICTIM_WINDOW  launches whose victim pages one copy-on-write
  *                        call takes [128]
  *   PHOS_VTILE_MAX       largest validation tile, records [16384 / 32768 tracked]
- *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles order in one kernel [4096]
+ *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles (at most 4096) order
+ *                        their violations in one kernel [4096]
  *   PHOS_RST_PAUSE       restore: polls (about 0.5 us each) the background
  *                        holds back per batch while on-demand copies run [64];
  *                        0 lets them share the link

@@ -592,16 +592,20 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   }
 }
 
-// Small calls (at most kFuseTiles tiles): one workgroup scans the tile counts
-// and moves every tile's violations to their ordered place, then resets the
-// workspace counters.
+// Calls of at most kFuseTiles tiles, in one kernel: every workgroup scans
+// the tile counts itself (at most kFuseTiles of them, from L2) and keeps each
+// tile's destination in LDS; then each wave moves whole tiles (tile i by
+// wave i % (waves of the grid)), its lanes one violation each.  Workgroup 0
+// also writes the total and resets the workspace counters (nothing here
+// reads them).
 __global__ void __launch_bounds__(1024)
     vfinish_kernel(const uint32_t *tile_count, const unsigned long long *tile_off, uint32_t ntiles,
                    const phos_violation *scratch, uint64_t scratch_cap, phos_violation *out,
                    uint64_t cap, uint64_t *n_out, unsigned long long *cursor,
                    unsigned long long *seg_sum, uint32_t *overflow) {
   __shared__ unsigned long long s[1024];
-  const uint32_t t = threadIdx.x;
+  __shared__ unsigned long long s_dst[kFuseTiles];
+  const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
   const uint32_t per = (ntiles + 1023) / 1024;
   const uint32_t t0 = t * per < ntiles ? t * per : ntiles;
   const uint32_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
@@ -617,20 +621,32 @@ __global__ void __launch_bounds__(1024)
   }
   unsigned long long dst = s[t] - sum;
   for (uint32_t i = t0; i < t1; ++i) {
+    s_dst[i] = dst;
+    dst += tile_count[i];
+  }
+  __syncthreads();
+  const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+  for (uint32_t i = blockIdx.x * (blockDim.x / 64u) + wave; i < ntiles; i += waves) {
     const uint32_t c = tile_count[i];
-    if (c) {
-      const unsigned long long src = tile_off[i];
-      for (uint32_t j = 0; j < c; ++j)
-        if (dst + j < cap && src + j < scratch_cap) out[dst + j] = scratch[src + j];
+    if (!c) continue;
+    const unsigned long long src = tile_off[i], d0 = s_dst[i];
+    for (uint32_t j = lane; j < c; j += 64) {
+      if (d0 + j >= cap || src + j >= scratch_cap) continue;
+      const u32x4 *from = reinterpret_cast<const u32x4 *>(scratch + src + j);
+      u32x4 *to = reinterpret_cast<u32x4 *>(out + d0 + j);
+      const u32x4 a0 = from[0], a1 = from[1];
+      to[0] = a0;
+      to[1] = a1;
     }
-    dst += c;
   }
-  if (t == 1023) {
-    *n_out = s[1023];
-    *cursor = 0;
-    if (overflow && s[1023] > cap) atomicOr(overflow, 1u);  // sticky until read
+  if (blockIdx.x == 0) {
+    if (t == 1023) {
+      *n_out = s[1023];
+      *cursor = 0;
+      if (overflow && s[1023] > cap) atomicOr(overflow, 1u);  // sticky until read
+    }
+    for (uint32_t i = t; i < (ntiles + kSeg - 1) / kSeg; i += 1024) seg_sum[i] = 0;
   }
-  for (uint32_t i = t; i < (ntiles + kSeg - 1) / kSeg; i += 1024) seg_sum[i] = 0;
 }
 
 // Exclusive scan of per-segment violation counts (one block of 1024).
@@ -1948,7 +1964,11 @@ hipError_t launch_vfinish(const uint32_t *tile_count, const unsigned long long *
                           phos_violation *out, uint64_t cap, uint64_t *n_out,
                           unsigned long long *cursor, unsigned long long *seg_sum,
                           uint32_t *overflow, hipStream_t s) {
-  hipLaunchKernelGGL(vfinish_kernel, dim3(1), dim3(1024), 0, s, tile_count, tile_off, ntiles,
+  if (ntiles > kFuseTiles) return hipErrorInvalidValue;
+  // a wave per tile, up to 64 workgroups of 16 waves
+  uint32_t blocks = (ntiles + 15u) / 16u;
+  blocks = blocks < 1u ? 1u : (blocks > 64u ? 64u : blocks);
+  hipLaunchKernelGGL(vfinish_kernel, dim3(blocks), dim3(1024), 0, s, tile_count, tile_off, ntiles,
                      scratch, scratch_cap, out, cap, n_out, cursor, seg_sum, overflow);
   return hipGetLastError();
 }

@@ -440,7 +440,7 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->bg_batch = env_u32("PHOS_BG_BATCH", 64);
   c->bg_batch_pcie = env_u32("PHOS_BG_BATCH_PCIE", 4);
   c->copy_nt = env_u32("PHOS_COPY_NT", 1);  // streaming copies: keep the application's L2 lines
-  c->finish_tiles = env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles);
+  c->finish_tiles = std::min<uint32_t>(kFuseTiles, env_u32("PHOS_VFINISH_MAX_TILES", kFuseTiles));
   c->tile_max = std::max<uint32_t>(kVQuantum, env_u32("PHOS_VTILE_MAX", 8 * kVQuantum) /
                                                   kVQuantum * kVQuantum);
   c->tile_max_track = std::max<uint32_t>(

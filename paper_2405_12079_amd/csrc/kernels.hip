@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(1024)
 // 30 CUs): the block adds up the counts of its segment's tiles before its
 // own, scans its own counts in one wave, and its four waves move the tiles,
 // one violation per lane as two 16-byte loads and stores.
-constexpr uint32_t kScatTiles = 64;
+constexpr uint32_t kScatTiles = 16;  // a scatter block's tiles: four per wave
 static_assert(kSeg % kScatTiles == 0, "a scatter block's tiles lie in one segment");
 
 __global__ void __launch_bounds__(256)
@@ -705,14 +705,16 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   if (wave == 0) {
     const uint32_t tk = tile0 + lane;
-    const uint32_t c = tk < ntiles ? tile_count[tk] : 0u;
+    const uint32_t c = lane < kScatTiles && tk < ntiles ? tile_count[tk] : 0u;
     uint32_t incl = c;
     for (uint32_t d = 1; d < 64; d <<= 1) {
       const uint32_t x = __shfl_up(incl, d, 64);
       if (lane >= d) incl += x;
     }
-    s_cnt[lane] = c;
-    s_dst[lane] = seg_prefix[tile0 / kSeg] + s_red[0] + s_red[1] + s_red[2] + s_red[3] + (incl - c);
+    if (lane < kScatTiles) {
+      s_cnt[lane] = c;
+      s_dst[lane] = seg_prefix[tile0 / kSeg] + s_red[0] + s_red[1] + s_red[2] + s_red[3] + (incl - c);
+    }
   }
   __syncthreads();
   for (uint32_t k = wave; k < kScatTiles; k += 4) {

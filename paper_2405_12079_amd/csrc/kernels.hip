@@ -195,30 +195,6 @@ __device__ __forceinline__ void track_write(const VArgs &A, const TrackWin &W, u
   atomicOr(&s_track[word], bit);  // result unused: no return
 }
 
-// The bits of global dirty-map word gw (pages 32 gw .. 32 gw + 31) that
-// lie in one of the spec's write intervals: the only pages a validated write
-// can mark.
-__device__ __forceinline__ uint32_t win_imask(const VArgs &A, const DevSpec &sp, uint32_t niv,
-                                              uint32_t gw) {
-  const uint64_t pool_end = A.pool_base + A.pool_bytes;
-  const uint32_t base = gw * 32u;
-  uint32_t m = 0;
-  for (uint32_t j = 0; j < niv; ++j) {
-    const DevIv iv = sp.iv[j];
-    if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
-    const uint64_t hi = iv.lo + iv.span + 8;
-    const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
-    const uint64_t hi_c = hi < pool_end ? hi : pool_end;
-    if (hi_c <= lo_c) continue;
-    const uint32_t p0 = (uint32_t)((lo_c - A.pool_base) >> A.page_shift);
-    const uint32_t p1 = (uint32_t)((hi_c - 1 - A.pool_base) >> A.page_shift);
-    if (p1 < base || p0 > base + 31u) continue;
-    const uint32_t a = p0 > base ? p0 - base : 0u, b = p1 < base + 31u ? p1 - base : 31u;
-    m |= (b == 31u ? ~0u : (2u << b) - 1u) & ~((1u << a) - 1u);
-  }
-  return m;
-}
-
 // A failing write at pool page `page` of launch number `seq`: inside a
 // buffer, the page is a victim (Section 4.3).
 __device__ __forceinline__ void track_victim(const VArgs &A, uint32_t seq, uint32_t page) {
@@ -417,58 +393,79 @@ __global__ void __launch_bounds__(kVThreads) validate_kernel(VArgs A, DevSpec si
   __syncthreads();
 
   if (TRACK) {
-    if (tid == 0) {
-      // one LDS window of whole dirty-map words spanning every write interval
-      uint32_t fw = kNone, lw = 0;
+    // The window, built by wave 0 with a lane per interval (at most kMaxIv =
+    // 64): one LDS window of whole dirty-map words spanning every write
+    // interval, and the window words holding write-interval pages, if at
+    // most 64 (with them the scan can tell when every such page is marked).
+    static_assert(kMaxIv <= 64, "one lane per interval");
+    if (wave == 0) {
       const uint64_t pool_end = A.pool_base + A.pool_bytes;
-      for (uint32_t j = 0; j < niv; ++j) {
-        const DevIv iv = S.spec.iv[j];
-        if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
+      uint32_t f = kNone, l = 0, p0 = 1u, p1 = 0u;  // this lane's words and pages (p0 > p1: none)
+      if (lane < niv) {
+        const DevIv iv = S.spec.iv[lane];
         const uint64_t hi = iv.lo + iv.span + 8;
         const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
         const uint64_t hi_c = hi < pool_end ? hi : pool_end;
-        if (hi_c <= lo_c) continue;
-        const uint32_t f = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
-        const uint32_t l = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
-        fw = f < fw ? f : fw;
-        lw = l > lw ? l : lw;
-      }
-      S.win_fw = fw;
-      S.win_nw = (fw != kNone && lw - fw + 1 <= kTrackWords) ? lw - fw + 1 : (fw == kNone ? 0u : kNone);
-      // the window words holding write-interval pages, if at most 64
-      uint32_t niw = (S.win_nw == kNone || S.win_nw == 0) ? kNone : 0u;
-      for (uint32_t j = 0; j < niv && niw != kNone; ++j) {
-        const DevIv iv = S.spec.iv[j];
-        if (!(iv.mode & PHOS_W) || iv.lo == ~0ull) continue;
-        const uint64_t hi = iv.lo + iv.span + 8;
-        const uint64_t lo_c = iv.lo > A.pool_base ? iv.lo : A.pool_base;
-        const uint64_t hi_c = hi < pool_end ? hi : pool_end;
-        if (hi_c <= lo_c) continue;
-        const uint32_t f = (uint32_t)(((lo_c - A.pool_base) >> A.page_shift) >> 5);
-        const uint32_t l = (uint32_t)(((hi_c - 1 - A.pool_base) >> A.page_shift) >> 5);
-        if (l - f + 1 > 64u - niw) {
-          niw = kNone;
-          break;
+        if ((iv.mode & PHOS_W) && iv.lo != ~0ull && hi_c > lo_c) {
+          p0 = (uint32_t)((lo_c - A.pool_base) >> A.page_shift);
+          p1 = (uint32_t)((hi_c - 1 - A.pool_base) >> A.page_shift);
+          f = p0 >> 5;
+          l = p1 >> 5;
         }
-        for (uint32_t w = f; w <= l; ++w) S.iw[niw++] = w - fw;
       }
-      S.niw = niw;
+      uint32_t fw = f, lw = l;
+      for (uint32_t d = 32; d; d >>= 1) {
+        const uint32_t of = __shfl_xor(fw, (int)d, 64), ol = __shfl_xor(lw, (int)d, 64);
+        fw = of < fw ? of : fw;
+        lw = ol > lw ? ol : lw;
+      }
+      const uint32_t nw =
+          (fw != kNone && lw - fw + 1 <= kTrackWords) ? lw - fw + 1 : (fw == kNone ? 0u : kNone);
+      // the list: each interval's words at its exclusive prefix of word counts
+      const uint32_t c = f != kNone ? l - f + 1 : 0u;
+      uint32_t incl = c;
+      for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t x = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += x;
+      }
+      const uint32_t total = __shfl(incl, 63, 64);
+      const uint32_t niw = (nw == kNone || nw == 0 || total > 64u) ? kNone : total;
+      if (lane == 0) {
+        S.win_fw = fw;
+        S.win_nw = nw;
+        S.niw = niw;
+      }
+      // Lane i takes list entry i: the word of the interval whose words
+      // cover position i.  Pages of the listed words outside the write
+      // intervals start marked, so the words are all ones once every
+      // write-interval page is (the flush masks those pages off again); a
+      // word listed twice stores the same value twice.
+      if (niw != kNone) {
+        uint32_t gw = 0;
+        for (uint32_t j = 0; j < niv; ++j) {
+          const uint32_t qs = __shfl(incl - c, (int)j, 64), qc = __shfl(c, (int)j, 64);
+          const uint32_t qf = __shfl(f, (int)j, 64);
+          if (lane >= qs && lane < qs + qc) gw = qf + (lane - qs);
+        }
+        const uint32_t base = gw * 32u;
+        uint32_t m = 0;
+        for (uint32_t j = 0; j < niv; ++j) {
+          const uint32_t q0 = __shfl(p0, (int)j, 64), q1 = __shfl(p1, (int)j, 64);
+          if (q0 > q1 || q1 < base || q0 > base + 31u) continue;
+          const uint32_t x = q0 > base ? q0 - base : 0u, y = q1 < base + 31u ? q1 - base : 31u;
+          m |= (y == 31u ? ~0u : (2u << y) - 1u) & ~((1u << x) - 1u);
+        }
+        if (lane < niw) {
+          S.iw[lane] = gw - fw;
+          S.imask[lane] = m;
+          s_track[gw - fw] = ~m;
+        }
+      }
     }
     __syncthreads();
-    // With the word list only its words are ever marked, read or flushed;
-    // their pages outside the write intervals start marked, so the words are
-    // all ones once every write-interval page is (the flush masks those
-    // pages off again).  Otherwise the whole window starts clear.
-    const uint32_t niw = S.niw;
-    if (niw != kNone) {
-      if (tid < niw) {
-        const uint32_t m = win_imask(A, S.spec, niv, S.win_fw + S.iw[tid]);
-        S.imask[tid] = m;
-        s_track[S.iw[tid]] = ~m;  // a repeated word stores the same value
-      }
-    } else if (S.win_nw != kNone) {
+    // Without the word list the whole window starts clear.
+    if (S.niw == kNone && S.win_nw != kNone)
       for (uint32_t j = tid; j < S.win_nw; j += kVThreads) s_track[j] = 0;
-    }
     __syncthreads();
   }
 

@@ -1759,16 +1759,16 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // asked for and no victim page possibly new, there is nothing to do.
   const bool exact = !capturing && !k->cow_streams_many && !victims_unsure;
   // Victim pages by launch: a spec validated once (with tracking) in this
-  // window is launch number h->vb_seq, and its copy-on-write takes its own
-  // bucket, the victim pages it is the first to write; the others wait for
-  // the launches that write them first, or for the background copy.  Its
-  // size is known once the bucket bounds have reached the host.
-  // Calls take the buckets of a window of launch numbers at once (from the
-  // first not yet taken to at least this launch's, cow_victim_window of
-  // them), so most calls have none to take: one kernel for many launches.
-  // Consecutive buckets lie consecutively in the bucket array, so a window
-  // is one range.  A window stops at the end of the validation call that
-  // built it; a launch number without a bucket sends the call to the list.
+  // tracking window is launch number h->vb_seq; the victim pages each launch
+  // is the first to write form its bucket.  A call takes the buckets of a
+  // window of launch numbers at once, from the first not yet taken through
+  // at least this launch's (cow_victim_window of them, never past the end
+  // of the validation call that built them), so most calls have none to
+  // take; later launches' pages wait for their window or for the background
+  // copy.  Consecutive buckets lie consecutively in the bucket array, so a
+  // window is one range, whose size the host knows once the bucket bounds
+  // have reached it.  A launch number without a bucket sends the call to
+  // the appended list.
   bool bucketed = exact && !c->vb_broken && h->vb_gen == c->vb_gen && h->vb_n == 1 &&
                   h->vb_seq >= 1 && h->vb_seq <= c->vb_hi;
   uint32_t win_lo = 0, win_hi = 0;  // launch numbers of the buckets this call takes (0: none)

@@ -1727,7 +1727,8 @@ def parse_args(argv=None):
                     choices=("begin", "validation", "cow"),
                     help="config 2: when the background copies start: with the checkpoints "
                          "(begin), after the first validation pass (validation), or after launch "
-                         "0's copy-on-write, which takes the pages hit by failing writes (cow)")
+                         "0's copy-on-write, which takes the pages the first launches hit with "
+                         "failing writes (cow)")
     ap.add_argument("--pipelined-validation", dest="pipelined_validation", action="store_true",
                     help="config 2: validate the launch chunks on their own stream ahead of the "
                          "launches (use with --val-chunk)")

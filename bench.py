@@ -1735,7 +1735,7 @@ def parse_args(argv=None):
     ap.add_argument("--precopy", action="store_true",
                     help="config 2: a pre-copy round of the recopy image before each validation "
                          "chunk after the first (iterative recopy; use with --val-chunk)")
-    ap.add_argument("--final-at", dest="final_at", default="400,650,850,950,990",
+    ap.add_argument("--final-at", dest="final_at", default="300,600,800,900,970,995",
                     help="config 2: launch positions before which a pre-copy round copies the "
                          "dirty pages no remaining launch may write ('' for none)")
     ap.add_argument("--budgets", default="0,256,1024,2048,8192,16384",

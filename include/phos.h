@@ -171,7 +171,8 @@ typedef struct {
  *   PHOS_COW_DEEP        copy-on-write copies keep 16 loads in flight per
  *                        thread instead of 8 [1]
  *   PHOS_COW_VICTIM_WINDOW  launches whose victim pages one copy-on-write
- *                        call takes [128]
+ *                        call takes [128]; PHOS_COW_VICTIM_FIRST the first
+ *                        such call after the tracking window opens [16]
  *   PHOS_VTILE_MAX       largest validation tile, records [16384 / 32768 tracked]
  *   PHOS_VFINISH_MAX_TILES  calls up to this many tiles (at most 4096) order
  *                        their violations in one kernel [4096]
@@ -395,8 +396,9 @@ phos_status phos_ckpt_start_pair(phos_ckpt *cow, phos_ckpt *recopy, hipStream_t 
  * (with tracking) since the checkpoint opened, the victim pages are sorted by
  * the launch that writes them first, and a call copies those of a window of
  * launches (from the first not yet taken through at least this one,
- * PHOS_COW_VICTIM_WINDOW of them, never past the end of the validation call
- * that numbered them) instead of every victim page marked so far. */
+ * PHOS_COW_VICTIM_WINDOW of them, PHOS_COW_VICTIM_FIRST for the first call,
+ * never past the end of the validation call that numbered them) instead of
+ * every victim page marked so far. */
 phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream);
 
 /* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every

@@ -131,6 +131,7 @@ struct phos_ctx {
   // built its bucket (0: no bucket)
   std::vector<uint32_t> vb_last = std::vector<uint32_t>(kVBuckets + 1, 0);
   uint32_t cow_victim_window = 128;  // buckets a copy-on-write call takes at once
+  uint32_t cow_victim_first = 16;    // ... the first call of a tracking window (its stall)
   uint32_t vlist_cap = 0;
   // status words the kernels raise (device memory, kErr* entries): a bounded
   // wait expired; a validation found more violations than its cap; a
@@ -451,6 +452,8 @@ extern "C" phos_status phos_create(int device, uint64_t pool_base, uint64_t pool
   c->stage_threads = env_u32("PHOS_STAGE_THREADS", 4);
   c->cow_victim_window =
       std::min<uint32_t>(kVBuckets, std::max<uint32_t>(1, env_u32("PHOS_COW_VICTIM_WINDOW", 128)));
+  c->cow_victim_first = std::min<uint32_t>(
+      c->cow_victim_window, std::max<uint32_t>(1, env_u32("PHOS_COW_VICTIM_FIRST", 16)));
   c->stage_high_pct = env_u32("PHOS_STAGE_HIGH_PCT", 50);
   c->drain_chunk = (uint64_t)env_u32("PHOS_DRAIN_CHUNK_KB", 16384) << 10;
   c->drain_window = env_u32("PHOS_DRAIN_WINDOW", 2);
@@ -1762,8 +1765,9 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // tracking window is launch number h->vb_seq; the victim pages each launch
   // is the first to write form its bucket.  A call takes the buckets of a
   // window of launch numbers at once, from the first not yet taken through
-  // at least this launch's (cow_victim_window of them, never past the end
-  // of the validation call that built them), so most calls have none to
+  // at least this launch's (cow_victim_window of them, cow_victim_first for
+  // the first call, whose copy the first launch waits for; never past the
+  // end of the validation call that built them), so most calls have none to
   // take; later launches' pages wait for their window or for the background
   // copy.  Consecutive buckets lie consecutively in the bucket array, so a
   // window is one range, whose size the host knows once the bucket bounds
@@ -1782,8 +1786,10 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
       win_lo = k->vb_covered + 1;
       for (uint32_t q = win_lo; q <= h->vb_seq && bucketed; ++q) bucketed = c->vb_last[q] != 0;
       if (bucketed)
-        win_hi = std::max(h->vb_seq, std::min(c->vb_last[h->vb_seq],
-                                              win_lo + c->cow_victim_window - 1));
+        win_hi = std::max(h->vb_seq,
+                          std::min(c->vb_last[h->vb_seq],
+                                   win_lo - 1 + (win_lo == 1 ? c->cow_victim_first
+                                                             : c->cow_victim_window)));
     }
   }
   if (bucketed) {

@@ -128,15 +128,15 @@ def env_w3(monkeypatch):
 def test_soft_cow_chunked_validation_small_window(env_w3):
     """As below ("same"), with victim windows of 3 launches: several windows
     per validation call, the last one cut short at the call's end."""
-    _chunked_validation(env_w3, "same", 3)
+    _chunked_validation(env_w3, "same", 3, 3)
 
 
 @pytest.mark.parametrize("vstream", ["same", "other"])
 def test_soft_cow_chunked_validation(env, vstream):
-    _chunked_validation(env, vstream, 128)
+    _chunked_validation(env, vstream, 128, 16)
 
 
-def _chunked_validation(env, vstream, window):
+def _chunked_validation(env, vstream, window, first):
     """The training step's order on the plain-tiny workload: each chunk of 20
     launches is validated in one batched call ahead of its launches, on the
     application's stream ("same": a copy-on-write call whose write pages
@@ -201,10 +201,11 @@ def _chunked_validation(env, vstream, window):
             so_far[res.cow_sets[j - T1].astype(np.int64)] = 1
             # launch numbers count from 1 at the checkpoint's open; a call
             # takes the window from the first launch not yet taken, at least
-            # through its own, `window` launches, cut at its validation call's end
+            # through its own, `window` launches (`first` for the first call),
+            # cut at its validation call's end
             q, last = j - T1 + 1, (g + 1) * 20 - T1
             if q > covered:
-                covered = max(q, min(last, covered + window))
+                covered = max(q, min(last, covered + (first if covered == 0 else window)))
             upto = np.zeros(w.n_pages, np.uint8)
             for cs in res.cow_sets[:covered]:
                 upto[cs.astype(np.int64)] = 1

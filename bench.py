@@ -312,6 +312,7 @@ def run_training_step(args):
             synth.apply_writes_device(base, base, w.pool_bytes, w.seed, L.k, rec_list[j], n_rec, app)
 
     e_first = torch.cuda.Event(enable_timing=True)  # launch 0 may start
+    e_val = torch.cuda.Event(enable_timing=True)  # the step's first validation call has ended
 
     def app_loop(ca, cb):
         if vstream is not None:
@@ -324,6 +325,8 @@ def run_training_step(args):
                 sl = slice(j, min(j + chunk, n_launch))
                 phos.phos_validate_batch(ctx, specs[sl], rec_ptrs[sl], n_recs[sl],
                                          VFLAGS, vout, lcap, lcnt.data_ptr() + 8 * c, app)
+                if j == 0:
+                    e_val.record(app)
                 if j == 0 and args.copy_start == "validation":
                     start_copies(ca, cb)
             if j in final_at:  # pages no remaining launch may write
@@ -379,8 +382,9 @@ def run_training_step(args):
         sa, sb = step()  # ends with both checkpoints finished (synchronous)
         step_s.append(time.perf_counter() - ts0)
         stall = t_app.e0.elapsed_time(e_first) if not (args.app_graph or vstream) else float("nan")
+        val = t_app.e0.elapsed_time(e_val) if not (args.app_graph or vstream) else float("nan")
         rows.append(dict(bg_a=sa.bg_ms, bg_b=sb.bg_ms if not pair else 0.0, app=t_app.ms(),
-                         rec=t_rec.ms(), stall_t1=stall, bg_a_pages=sa.bg_pages,
+                         rec=t_rec.ms(), stall_t1=stall, val_in_step=val, bg_a_pages=sa.bg_pages,
                          cow_pages=sa.cow_pages,
                          bg_b_pages=sb.bg_pages, bg_read_pages=sa.bg_read_pages + sb.bg_read_pages,
                          recopy_pages=sb.recopy_pages,
@@ -543,6 +547,10 @@ def run_training_step(args):
         "validated_addr_per_s": round(n_addr / (alone["track"] / 1e3), 1),
         "validation_ms_alone": {k: round(v, 4) for k, v in alone.items()},
         "validation_call_ms_alone": {k: round(v, 4) for k, v in alone_call.items()},
+        # the step's own tracked validation call, from the step's start on the
+        # application stream to the call's end (median over the timed steps)
+        "validation_ms_in_step": round(float(np.nanmedian([r["val_in_step"] for r in rows])), 4)
+        if rows and not np.isnan(rows[0]["val_in_step"]) else None,
         "app_loop_ms": round(float(np.mean([r["app"] for r in rows])), 3),
         "stop_the_world_step_ms": round(stw_ms, 3),
         "stop_the_world_parts_ms": {"copy_A": round(float(stw_parts[0]), 3),

@@ -398,7 +398,9 @@ phos_status phos_ckpt_start_pair(phos_ckpt *cow, phos_ckpt *recopy, hipStream_t 
  * launches (from the first not yet taken through at least this one,
  * PHOS_COW_VICTIM_WINDOW of them, PHOS_COW_VICTIM_FIRST for the first call,
  * never past the end of the validation call that numbered them) instead of
- * every victim page marked so far. */
+ * every victim page marked so far.  A checkpoint into a host image with a
+ * staging area (host-direct, or a blocking ring of at least half the pool's
+ * pages) takes them all in the first call. */
 phos_status phos_ckpt_cow(phos_ckpt *ck, phos_spec spec, hipStream_t app_stream);
 
 /* Section 4.3: re-quiesce (copy_stream waits for app_stream) and recopy every

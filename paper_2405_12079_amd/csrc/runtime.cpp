@@ -1769,12 +1769,17 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
   // the first call, whose copy the first launch waits for; never past the
   // end of the validation call that built them), so most calls have none to
   // take; later launches' pages wait for their window or for the background
-  // copy.  Consecutive buckets lie consecutively in the bucket array, so a
+  // copy.  A host image with a device staging area takes them all in the
+  // first call: staging runs at HBM speed, while the background copy
+  // crosses PCIe far behind the launches (with the blocking policy only when
+  // the ring holds half the pool's pages; a smaller ring would fill and
+  // stall the first launch).  Consecutive buckets lie consecutively in the bucket array, so a
   // window is one range, whose size the host knows once the bucket bounds
   // have reached it.  A launch number without a bucket sends the call to
   // the appended list.
   bool bucketed = exact && !c->vb_broken && h->vb_gen == c->vb_gen && h->vb_n == 1 &&
                   h->vb_seq >= 1 && h->vb_seq <= c->vb_hi;
+  const bool all_at_once = k->stage && (!k->stage_block || 2ull * k->stage_cap >= c->n_pages);
   uint32_t win_lo = 0, win_hi = 0;  // launch numbers of the buckets this call takes (0: none)
   int64_t bucket_size = -1;          // their pages, -1: unknown
   if (bucketed) {
@@ -1788,8 +1793,9 @@ extern "C" phos_status phos_ckpt_cow(phos_ckpt *k, phos_spec spec, hipStream_t a
       if (bucketed)
         win_hi = std::max(h->vb_seq,
                           std::min(c->vb_last[h->vb_seq],
-                                   win_lo - 1 + (win_lo == 1 ? c->cow_victim_first
-                                                             : c->cow_victim_window)));
+                                   win_lo - 1 + (all_at_once   ? kVBuckets
+                                                 : win_lo == 1 ? c->cow_victim_first
+                                                               : c->cow_victim_window)));
     }
   }
   if (bucketed) {
